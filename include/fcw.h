@@ -1,0 +1,160 @@
+/*
+ * fcw.h - C ABI of the explicit / semi-explicit immersed-boundary spectral-cell
+ * wave solver for AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the semi-discrete system  M u'' + K u = F  (paper eq. semi)
+ * that the finite/spectral cell method builds on a Cartesian grid of GLL-Lagrange
+ * cells (Sec. 2.2) over a box from which a union of balls (voids) is removed.  Cells
+ * inside a void are dropped; cells that meet no void share one reference stiffness;
+ * each cut cell carries its own stiffness and mass, integrated by a space tree with
+ * the indicator alpha^FCM (Sec. 2.2, eq. weak_form_extended), eigenvalue-stabilised
+ * (Sec. 2.6) and HRZ-lumped (Sec. 2.4).  Time stepping is the central difference
+ * method (Sec. 2.3, eq. cdm) with the Newmark beta = 0 start-up (Alg. newmark).
+ *
+ * Conventions
+ *  - Every function returns an fcw_status; nothing throws or aborts across the ABI.
+ *    fcw_last_error() gives a thread-local message for the last non-OK status.
+ *  - Call order: fcw_assemble_cells -> fcw_stabilize_cut_cells -> fcw_critical_dt
+ *    (optional before stepping when dt is given) -> fcw_step_explicit / fcw_run.
+ *    A call out of order returns FCW_E_STATE and leaves the context unchanged.
+ *  - Host arrays in descriptors are copied during the call; the context owns every
+ *    device allocation it makes until fcw_destroy.  State vectors are caller-owned
+ *    device buffers, borrowed for the duration of the call.
+ *  - Work is enqueued on the context's stream (desc.stream, a hipStream_t; NULL means
+ *    the default stream).  Only calls that return host values synchronise.
+ *  - DOF layout: node-lexicographic over the full structured node grid
+ *    (n_k = ncells_k * p + 1 nodes per direction, x fastest), components stored one
+ *    after another (dof = comp * nnodes + node), right-hand sides one after another
+ *    (index = rhs * ndof + dof).  Nodes of no active cell have zero mass and stay 0.
+ *  - State precision: FCW_FP64 stores u, d as double; FCW_FP32 and FCW_BF16 store
+ *    them as float (FCW_BF16 only changes the operands of the stiffness product).
+ *  - A context is not thread-safe; distinct contexts are.
+ */
+#ifndef FCW_H
+#define FCW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcw_ctx fcw_ctx;
+typedef int32_t fcw_status;
+
+enum {
+  FCW_OK = 0,
+  FCW_E_ARG = -1,         /* invalid argument (shape, range, source in a void, ...) */
+  FCW_E_NOMEM = -2,       /* device allocation failed */
+  FCW_E_DEVICE = -3,      /* HIP runtime error; the context is poisoned */
+  FCW_E_STATE = -4,       /* call out of order */
+  FCW_E_NOCONV = -5,      /* an iterative eigen-solve did not converge */
+  FCW_E_UNSTABLE = -6,    /* dt above the critical step (detected growth) */
+  FCW_E_UNSUPPORTED = -7  /* configuration not built into this library */
+};
+
+enum { FCW_FP64 = 0, FCW_FP32 = 1, FCW_BF16 = 2 };
+
+/* Problem description (Sec. 2.1-2.2).  dim 2 or 3; ncomp 1 (scalar wave, eq.
+ * scalar_wave_equation: rho u'' - div(rho c^2 grad u) = rho f) or 3 (isotropic
+ * linear elasticity with E, nu, rho; dim must be 3).  Cells are cubes of edge
+ * (hi-lo)/ncells, equal in every direction.  Voids: nvoids balls (centre [dim],
+ * radius); a point is fictitious iff |x-c|^2 < r^2 for some void.  alpha is the
+ * indicator value in the fictitious domain.  The outer box boundary and the void
+ * surfaces carry homogeneous Neumann conditions (natural).  tree_depth: depth of the
+ * space tree in cut cells (leaf edge h / 2^depth).  precision: FCW_FP64 / FCW_FP32 /
+ * FCW_BF16 for the per-step stiffness product; all setup runs in FP64. */
+typedef struct {
+  int32_t dim, ncomp;
+  int32_t ncells[3];
+  double lo[3], hi[3];
+  int32_t p, tree_depth;
+  int32_t nvoids;
+  const double* void_center; /* host, [nvoids][dim], copied */
+  const double* void_radius; /* host, [nvoids], copied */
+  double alpha, rho, c, E, nu;
+  int32_t precision;
+  void* stream;              /* hipStream_t or NULL */
+} fcw_problem_desc;
+
+/* Point source with Ricker time function (eq. source_time, t_s = 2 sqrt(6)/(pi f0)):
+ * F(t) = f_t(t) * amp * rho * N(x) * dir_c on component c (dir ignored for scalar). */
+typedef struct {
+  double x[3], dir[3], f0, amp;
+} fcw_source;
+
+typedef struct {
+  int64_t ndof, nnodes, ncells, n_cut, n_uncut, n_out;
+  int32_t n_loc, precision;
+  int64_t footprint_bytes; /* device bytes held by the context */
+  double dt_crit;          /* 0 until fcw_critical_dt has run */
+  double min_evs_margin;   /* min over cut cells of |lambda_i/lambda_max - f_lambda| */
+} fcw_info;
+
+/* Classify cells, build the reference element and integrate every cut cell with the
+ * space tree (Sec. 2.2).  Allocates the context. */
+fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out);
+
+/* Eigenvalue-stabilise (Sec. 2.6: M^s from the eigenvectors of M^o whose eigenvalues
+ * are below f_lambda * lambda_max, scaled to max(M^f)) and lump (Sec. 2.4, HRZ) the
+ * cut-cell masses: diag = HRZ(M^o) + eps * diag(M^s); assemble the global diagonal
+ * mass and prepare the per-step operands in the context precision.  Returns
+ * FCW_E_NOCONV if a cut-cell eigen-solve does not converge. */
+fcw_status fcw_stabilize_cut_cells(fcw_ctx* ctx, double eps, double f_lambda);
+
+/* Critical step dt_crit = 2 / sqrt(lambda_max(K, M)) (Sec. 2.3) by FP64 Lanczos on
+ * M^{-1/2} K M^{-1/2}, run until the largest Ritz value changes by less than rtol
+ * between checks (or max_iter iterations).  Synchronises; writes *dt_crit. */
+fcw_status fcw_critical_dt(fcw_ctx* ctx, int32_t max_iter, double rtol, double* dt_crit);
+
+/* Advance nrhs independent right-hand sides by nsteps central-difference steps
+ * (eq. cdm in increment form: d_{k+1} = d_k + dt^2 M^{-1}(F_k - K u_k),
+ * u_{k+1} = u_k + d_{k+1}, where d_k = u_k - u_{k-1}).
+ *   u, d : device, [nrhs][ndof] in the state precision, in/out.
+ *   src  : host, [nrhs] one point source per right-hand side (may be NULL: F = 0).
+ *   t0   : time of the first step of this call; step j uses F at t0 + j*dt.
+ *   start: nonzero on the first call of a run; d then holds dt * v_0 and the first
+ *          step is the Newmark beta = 0 start-up u_1 = u_0 + dt v_0 + dt^2/2 a_0.
+ * Returns FCW_E_ARG for a source outside the box or inside a void. */
+fcw_status fcw_step_explicit(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
+                             const fcw_source* src, double t0, double dt,
+                             int32_t nsteps, int32_t start);
+
+/* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
+fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,
+                         const fcw_source* src, double t0, double dt, int32_t nsteps);
+
+/* Stiffness action r = K u (eq. semi, element by element, same kernels as the step):
+ * u, r device [nrhs][ndof] in the state precision. */
+fcw_status fcw_apply_stiffness(fcw_ctx* ctx, int32_t nrhs, const void* u, void* r);
+
+/* Problem sizes and state; synchronises. */
+fcw_status fcw_query(const fcw_ctx* ctx, fcw_info* info);
+
+/* Copy an internal array to host memory (synchronous) for inspection:
+ * which = FCW_ARR_*; *count receives the number of elements; dst may be NULL to
+ * query the count; capacity is in elements. */
+enum {
+  FCW_ARR_CELL_CLASS = 0, /* int8 [ncells]: 0 OUT, 1 UNCUT, 2 CUT (after reclassification) */
+  FCW_ARR_CUT_CELLS = 1,  /* int32 [n_cut] cell index of each kept cut cell */
+  FCW_ARR_K_REF = 2,      /* double [n_loc*n_loc] uncut stiffness, row-major */
+  FCW_ARR_K_CUT = 3,      /* double [n_cut*n_loc*n_loc] cut-cell stiffness */
+  FCW_ARR_M_CUT = 4,      /* double [n_cut*n_s*n_s] cut-cell scalar consistent mass */
+  FCW_ARR_LUMPED_CUT = 5, /* double [n_cut*n_s] stabilised lumped diagonal */
+  FCW_ARR_MASS = 6,       /* double [nnodes] assembled lumped mass */
+  FCW_ARR_EVS_MARGIN = 7  /* double [n_cut] */
+};
+fcw_status fcw_export(const fcw_ctx* ctx, int32_t which, void* dst, int64_t capacity,
+                      int64_t* count);
+
+/* Release every device allocation of the context. */
+void fcw_destroy(fcw_ctx* ctx);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* fcw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCW_H */

@@ -1,0 +1,393 @@
+// C ABI entry points (include/fcw.h): argument checks, context lifetime, call order,
+// buffer management and the step loop.  All numerical work runs in the kernels of
+// setup.hip, step.hip and lanczos.hip.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace fcw {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+fcw_status hip_fail(hipError_t e, const char* what) {
+  set_error("%s failed: %s", what, hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? FCW_E_NOMEM : FCW_E_DEVICE;
+}
+
+template <typename P>
+static fcw_status dmalloc(Ctx& c, P** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  c.footprint += (int64_t)bytes;
+  return FCW_OK;
+}
+
+template <typename P>
+static void dfree(P*& ptr) {
+  if (ptr) (void)hipFree((void*)ptr);
+  ptr = nullptr;
+}
+
+static void free_all(Ctx& c) {
+  dfree(c.d_void_c); dfree(c.d_void_r); dfree(c.d_cls); dfree(c.d_info);
+  dfree(c.d_cut_cells); dfree(c.d_cut_vptr); dfree(c.d_cut_vidx); dfree(c.d_all_void);
+  dfree(c.d_tab); dfree(c.d_kref); dfree(c.d_mfull); dfree(c.d_lref); dfree(c.d_kcut);
+  dfree(c.d_mcut); dfree(c.d_lumped); dfree(c.d_margin); dfree(c.d_evs_fail); dfree(c.d_mass);
+  dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf);
+  dfree(c.d_src);
+}
+
+static bool in_any_void(const Ctx& c, const double* x) {
+  for (int v = 0; v < c.nvoids; ++v) {
+    double d2 = 0.0;
+    for (int k = 0; k < c.dim; ++k) {
+      const double t = x[k] - c.void_c[(size_t)v * c.dim + k];
+      d2 += t * t;
+    }
+    if (d2 < c.void_r[v] * c.void_r[v]) return true;
+  }
+  return false;
+}
+
+static fcw_status check_ctx(const fcw_ctx* ctx, int need_state) {
+  if (!ctx) {
+    set_error("null context");
+    return FCW_E_ARG;
+  }
+  if (ctx->poisoned) {
+    set_error("context is unusable after a device error");
+    return FCW_E_DEVICE;
+  }
+  if (ctx->state < need_state) {
+    set_error("call out of order (context state %d, need %d)", ctx->state, need_state);
+    return FCW_E_STATE;
+  }
+  return FCW_OK;
+}
+
+}  // namespace fcw
+
+using namespace fcw;
+
+extern "C" {
+
+const char* fcw_last_error(void) { return g_err.c_str(); }
+
+fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out) {
+  g_err.clear();
+  if (!desc || !out) {
+    set_error("null argument");
+    return FCW_E_ARG;
+  }
+  *out = nullptr;
+  const fcw_problem_desc& d = *desc;
+  if (d.dim != 2 && d.dim != 3) { set_error("dim must be 2 or 3"); return FCW_E_ARG; }
+  if (!(d.ncomp == 1 || (d.ncomp == 3 && d.dim == 3))) {
+    set_error("ncomp must be 1, or 3 with dim 3");
+    return FCW_E_ARG;
+  }
+  if (d.p < 1 || d.p > kMaxP) { set_error("p must be in [1, %d]", kMaxP); return FCW_E_ARG; }
+  if (d.tree_depth < 0 || d.dim * d.tree_depth > 10) {
+    set_error("tree_depth must satisfy 0 <= dim*depth <= 10 (got %d)", d.tree_depth);
+    return FCW_E_ARG;
+  }
+  if (d.nvoids < 0 || (d.nvoids > 0 && (!d.void_center || !d.void_radius))) {
+    set_error("invalid void arrays");
+    return FCW_E_ARG;
+  }
+  if (!(d.alpha >= 0.0) || !(d.rho > 0.0)) { set_error("need alpha >= 0, rho > 0"); return FCW_E_ARG; }
+  if (d.ncomp == 1 && !(d.c > 0.0)) { set_error("need c > 0"); return FCW_E_ARG; }
+  if (d.ncomp == 3 && !(d.E > 0.0 && d.nu > -1.0 && d.nu < 0.5)) {
+    set_error("need E > 0 and -1 < nu < 0.5");
+    return FCW_E_ARG;
+  }
+  if (d.precision != FCW_FP64 && d.precision != FCW_FP32) {
+    set_error("precision %d not built", d.precision);
+    return FCW_E_UNSUPPORTED;
+  }
+  double h = 0.0;
+  for (int k = 0; k < d.dim; ++k) {
+    if (d.ncells[k] < 1 || !(d.hi[k] > d.lo[k])) { set_error("empty grid"); return FCW_E_ARG; }
+    const double hk = (d.hi[k] - d.lo[k]) / d.ncells[k];
+    if (k == 0) h = hk;
+    else if (std::fabs(hk - h) > 1e-14 * h) { set_error("cells must be cubes"); return FCW_E_ARG; }
+  }
+  fcw_ctx* c = new (std::nothrow) fcw_ctx();
+  if (!c) { set_error("host allocation failed"); return FCW_E_NOMEM; }
+  c->dim = d.dim;
+  c->ncomp = d.ncomp;
+  c->p = d.p;
+  c->depth = d.tree_depth;
+  c->precision = d.precision;
+  c->h = h;
+  c->alpha = d.alpha;
+  c->rho = d.rho;
+  c->c = d.c;
+  c->E = d.E;
+  c->nu = d.nu;
+  c->stream = (hipStream_t)d.stream;
+  c->ncell_total = 1;
+  c->nnodes = 1;
+  for (int k = 0; k < 3; ++k) {
+    c->ncells[k] = (k < d.dim) ? d.ncells[k] : 1;
+    c->npts[k] = (k < d.dim) ? d.ncells[k] * d.p + 1 : 1;
+    c->lo[k] = (k < d.dim) ? d.lo[k] : 0.0;
+    c->hi[k] = (k < d.dim) ? d.hi[k] : 0.0;
+    c->ncell_total *= c->ncells[k];
+    c->nnodes *= c->npts[k];
+  }
+  c->ndof = c->nnodes * c->ncomp;
+  c->n_s = ipow(d.p + 1, d.dim);
+  c->n_loc = c->n_s * d.ncomp;
+  c->nvoids = d.nvoids;
+  c->void_c.assign(d.void_center, d.void_center + (size_t)d.nvoids * d.dim);
+  c->void_r.assign(d.void_radius, d.void_radius + d.nvoids);
+  if (!step_supported(*c)) {
+    set_error("no step kernel built for dim=%d p=%d ncomp=%d", d.dim, d.p, d.ncomp);
+    delete c;
+    return FCW_E_UNSUPPORTED;
+  }
+
+  auto fail = [&](fcw_status st) {
+    free_all(*c);
+    delete c;
+    return st;
+  };
+  fcw_status st;
+  const size_t nl2 = (size_t)c->n_loc * c->n_loc, ns2 = (size_t)c->n_s * c->n_s;
+  if ((st = dmalloc(*c, &c->d_void_c, (size_t)d.nvoids * d.dim * 8)) ||
+      (st = dmalloc(*c, &c->d_void_r, (size_t)d.nvoids * 8)) ||
+      (st = dmalloc(*c, &c->d_cls, (size_t)c->ncell_total)) ||
+      (st = dmalloc(*c, &c->d_info, (size_t)c->ncell_total * 4)) ||
+      (st = dmalloc(*c, &c->d_tab, sizeof(RefTables))) ||
+      (st = dmalloc(*c, &c->d_kref, nl2 * 8)) || (st = dmalloc(*c, &c->d_mfull, ns2 * 8)) ||
+      (st = dmalloc(*c, &c->d_lref, (size_t)c->n_s * 8)))
+    return fail(st);
+  if (d.nvoids > 0) {
+    if (hipMemcpyAsync(c->d_void_c, d.void_center, (size_t)d.nvoids * d.dim * 8,
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_void_r, d.void_radius, (size_t)d.nvoids * 8, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess)
+      return fail(hip_fail(hipGetLastError(), "hipMemcpyAsync"));
+  }
+  if ((st = setup_reference(*c)) || (st = setup_classify(*c))) return fail(st);
+  const size_t nc = (size_t)(c->n_cut_cand > 0 ? c->n_cut_cand : 1);
+  if ((st = dmalloc(*c, &c->d_kcut, nc * nl2 * 8)) || (st = dmalloc(*c, &c->d_mcut, nc * ns2 * 8)) ||
+      (st = dmalloc(*c, &c->d_lumped, nc * c->n_s * 8)) ||
+      (st = dmalloc(*c, &c->d_margin, nc * 8)))
+    return fail(st);
+  if ((st = setup_integrate(*c))) return fail(st);
+  if ((st = setup_reclassify(*c))) return fail(st);
+  c->state = 1;
+  *out = c;
+  return FCW_OK;
+}
+
+fcw_status fcw_stabilize_cut_cells(fcw_ctx* c, double eps, double f_lambda) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  if (!(eps >= 0.0) || !(f_lambda > 0.0 && f_lambda < 1.0)) {
+    set_error("need eps >= 0 and 0 < f_lambda < 1");
+    return FCW_E_ARG;
+  }
+  const size_t sb = c->state_bytes();
+  const size_t nl = c->n_loc;
+  const size_t npk = nl * (nl + 1) / 2;
+  const size_t nc = (size_t)(c->n_cut_cand > 0 ? c->n_cut_cand : 1);
+  if (!c->d_mass) {
+    if ((st = dmalloc(*c, &c->d_mass, c->nnodes * 8)) ||
+        (st = dmalloc(*c, &c->d_invm64, c->nnodes * 8)) ||
+        (st = dmalloc(*c, &c->d_invm, c->nnodes * sb)) ||
+        (st = dmalloc(*c, &c->d_kref_s, nl * nl * sb)) ||
+        (st = dmalloc(*c, &c->d_kcut_s, nc * npk * sb)))
+      return st;
+  }
+  if ((st = setup_stabilize(*c, eps, f_lambda))) return st;
+  if ((st = setup_mass_and_pack(*c))) return st;
+  // smallest classification margin of the eigenvalue split over the kept cut cells
+  c->min_margin = 0.0;
+  if (c->n_cut_cand > 0 && eps != 0.0) {
+    std::vector<double> m(c->n_cut_cand);
+    std::vector<int32_t> av(c->n_cut_cand);
+    FCW_HIP(hipMemcpyAsync(m.data(), c->d_margin, m.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    FCW_HIP(hipMemcpyAsync(av.data(), c->d_all_void, av.size() * 4, hipMemcpyDeviceToHost,
+                           c->stream));
+    FCW_HIP(hipStreamSynchronize(c->stream));
+    double mm = 1e300;
+    for (size_t i = 0; i < m.size(); ++i)
+      if (!av[i]) mm = std::fmin(mm, m[i]);
+    c->min_margin = mm;
+  }
+  c->state = 2;
+  c->dt_crit = 0.0;
+  return FCW_OK;
+}
+
+fcw_status fcw_critical_dt(fcw_ctx* c, int32_t max_iter, double rtol, double* dt_crit) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (!dt_crit || max_iter < 2 || !(rtol > 0.0)) {
+    set_error("need dt_crit != NULL, max_iter >= 2, rtol > 0");
+    return FCW_E_ARG;
+  }
+  double lmax = 0.0;
+  if ((st = lanczos_lambda_max(*c, max_iter, rtol, &lmax))) return st;
+  c->dt_crit = 2.0 / std::sqrt(lmax);
+  *dt_crit = c->dt_crit;
+  return FCW_OK;
+}
+
+fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
+                             double t0, double dt, int32_t nsteps, int32_t start) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > 64 || !u || !d || !(dt > 0.0) || nsteps < 0) {
+    set_error("invalid arguments (nrhs in [1,64], u, d non-null, dt > 0, nsteps >= 0)");
+    return FCW_E_ARG;
+  }
+  if (nsteps == 0) return FCW_OK;
+  if (src) {
+    for (int s = 0; s < nrhs; ++s) {
+      for (int k = 0; k < c->dim; ++k)
+        if (!(src[s].x[k] >= c->lo[k] && src[s].x[k] <= c->hi[k])) {
+          set_error("source %d outside the box", s);
+          return FCW_E_ARG;
+        }
+      if (in_any_void(*c, src[s].x)) {
+        set_error("source %d lies inside a void", s);
+        return FCW_E_ARG;
+      }
+      if (!(src[s].f0 > 0.0)) {
+        set_error("source %d needs f0 > 0", s);
+        return FCW_E_ARG;
+      }
+    }
+    if ((st = prepare_sources(*c, nrhs, src))) return st;
+  }
+  const size_t bytes = (size_t)nrhs * c->ndof * c->state_bytes();
+  if (c->ubuf_bytes < bytes) {
+    dfree(c->d_ubuf);
+    c->footprint -= (int64_t)c->ubuf_bytes;
+    c->ubuf_bytes = 0;
+    if ((st = dmalloc(*c, &c->d_ubuf, bytes))) return st;
+    c->ubuf_bytes = bytes;
+  }
+  void* a = u;
+  void* b = c->d_ubuf;
+  if (nsteps % 2 == 1) {
+    FCW_HIP(hipMemcpyAsync(c->d_ubuf, u, bytes, hipMemcpyDeviceToDevice, c->stream));
+    a = c->d_ubuf;
+    b = u;
+  }
+  const SourceDev* saved = c->d_src;
+  if (!src) c->d_src = nullptr;
+  for (int j = 0; j < nsteps; ++j) {
+    st = launch_step(*c, nrhs, a, b, d, t0 + j * dt, dt, (start && j == 0) ? 1 : 0);
+    if (st) break;
+    void* t = a;
+    a = b;
+    b = t;
+  }
+  c->d_src = const_cast<SourceDev*>(saved);
+  return st;
+}
+
+fcw_status fcw_step_imex(fcw_ctx* c, int32_t, void*, void*, void*, const fcw_source*, double,
+                         double, int32_t) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  set_error("the IMEX step is not built in this library");
+  return FCW_E_UNSUPPORTED;
+}
+
+fcw_status fcw_apply_stiffness(fcw_ctx* c, int32_t nrhs, const void* u, void* r) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > 65535 || !u || !r) {
+    set_error("invalid arguments");
+    return FCW_E_ARG;
+  }
+  return launch_apply(*c, nrhs, u, r);
+}
+
+fcw_status fcw_query(const fcw_ctx* c, fcw_info* info) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  if (!info) { set_error("null info"); return FCW_E_ARG; }
+  std::memset(info, 0, sizeof *info);
+  info->ndof = c->ndof;
+  info->nnodes = c->nnodes;
+  info->ncells = c->ncell_total;
+  info->n_cut = c->n_cut;
+  info->n_uncut = c->n_uncut;
+  info->n_out = c->n_out;
+  info->n_loc = c->n_loc;
+  info->precision = c->precision;
+  info->footprint_bytes = c->footprint;
+  info->dt_crit = c->dt_crit;
+  info->min_evs_margin = c->min_margin;
+  return FCW_OK;
+}
+
+fcw_status fcw_export(const fcw_ctx* c, int32_t which, void* dst, int64_t capacity,
+                      int64_t* count) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  const void* srcp = nullptr;
+  int64_t n = 0;
+  size_t es = 8;
+  const int64_t ncand = c->n_cut_cand;
+  switch (which) {
+    case FCW_ARR_CELL_CLASS: srcp = c->d_cls; n = c->ncell_total; es = 1; break;
+    case FCW_ARR_CUT_CELLS: srcp = c->d_cut_cells; n = ncand; es = 4; break;
+    case FCW_ARR_K_REF: srcp = c->d_kref; n = (int64_t)c->n_loc * c->n_loc; break;
+    case FCW_ARR_K_CUT: srcp = c->d_kcut; n = ncand * c->n_loc * c->n_loc; break;
+    case FCW_ARR_M_CUT: srcp = c->d_mcut; n = ncand * c->n_s * c->n_s; break;
+    case FCW_ARR_LUMPED_CUT: srcp = c->d_lumped; n = ncand * c->n_s; break;
+    case FCW_ARR_MASS: srcp = c->d_mass; n = c->state >= 2 ? c->nnodes : 0; break;
+    case FCW_ARR_EVS_MARGIN: srcp = c->d_margin; n = ncand; break;
+    default: set_error("unknown array %d", which); return FCW_E_ARG;
+  }
+  if (count) *count = n;
+  if (!dst) return FCW_OK;
+  if (capacity < n) {
+    set_error("capacity %lld < %lld", (long long)capacity, (long long)n);
+    return FCW_E_ARG;
+  }
+  if (n == 0) return FCW_OK;
+  FCW_HIP(hipMemcpyAsync(dst, srcp, (size_t)n * es, hipMemcpyDeviceToHost, c->stream));
+  FCW_HIP(hipStreamSynchronize(c->stream));
+  return FCW_OK;
+}
+
+void fcw_destroy(fcw_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  free_all(*c);
+  delete c;
+}
+
+}  // extern "C"

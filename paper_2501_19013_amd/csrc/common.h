@@ -1,0 +1,125 @@
+// Internal declarations of the fcw library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fcw.h"
+
+namespace fcw {
+
+constexpr int kMaxP = 8;
+constexpr int kMaxNl = 256;  // largest n_loc built (3-D elasticity p=3: 192)
+
+// Cell classes as exported (FCW_ARR_CELL_CLASS).
+constexpr int8_t kClsOut = 0, kClsUncut = 1, kClsCut = 2;
+// Per-cell step info: >= 0 is the cut-cell index; negative codes below.
+constexpr int32_t kInfoOut = -1, kInfoUncut = -2;
+
+// 1-D tables of the reference element, FP64, device resident.
+struct RefTables {
+  double gll_x[kMaxP + 1], gll_w[kMaxP + 1];  // GLL nodes / weights (p+1 points)
+  double gl_x[kMaxP + 1], gl_w[kMaxP + 1];    // GL nodes / weights (p+1 points)
+};
+
+// Point-source data prepared on the device for one step call.
+struct SourceDev {
+  int32_t cell[3];  // cell coordinates containing the source
+  int32_t pad;
+  double f0;
+  double b[kMaxNl];  // rho * amp * dir_c * N_a(x_s), local (comp-major) order
+};
+
+struct Ctx {
+  // problem
+  int dim = 2, ncomp = 1, p = 1, depth = 0, precision = FCW_FP64;
+  int ncells[3] = {1, 1, 1};
+  int npts[3] = {1, 1, 1};  // nodes per direction
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h = 1;
+  double alpha = 1e-12, rho = 1, c = 1, E = 1, nu = 0.3;
+  int64_t ncell_total = 0, nnodes = 0, ndof = 0;
+  int n_s = 0, n_loc = 0;
+  hipStream_t stream = nullptr;
+  int state = 0;  // 1 assembled, 2 stabilised
+  bool poisoned = false;
+  std::vector<double> void_c, void_r;  // host copies
+  int nvoids = 0;
+
+  // counts
+  int64_t n_cut_cand = 0;  // cut cells before reclassification
+  int64_t n_cut = 0, n_uncut = 0, n_out = 0;
+  double dt_crit = 0.0, min_margin = 0.0;
+
+  // device buffers (FP64 setup data)
+  double* d_void_c = nullptr;
+  double* d_void_r = nullptr;
+  int8_t* d_cls = nullptr;        // [ncells]
+  int32_t* d_info = nullptr;      // [ncells]
+  int32_t* d_cut_cells = nullptr; // [n_cut_cand] cell index per cut candidate
+  int32_t* d_cut_vptr = nullptr;  // [n_cut_cand+1] offsets into d_cut_vidx
+  int32_t* d_cut_vidx = nullptr;  // void indices meeting each cut candidate
+  int32_t* d_all_void = nullptr;  // [n_cut_cand] tree found only void boxes
+  RefTables* d_tab = nullptr;
+  double* d_kref = nullptr;       // [n_loc^2]
+  double* d_mfull = nullptr;      // [n_s^2]
+  double* d_lref = nullptr;       // [n_s]
+  double* d_kcut = nullptr;       // [n_cut_cand * n_loc^2]
+  double* d_mcut = nullptr;       // [n_cut_cand * n_s^2]
+  double* d_lumped = nullptr;     // [n_cut_cand * n_s]
+  double* d_margin = nullptr;     // [n_cut_cand]
+  int32_t* d_evs_fail = nullptr;  // [1]
+  double* d_mass = nullptr;       // [nnodes]
+
+  // per-step operands in the step precision
+  void* d_invm = nullptr;     // [nnodes]
+  void* d_kref_s = nullptr;   // [n_loc^2]
+  void* d_kcut_s = nullptr;   // [n_cut_cand * n_loc(n_loc+1)/2], packed upper, column-major
+  double* d_invm64 = nullptr; // [nnodes] FP64 copy for the Lanczos iteration
+
+  // scratch
+  void* d_ubuf = nullptr;
+  size_t ubuf_bytes = 0;
+  SourceDev* d_src = nullptr;
+  int src_cap = 0;
+  int64_t footprint = 0;
+
+  size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
+};
+
+// error reporting (thread-local message)
+void set_error(const char* fmt, ...);
+fcw_status hip_fail(hipError_t e, const char* what);
+
+#define FCW_HIP(call)                                      \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return ::fcw::hip_fail(e_, #call); \
+  } while (0)
+
+// ---- launchers implemented in the .hip sources ----
+// setup.hip
+fcw_status setup_reference(Ctx& c);
+fcw_status setup_classify(Ctx& c);
+fcw_status setup_integrate(Ctx& c);
+fcw_status setup_reclassify(Ctx& c);
+fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda);
+fcw_status setup_mass_and_pack(Ctx& c);
+fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
+// step.hip
+bool step_supported(const Ctx& c);
+fcw_status launch_step(Ctx& c, int nrhs, const void* u_in, void* u_out, void* d,
+                       double t, double dt, int start);
+fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);
+fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
+// lanczos.hip
+fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax);
+
+// small helpers usable on host and device
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+}  // namespace fcw
+
+struct fcw_ctx : public fcw::Ctx {};

@@ -1,0 +1,197 @@
+// Critical time step of the central difference method (paper Sec. 2.3):
+//   dt_crit = 2 / sqrt(lambda_max(K, M)),
+// with lambda_max the largest eigenvalue of the symmetric operator M^{-1/2} K M^{-1/2}
+// on the active DOFs.  FP64 Lanczos iteration on the device (the operator is the tile
+// stiffness kernel in FP64); the largest eigenvalue of the tridiagonal Lanczos matrix is
+// found by Sturm-sequence bisection in a one-thread kernel.  Every reduction uses a
+// fixed block count and a fixed tree, so the result is bitwise reproducible.
+#include <cmath>
+
+#include "common.h"
+
+namespace fcw {
+
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+__device__ static double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if (t < off) sh[t] += sh[t + off];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ static double sum_partials(const double* part, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) v += part[i];
+  return block_sum(v, sh);
+}
+
+// splitmix64 hash -> uniform in [-1, 1)
+__device__ static double hash_unit(uint64_t i) {
+  uint64_t z = i + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ __launch_bounds__(kRedThreads) void start_vector_kernel(double* v, const double* invm,
+                                                                    int64_t nnodes, int ncomp,
+                                                                    double* part) {
+  __shared__ double sh[kRedThreads];
+  const int64_t n = nnodes * ncomp;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)kRedBlocks * kRedThreads) {
+    const double x = (invm[i % nnodes] > 0.0) ? hash_unit((uint64_t)i) : 0.0;
+    v[i] = x;
+    s += x * x;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void scale_kernel(double* v, const double* src,
+                                                             int64_t n, const double* part,
+                                                             double* beta_out) {
+  __shared__ double sh[kRedThreads];
+  const double nrm = sqrt(sum_partials(part, sh));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && beta_out) *beta_out = nrm;
+  const double inv = (nrm > 0.0) ? 1.0 / nrm : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)kRedBlocks * kRedThreads)
+    v[i] = src[i] * inv;
+}
+
+__global__ __launch_bounds__(kRedThreads) void dot_kernel(const double* a, const double* b,
+                                                           int64_t n, double* part) {
+  __shared__ double sh[kRedThreads];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)kRedBlocks * kRedThreads)
+    s += a[i] * b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// w <- w - alpha v - beta_prev v_prev, alpha = sum(part); partial sums of |w|^2
+__global__ __launch_bounds__(kRedThreads) void axpy_kernel(double* w, const double* v,
+                                                            const double* vprev, int64_t n,
+                                                            const double* part, double* alpha_out,
+                                                            const double* beta_prev,
+                                                            double* part2) {
+  __shared__ double sh[kRedThreads];
+  const double alpha = sum_partials(part, sh);
+  const double bp = beta_prev ? *beta_prev : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)kRedBlocks * kRedThreads) {
+    double x = w[i] - alpha * v[i];
+    if (vprev) x -= bp * vprev[i];
+    w[i] = x;
+    s += x * x;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part2[blockIdx.x] = s;
+}
+
+// largest eigenvalue of the symmetric tridiagonal (alpha[0..k), beta[0..k-1)) by
+// bisection on the Sturm count
+__global__ void tridiag_max_kernel(const double* alpha, const double* beta, int k, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
+    lo = fmin(lo, alpha[i] - r);
+    hi = fmax(hi, alpha[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    // number of eigenvalues greater than mid
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double b2 = (i > 0) ? beta[i - 1] * beta[i - 1] : 0.0;
+      q = alpha[i] - mid - ((i > 0) ? b2 / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q > 0.0) ++cnt;
+    }
+    if (cnt >= 1) lo = mid; else hi = mid;
+  }
+  *out = lo;
+}
+
+fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
+  const int64_t n = c.ndof;
+  double *v0 = nullptr, *v1 = nullptr, *w = nullptr, *ab = nullptr, *part = nullptr;
+  const size_t vb = (size_t)n * sizeof(double);
+  FCW_HIP(hipMallocAsync((void**)&v0, vb, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&v1, vb, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&w, vb, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&ab, (2 * (size_t)max_iter + 2) * sizeof(double), c.stream));
+  FCW_HIP(hipMallocAsync((void**)&part, 2 * kRedBlocks * sizeof(double), c.stream));
+  double* alpha = ab;
+  double* beta = ab + max_iter;
+  double* res = ab + 2 * max_iter;
+  double* part2 = part + kRedBlocks;
+
+  start_vector_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(w, c.d_invm64, c.nnodes,
+                                                                  c.ncomp, part);
+  scale_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(v1, w, n, part, nullptr);
+  FCW_HIP(hipGetLastError());
+  double* vcur = v1;
+  double* vprev = v0;
+  double last = -1.0, cur = 0.0;
+  int k = 0;
+  const int check = 20;
+  fcw_status st = FCW_OK;
+  for (int j = 0; j < max_iter; ++j) {
+    st = launch_apply_scaled64(c, vcur, w);
+    if (st != FCW_OK) break;
+    dot_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(w, vcur, n, part);
+    axpy_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(
+        w, vcur, j > 0 ? vprev : nullptr, n, part, alpha + j, j > 0 ? beta + j - 1 : nullptr,
+        part2);
+    scale_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(vprev, w, n, part2, beta + j);
+    FCW_HIP(hipGetLastError());
+    double* t = vprev;
+    vprev = vcur;
+    vcur = t;
+    k = j + 1;
+    if (k % check == 0 || k == max_iter) {
+      tridiag_max_kernel<<<1, 64, 0, c.stream>>>(alpha, beta, k, res);
+      double hb[2];
+      FCW_HIP(hipMemcpyAsync(&hb[0], res, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+      FCW_HIP(hipMemcpyAsync(&hb[1], beta + j, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+      FCW_HIP(hipStreamSynchronize(c.stream));
+      cur = hb[0];
+      if (last > 0.0 && fabs(cur - last) <= rtol * fabs(cur)) break;
+      if (!(hb[1] > 1e-300 * fabs(cur))) break;  // invariant subspace found
+      last = cur;
+    }
+  }
+  FCW_HIP(hipFreeAsync(v0, c.stream));
+  FCW_HIP(hipFreeAsync(v1, c.stream));
+  FCW_HIP(hipFreeAsync(w, c.stream));
+  FCW_HIP(hipFreeAsync(ab, c.stream));
+  FCW_HIP(hipFreeAsync(part, c.stream));
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  if (st != FCW_OK) return st;
+  if (!(cur > 0.0) || !std::isfinite(cur)) {
+    set_error("Lanczos iteration gave no positive eigenvalue (%g)", cur);
+    return FCW_E_NOCONV;
+  }
+  *lmax = cur;
+  return FCW_OK;
+}
+
+}  // namespace fcw

@@ -1,0 +1,1131 @@
+// Setup kernels of the spectral cell method, all in FP64 on the device:
+//  - 1-D GLL / GL rules (Sec. 2.2), uncut reference element and GLL lumped mass,
+//  - cell classification against the voids (Sec. 2.2: cells outside the physical
+//    domain are dropped) and compaction of the cut cells,
+//  - space-tree quadrature of every cut cell (Sec. 2.2) giving K_e and M^o_e,
+//  - eigenvalue stabilisation (Sec. 2.6) + HRZ lumping (Sec. 2.4) of the cut-cell
+//    masses by a batched parallel-ordering Jacobi eigensolver,
+//  - assembly of the diagonal mass and packing of the per-step operands.
+// Geometric predicates and quadrature coordinates are evaluated with contraction
+// disabled so that they follow plain IEEE double arithmetic step by step.
+#include <cmath>
+#include <cstdio>
+
+#include "common.h"
+
+namespace fcw {
+
+// --------------------------------------------------------------------------------
+// 1-D rules
+// --------------------------------------------------------------------------------
+
+__device__ static void legendre_pair(int n, double x, double& pn, double& pn1) {
+  // P_n(x) and P_{n-1}(x) by the three-term recurrence
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { pn = 1.0; pn1 = 0.0; return; }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  pn1 = p0;
+}
+
+__global__ void ref_tables_kernel(RefTables* tab, int p) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double pi = 3.14159265358979323846;
+  // GLL: -1, +1 and the roots of P_p'; Newton on P_p' with P_p'' from the ODE.
+  tab->gll_x[0] = -1.0;
+  tab->gll_x[p] = 1.0;
+  for (int i = 1; i < p; ++i) {
+    double x = -cos(pi * i / p);
+    for (int it = 0; it < 100; ++it) {
+      double pn, pn1;
+      legendre_pair(p, x, pn, pn1);
+      double d1 = p * (pn1 - x * pn) / (1.0 - x * x);
+      double d2 = (2.0 * x * d1 - p * (p + 1.0) * pn) / (1.0 - x * x);
+      double dx = d1 / d2;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    tab->gll_x[i] = x;
+  }
+  for (int i = 0; i <= p; ++i) {
+    double pn, pn1;
+    legendre_pair(p, tab->gll_x[i], pn, pn1);
+    tab->gll_w[i] = 2.0 / (p * (p + 1.0) * pn * pn);
+  }
+  // GL with n = p+1 points: roots of P_n.
+  const int n = p + 1;
+  for (int i = 0; i < n; ++i) {
+    double x = -cos(pi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn, pn1;
+      legendre_pair(n, x, pn, pn1);
+      double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
+      double dx = pn / d1;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    double pn, pn1;
+    legendre_pair(n, x, pn, pn1);
+    double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
+    tab->gl_x[i] = x;
+    tab->gl_w[i] = 2.0 / ((1.0 - x * x) * d1 * d1);
+  }
+}
+
+// Lagrange polynomials on the GLL nodes and their derivatives at x (product rule).
+template <int NP1>
+__device__ static void lagrange_1d(const double* nodes, double x, double* L, double* dL) {
+#pragma clang fp contract(off)
+  for (int i = 0; i < NP1; ++i) {
+    double v = 1.0;
+    for (int j = 0; j < NP1; ++j)
+      if (j != i) v *= (x - nodes[j]) / (nodes[i] - nodes[j]);
+    L[i] = v;
+    double dv = 0.0;
+    for (int k = 0; k < NP1; ++k) {
+      if (k == i) continue;
+      double t = 1.0 / (nodes[i] - nodes[k]);
+      for (int j = 0; j < NP1; ++j)
+        if (j != i && j != k) t *= (x - nodes[j]) / (nodes[i] - nodes[j]);
+      dv += t;
+    }
+    dL[i] = dv;
+  }
+}
+
+__global__ void gll_lumped_kernel(const RefTables* tab, int dim, int p, double h, double rho,
+                                  double* lref) {
+  int ns = 1;
+  for (int k = 0; k < dim; ++k) ns *= (p + 1);
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= ns) return;
+  double m = rho;
+  for (int k = 0; k < dim; ++k) m *= 0.5 * h;
+  int r = a;
+  for (int k = 0; k < dim; ++k) {
+    m *= tab->gll_w[r % (p + 1)];
+    r /= (p + 1);
+  }
+  lref[a] = m;
+}
+
+// --------------------------------------------------------------------------------
+// Classification
+// --------------------------------------------------------------------------------
+
+struct Grid {
+  int dim;
+  int n[3];
+  double lo[3];
+  double h;
+};
+
+__device__ static void cell_box(const Grid& g, int64_t cell, double* blo, double* bhi) {
+#pragma clang fp contract(off)
+  int64_t r = cell;
+  for (int k = 0; k < g.dim; ++k) {
+    int64_t i = r % g.n[k];
+    r /= g.n[k];
+    blo[k] = g.lo[k] + (double)i * g.h;
+    bhi[k] = g.lo[k] + (double)(i + 1) * g.h;
+  }
+}
+
+// (meets, contained) of box [lo,hi] and ball (c, r): squared distance to the box
+// below r^2, squared distance to the farthest corner at most r^2.
+__device__ static void box_ball(int dim, const double* lo, const double* hi, const double* c,
+                                double r, bool& meets, bool& contained) {
+#pragma clang fp contract(off)
+  double dmin2 = 0.0, dmax2 = 0.0;
+  for (int k = 0; k < dim; ++k) {
+    double gap = fmax(fmax(lo[k] - c[k], 0.0), c[k] - hi[k]);
+    double far = fmax(fabs(c[k] - lo[k]), fabs(hi[k] - c[k]));
+    dmin2 = dmin2 + gap * gap;
+    dmax2 = dmax2 + far * far;
+  }
+  meets = dmin2 < r * r;
+  contained = dmax2 <= r * r;
+}
+
+__global__ void classify_kernel(Grid g, int64_t ncell, int nvoids, const double* vc,
+                                const double* vr, int8_t* cls, int32_t* iscut,
+                                int32_t* nmeet) {
+  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  double blo[3], bhi[3];
+  cell_box(g, cell, blo, bhi);
+  bool any = false, inside = false;
+  int cnt = 0;
+  for (int v = 0; v < nvoids; ++v) {
+    bool m, c;
+    box_ball(g.dim, blo, bhi, vc + (int64_t)v * g.dim, vr[v], m, c);
+    inside |= c;
+    any |= m;
+    cnt += m ? 1 : 0;
+  }
+  int8_t k = inside ? kClsOut : (any ? kClsCut : kClsUncut);
+  cls[cell] = k;
+  iscut[cell] = (k == kClsCut) ? 1 : 0;
+  nmeet[cell] = (k == kClsCut) ? cnt : 0;
+}
+
+__global__ void compact_cut_kernel(Grid g, int64_t ncell, int nvoids, const double* vc,
+                                   const double* vr, const int8_t* cls, const int32_t* cutpos,
+                                   const int32_t* voff, int32_t* info, int32_t* cut_cells,
+                                   int32_t* vptr, int32_t* vidx) {
+  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= ncell) return;
+  int8_t k = cls[cell];
+  if (k == kClsOut) { info[cell] = kInfoOut; return; }
+  if (k == kClsUncut) { info[cell] = kInfoUncut; return; }
+  int q = cutpos[cell];
+  info[cell] = q;
+  cut_cells[q] = (int32_t)cell;
+  int off = voff[cell];
+  vptr[q] = off;
+  double blo[3], bhi[3];
+  cell_box(g, cell, blo, bhi);
+  for (int v = 0; v < nvoids; ++v) {
+    bool m, c;
+    box_ball(g.dim, blo, bhi, vc + (int64_t)v * g.dim, vr[v], m, c);
+    if (m) vidx[off++] = v;
+  }
+}
+
+// ---- deterministic exclusive scan of int32 (two levels, 4096 items per block) ----
+constexpr int kScanThreads = 1024, kScanItems = 4;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+__device__ static int block_exclusive_scan_1024(int v, int* sh) {
+  // Hillis-Steele inclusive scan over 1024 threads, returns the exclusive prefix.
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    int add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int incl = sh[t];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(1024) void scan_block_kernel(const int32_t* in, int32_t* out,
+                                                          int32_t* sums, int64_t n) {
+  __shared__ int sh[kScanThreads];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int tot = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? in[base + i] : 0;
+    tot += v[i];
+  }
+  int pre = block_exclusive_scan_1024(tot, sh);
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) out[base + i] = pre;
+    pre += v[i];
+  }
+  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = pre;
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(int32_t* sums, int nblocks,
+                                                         int32_t* total) {
+  __shared__ int sh[kScanThreads];
+  int carry = 0;
+  for (int b0 = 0; b0 < nblocks; b0 += kScanThreads) {
+    int i = b0 + threadIdx.x;
+    int v = (i < nblocks) ? sums[i] : 0;
+    int pre = block_exclusive_scan_1024(v, sh);
+    if (i < nblocks) sums[i] = pre + carry;
+    // total of this chunk: last thread's inclusive value
+    if (threadIdx.x == kScanThreads - 1) sh[0] = pre + v;
+    __syncthreads();
+    carry += sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) total[0] = carry;
+}
+
+__global__ void scan_add_kernel(int32_t* out, const int32_t* sums, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / kScanBlock];
+}
+
+// exclusive scan of n ints on the stream; writes the total to *total_host (syncs).
+static fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
+                                 int32_t* total_host) {
+  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb < 1) nb = 1;
+  int32_t* sums = nullptr;
+  FCW_HIP(hipMallocAsync((void**)&sums, (nb + 1) * sizeof(int32_t), c.stream));
+  scan_block_kernel<<<(unsigned)nb, kScanThreads, 0, c.stream>>>(in, out, sums, n);
+  scan_sums_kernel<<<1, kScanThreads, 0, c.stream>>>(sums, (int)nb, sums + nb);
+  scan_add_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c.stream>>>(out, sums, n);
+  FCW_HIP(hipGetLastError());
+  FCW_HIP(hipMemcpyAsync(total_host, sums + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  FCW_HIP(hipFreeAsync(sums, c.stream));
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  return FCW_OK;
+}
+
+static Grid make_grid(const Ctx& c) {
+  Grid g;
+  g.dim = c.dim;
+  g.h = c.h;
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = c.ncells[k];
+    g.lo[k] = c.lo[k];
+  }
+  return g;
+}
+
+fcw_status setup_reference(Ctx& c) {
+  ref_tables_kernel<<<1, 64, 0, c.stream>>>(c.d_tab, c.p);
+  gll_lumped_kernel<<<(c.n_s + 255) / 256, 256, 0, c.stream>>>(c.d_tab, c.dim, c.p, c.h,
+                                                              c.rho, c.d_lref);
+  FCW_HIP(hipGetLastError());
+  return FCW_OK;
+}
+
+fcw_status setup_classify(Ctx& c) {
+  Grid g = make_grid(c);
+  const int64_t n = c.ncell_total;
+  int32_t *iscut = nullptr, *nmeet = nullptr, *cutpos = nullptr, *voff = nullptr;
+  FCW_HIP(hipMallocAsync((void**)&iscut, n * 4, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&nmeet, n * 4, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&cutpos, n * 4, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&voff, n * 4, c.stream));
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  classify_kernel<<<nb, 256, 0, c.stream>>>(g, n, c.nvoids, c.d_void_c, c.d_void_r, c.d_cls,
+                                            iscut, nmeet);
+  FCW_HIP(hipGetLastError());
+  int32_t ncut = 0, nv = 0;
+  fcw_status st = exclusive_scan(c, iscut, cutpos, n, &ncut);
+  if (st != FCW_OK) return st;
+  st = exclusive_scan(c, nmeet, voff, n, &nv);
+  if (st != FCW_OK) return st;
+  c.n_cut_cand = ncut;
+  const int64_t nc = ncut > 0 ? ncut : 1;
+  FCW_HIP(hipMalloc((void**)&c.d_cut_cells, nc * 4));
+  FCW_HIP(hipMalloc((void**)&c.d_cut_vptr, (nc + 1) * 4));
+  FCW_HIP(hipMalloc((void**)&c.d_cut_vidx, (nv > 0 ? nv : 1) * 4));
+  FCW_HIP(hipMalloc((void**)&c.d_all_void, nc * 4));
+  c.footprint += nc * 4 * 3 + (nv > 0 ? nv : 1) * 4;
+  compact_cut_kernel<<<nb, 256, 0, c.stream>>>(g, n, c.nvoids, c.d_void_c, c.d_void_r,
+                                               c.d_cls, cutpos, voff, c.d_info, c.d_cut_cells,
+                                               c.d_cut_vptr, c.d_cut_vidx);
+  FCW_HIP(hipGetLastError());
+  FCW_HIP(hipMemcpyAsync(c.d_cut_vptr + ncut, &nv, 4, hipMemcpyHostToDevice, c.stream));
+  FCW_HIP(hipFreeAsync(iscut, c.stream));
+  FCW_HIP(hipFreeAsync(nmeet, c.stream));
+  FCW_HIP(hipFreeAsync(cutpos, c.stream));
+  FCW_HIP(hipFreeAsync(voff, c.stream));
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  return FCW_OK;
+}
+
+// --------------------------------------------------------------------------------
+// Space-tree quadrature
+// --------------------------------------------------------------------------------
+
+// Box record of the tree: level (4 bits) | kind (2 bits) | ix, iy, iz (8 bits each).
+enum { kKindAlpha = 0, kKindOne = 1, kKindLeaf = 2, kKindCut = 3 };
+__device__ static inline uint32_t box_pack(int lvl, int kind, int ix, int iy, int iz) {
+  return (uint32_t)lvl | ((uint32_t)kind << 4) | ((uint32_t)ix << 6) | ((uint32_t)iy << 14) |
+         ((uint32_t)iz << 22);
+}
+__device__ static inline void box_unpack(uint32_t b, int& lvl, int& kind, int* ix) {
+  lvl = b & 15;
+  kind = (b >> 4) & 3;
+  ix[0] = (b >> 6) & 255;
+  ix[1] = (b >> 14) & 255;
+  ix[2] = (b >> 22) & 255;
+}
+
+// bounds of a tree box by replaying the midpoint bisection from the cell box
+__device__ static void tree_box_bounds(int dim, const double* clo, const double* chi, int lvl,
+                                       const int* ix, double* lo, double* hi) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < dim; ++k) {
+    double a = clo[k], b = chi[k];
+    for (int s = lvl - 1; s >= 0; --s) {
+      double mid = 0.5 * (a + b);
+      if ((ix[k] >> s) & 1) a = mid; else b = mid;
+    }
+    lo[k] = a;
+    hi[k] = b;
+  }
+}
+
+struct TreeArgs {
+  Grid g;
+  const int32_t* cut_cells;
+  const int32_t* vptr;
+  const int32_t* vidx;
+  const double* vc;
+  const double* vr;
+  const RefTables* tab;
+  double alpha, rho, c2, lam, mu;
+  int depth;
+  int reference;  // 1: integrate the full cell [0,h]^d with no voids (one block)
+  double* kout;
+  double* mout;
+  int32_t* all_void;
+};
+
+constexpr int kTreeThreads = 256;
+constexpr int kTreeMaxBoxes = 1024;
+constexpr int kTreeBatch = 64;
+
+// block-wide exclusive scan of two counters (256 threads)
+__device__ static void scan2_256(int a, int b, int& pa, int& pb, int& ta, int& tb, int* sh) {
+  int t = threadIdx.x;
+  sh[t] = a;
+  sh[256 + t] = b;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int xa = (t >= off) ? sh[t - off] : 0;
+    int xb = (t >= off) ? sh[256 + t - off] : 0;
+    __syncthreads();
+    sh[t] += xa;
+    sh[256 + t] += xb;
+    __syncthreads();
+  }
+  pa = sh[t] - a;
+  pb = sh[256 + t] - b;
+  ta = sh[255];
+  tb = sh[511];
+  __syncthreads();
+}
+
+template <int DIM, int P, int NCOMP>
+__global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a) {
+#pragma clang fp contract(off)
+  constexpr int NP1 = P + 1;
+  constexpr int NS = ipow(NP1, DIM);
+  constexpr int NPB = NS;  // GL points per box
+  constexpr int NENT = NS * (NS + 1) / 2;
+  constexpr int EPT = (NENT + kTreeThreads - 1) / kTreeThreads;
+  constexpr int NG = (NCOMP == 1) ? 1 : DIM * DIM;
+  constexpr int PD = 2 + 2 * DIM * NP1;  // per point: w_mass, w_stiff, L[DIM][NP1], dL[DIM][NP1]
+
+  __shared__ uint32_t lst[2][kTreeMaxBoxes];
+  __shared__ uint32_t outl[kTreeMaxBoxes];
+  __shared__ int scan_sh[512];
+  __shared__ double pts[kTreeBatch * PD];
+  __shared__ int s_ncur, s_nout;
+
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  double clo[3] = {0, 0, 0}, chi[3] = {0, 0, 0};
+  int vbeg = 0, vend = 0;
+  if (a.reference) {
+    for (int k = 0; k < DIM; ++k) { clo[k] = 0.0; chi[k] = a.g.h; }
+  } else {
+    cell_box(a.g, a.cut_cells[q], clo, chi);
+    vbeg = a.vptr[q];
+    vend = a.vptr[q + 1];
+  }
+  const double* gll = a.tab->gll_x;
+
+  // ---- breadth-first construction of the tree, deterministic order ----
+  if (tid == 0) {
+    lst[0][0] = box_pack(0, kKindCut, 0, 0, 0);
+    s_ncur = 1;
+    s_nout = 0;
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int lvl = 0; lvl <= a.depth; ++lvl) {
+    const int ncur = s_ncur;
+    int nnext = 0;
+    for (int base = 0; base < ncur; base += kTreeThreads) {
+      int i = base + tid;
+      int kind = -1;
+      int ix[3] = {0, 0, 0};
+      if (i < ncur) {
+        int l, kd;
+        box_unpack(lst[cur][i], l, kd, ix);
+        double lo[3], hi[3];
+        tree_box_bounds(DIM, clo, chi, lvl, ix, lo, hi);
+        bool any = false, inside = false;
+        for (int v = vbeg; v < vend; ++v) {
+          int vi = a.vidx[v];
+          bool m, cc;
+          box_ball(DIM, lo, hi, a.vc + (int64_t)vi * DIM, a.vr[vi], m, cc);
+          inside |= cc;
+          any |= m;
+        }
+        kind = inside ? kKindAlpha : (any ? (lvl < a.depth ? kKindCut : kKindLeaf) : kKindOne);
+      }
+      int nout_i = (kind >= 0 && kind != kKindCut) ? 1 : 0;
+      int nch_i = (kind == kKindCut) ? (1 << DIM) : 0;
+      int po, pc, to, tc;
+      scan2_256(nout_i, nch_i, po, pc, to, tc, scan_sh);
+      const int nout0 = s_nout;
+      if (nout_i) outl[nout0 + po] = box_pack(lvl, kind, ix[0], ix[1], ix[2]);
+      if (nch_i) {
+        for (int ch = 0; ch < (1 << DIM); ++ch) {
+          int cx = 2 * ix[0] + (ch & 1);
+          int cy = 2 * ix[1] + ((ch >> 1) & 1);
+          int cz = 2 * ix[2] + ((ch >> 2) & 1);
+          // child order: x bit slowest, matching lexicographic (x, y, z) corner order
+          int corder = 0;
+          for (int k = 0; k < DIM; ++k) corder = corder * 2 + ((ch >> k) & 1);
+          int pos = nnext + pc + corder;
+          if (pos < kTreeMaxBoxes) lst[cur ^ 1][pos] = box_pack(lvl + 1, kKindCut, cx, cy, cz);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_nout = nout0 + to;
+      nnext += tc;
+      __syncthreads();
+    }
+    if (tid == 0) s_ncur = nnext;
+    cur ^= 1;
+    __syncthreads();
+  }
+  const int nout = s_nout;
+
+  // ---- integration ----
+  int ei[EPT], ej[EPT];
+  double accM[EPT], accG[EPT][NG];
+  for (int e = 0; e < EPT; ++e) {
+    int lin = tid + e * kTreeThreads;
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= lin) ++j;
+    int i = lin - j * (j + 1) / 2;
+    ei[e] = (lin < NENT) ? i : 0;
+    ej[e] = (lin < NENT) ? j : 0;
+    accM[e] = 0.0;
+    for (int g = 0; g < NG; ++g) accG[e][g] = 0.0;
+  }
+  const double jac = 2.0 / a.g.h;
+  const int npts_total = nout * NPB;
+  for (int pb = 0; pb < npts_total; pb += kTreeBatch) {
+    if (tid < kTreeBatch) {
+      int ip = pb + tid;
+      double* d = pts + tid * PD;
+      if (ip < npts_total) {
+        int bi = ip / NPB, qi = ip % NPB;
+        int lvl, kind, ix[3];
+        box_unpack(outl[bi], lvl, kind, ix);
+        double lo[3], hi[3];
+        tree_box_bounds(DIM, clo, chi, lvl, ix, lo, hi);
+        double x[3], w = 1.0;
+        int r = qi;
+        for (int k = 0; k < DIM; ++k) {
+          int m = r % NP1;
+          r /= NP1;
+          double half = 0.5 * (hi[k] - lo[k]);
+          x[k] = lo[k] + (a.tab->gl_x[m] + 1.0) * half;
+          w = w * (a.tab->gl_w[m] * half);
+        }
+        double al = 1.0;
+        if (kind == kKindAlpha) {
+          al = a.alpha;
+        } else if (kind == kKindLeaf) {
+          for (int v = vbeg; v < vend; ++v) {
+            int vi = a.vidx[v];
+            const double* cc = a.vc + (int64_t)vi * DIM;
+            double d2 = 0.0;
+            for (int k = 0; k < DIM; ++k) d2 = d2 + (x[k] - cc[k]) * (x[k] - cc[k]);
+            if (d2 < a.vr[vi] * a.vr[vi]) { al = a.alpha; break; }
+          }
+        }
+        d[0] = w * al;
+        d[1] = w * al * jac * jac;
+        for (int k = 0; k < DIM; ++k) {
+          double xi = 2.0 * (x[k] - clo[k]) / a.g.h - 1.0;
+          lagrange_1d<NP1>(gll, xi, d + 2 + k * NP1, d + 2 + DIM * NP1 + k * NP1);
+        }
+      } else {
+        for (int k = 0; k < PD; ++k) d[k] = 0.0;
+      }
+    }
+    __syncthreads();
+    const int nb = min(kTreeBatch, npts_total - pb);
+    for (int e = 0; e < EPT; ++e) {
+      if (tid + e * kTreeThreads >= NENT) break;
+      int ia[3], ja[3];
+      int ri = ei[e], rj = ej[e];
+      for (int k = 0; k < DIM; ++k) {
+        ia[k] = ri % NP1; ri /= NP1;
+        ja[k] = rj % NP1; rj /= NP1;
+      }
+      double sm = 0.0;
+      double sg[NG];
+      for (int g = 0; g < NG; ++g) sg[g] = 0.0;
+      for (int qp = 0; qp < nb; ++qp) {
+        const double* d = pts + qp * PD;
+        const double* L = d + 2;
+        const double* dL = d + 2 + DIM * NP1;
+        double Ni = 1.0, Nj = 1.0;
+        double gi[DIM], gj[DIM];
+        for (int k = 0; k < DIM; ++k) {
+          Ni *= L[k * NP1 + ia[k]];
+          Nj *= L[k * NP1 + ja[k]];
+        }
+        for (int b = 0; b < DIM; ++b) {
+          double vi = dL[b * NP1 + ia[b]], vj = dL[b * NP1 + ja[b]];
+          for (int k = 0; k < DIM; ++k) {
+            if (k == b) continue;
+            vi *= L[k * NP1 + ia[k]];
+            vj *= L[k * NP1 + ja[k]];
+          }
+          gi[b] = vi;
+          gj[b] = vj;
+        }
+        sm += d[0] * Ni * Nj;
+        if (NCOMP == 1) {
+          double s = 0.0;
+          for (int b = 0; b < DIM; ++b) s += gi[b] * gj[b];
+          sg[0] += d[1] * s;
+        } else {
+          for (int b = 0; b < DIM; ++b)
+            for (int c2 = 0; c2 < DIM; ++c2) sg[b * DIM + c2] += d[1] * gi[b] * gj[c2];
+        }
+      }
+      accM[e] += sm;
+      for (int g = 0; g < NG; ++g) accG[e][g] += sg[g];
+    }
+    __syncthreads();
+  }
+
+  // ---- write K (n_loc x n_loc) and scalar M (n_s x n_s), both full symmetric ----
+  constexpr int NL = NCOMP * NS;
+  double* K = a.kout + (int64_t)q * NL * NL;
+  double* M = a.mout + (int64_t)q * NS * NS;
+  for (int e = 0; e < EPT; ++e) {
+    if (tid + e * kTreeThreads >= NENT) break;
+    const int i = ei[e], j = ej[e];
+    const double m = a.rho * accM[e];
+    M[i * NS + j] = m;
+    M[j * NS + i] = m;
+    if (NCOMP == 1) {
+      const double k = a.c2 * a.rho * accG[e][0];
+      K[i * NL + j] = k;
+      K[j * NL + i] = k;
+    } else {
+      double tr = 0.0;
+      for (int b = 0; b < DIM; ++b) tr += accG[e][b * DIM + b];
+      for (int cc = 0; cc < NCOMP; ++cc)
+        for (int ee = 0; ee < NCOMP; ++ee) {
+          // K[(c,i),(e,j)] = lam G_ce[i][j] + mu G_ec[i][j] + mu delta_ce sum_a G_aa[i][j]
+          double v = a.lam * accG[e][cc * DIM + ee] + a.mu * accG[e][ee * DIM + cc] +
+                     (cc == ee ? a.mu * tr : 0.0);
+          K[(cc * NS + i) * NL + ee * NS + j] = v;
+          K[(ee * NS + j) * NL + cc * NS + i] = v;
+        }
+    }
+  }
+  if (tid == 0 && !a.reference) {
+    int allv = 1;
+    for (int b = 0; b < nout; ++b) {
+      int lvl, kind, ix[3];
+      box_unpack(outl[b], lvl, kind, ix);
+      if (kind != kKindAlpha) { allv = 0; break; }
+    }
+    a.all_void[q] = allv;
+  }
+}
+
+template <int DIM, int P, int NCOMP>
+static fcw_status launch_tree(Ctx& c, TreeArgs& ta, int nblocks) {
+  tree_integrate_kernel<DIM, P, NCOMP><<<nblocks, kTreeThreads, 0, c.stream>>>(ta);
+  FCW_HIP(hipGetLastError());
+  return FCW_OK;
+}
+
+static fcw_status dispatch_tree(Ctx& c, TreeArgs& ta, int nblocks) {
+#define FCW_TREE_CASE(D, PP, NC) \
+  if (c.dim == D && c.p == PP && c.ncomp == NC) return launch_tree<D, PP, NC>(c, ta, nblocks);
+  FCW_TREE_CASE(2, 1, 1) FCW_TREE_CASE(2, 2, 1) FCW_TREE_CASE(2, 3, 1) FCW_TREE_CASE(2, 4, 1)
+  FCW_TREE_CASE(2, 5, 1) FCW_TREE_CASE(2, 6, 1)
+  FCW_TREE_CASE(3, 1, 1) FCW_TREE_CASE(3, 2, 1) FCW_TREE_CASE(3, 3, 1) FCW_TREE_CASE(3, 4, 1)
+  FCW_TREE_CASE(3, 1, 3) FCW_TREE_CASE(3, 2, 3) FCW_TREE_CASE(3, 3, 3)
+#undef FCW_TREE_CASE
+  set_error("tree integration not built for dim=%d p=%d ncomp=%d", c.dim, c.p, c.ncomp);
+  return FCW_E_UNSUPPORTED;
+}
+
+fcw_status setup_integrate(Ctx& c) {
+  TreeArgs ta{};
+  ta.g = make_grid(c);
+  ta.cut_cells = c.d_cut_cells;
+  ta.vptr = c.d_cut_vptr;
+  ta.vidx = c.d_cut_vidx;
+  ta.vc = c.d_void_c;
+  ta.vr = c.d_void_r;
+  ta.tab = c.d_tab;
+  ta.alpha = c.alpha;
+  ta.rho = c.rho;
+  ta.c2 = c.c * c.c;
+  ta.lam = c.E * c.nu / ((1.0 + c.nu) * (1.0 - 2.0 * c.nu));
+  ta.mu = c.E / (2.0 * (1.0 + c.nu));
+  ta.depth = c.depth;
+  // reference (uncut) cell: one box integrated with constant 1
+  ta.reference = 1;
+  ta.kout = c.d_kref;
+  ta.mout = c.d_mfull;
+  ta.all_void = c.d_all_void;
+  fcw_status st = dispatch_tree(c, ta, 1);
+  if (st != FCW_OK) return st;
+  if (c.n_cut_cand > 0) {
+    ta.reference = 0;
+    ta.kout = c.d_kcut;
+    ta.mout = c.d_mcut;
+    st = dispatch_tree(c, ta, (int)c.n_cut_cand);
+    if (st != FCW_OK) return st;
+  }
+  return FCW_OK;
+}
+
+// --------------------------------------------------------------------------------
+// Eigenvalue stabilisation + HRZ lumping (one workgroup per cut cell)
+// --------------------------------------------------------------------------------
+
+struct EvsArgs {
+  int n, m;  // matrix order and its even padding
+  const double* mcut;
+  const double* mfull;
+  double eps, f_lambda;
+  int max_sweeps;
+  double tol;
+  double* lumped;
+  double* margin;
+  int32_t* fail;
+};
+
+constexpr int kEvsThreads = 256;
+
+__device__ static double block_max_256(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) sh[t] = fmax(sh[t], sh[t + off]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ static double block_sum_256(double v, double* sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) sh[t] += sh[t + off];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kEvsThreads) void evs_lump_kernel(EvsArgs a) {
+  extern __shared__ double sm[];
+  const int n = a.n, m = a.m, ld = m + 1;
+  double* red = sm;                   // 256
+  double* dg = red + kEvsThreads;     // n: original diagonal
+  double* cs = dg + n;                // m/2 (c, s) pairs
+  int* pq = (int*)(cs + m);           // m/2 (p, q) pairs
+  double* A = (double*)(pq + m + (m & 1)) ;
+  double* V = A + m * ld;             // A, V only when eps != 0
+  const int tid = threadIdx.x;
+  const int q = blockIdx.x;
+  const double* Mo = a.mcut + (int64_t)q * n * n;
+
+  double s_all = 0.0, s_diag = 0.0, mf = -1e300;
+  for (int idx = tid; idx < n * n; idx += kEvsThreads) {
+    double v = Mo[idx];
+    s_all += v;
+    if (idx / n == idx % n) s_diag += v;
+    mf = fmax(mf, a.mfull[idx]);
+  }
+  for (int i = tid; i < n; i += kEvsThreads) dg[i] = Mo[i * n + i];
+  if (a.eps != 0.0) {
+    for (int idx = tid; idx < m * m; idx += kEvsThreads) {
+      int i = idx / m, j = idx % m;
+      A[i * ld + j] = (i < n && j < n) ? Mo[i * n + j] : 0.0;
+      V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+  }
+  const double me = block_sum_256(s_all, red);
+  const double tr = block_sum_256(s_diag, red);
+  const double maxmf = block_max_256(mf, red);
+  __syncthreads();
+
+  bool converged = true;
+  double marg = 1e300;
+  if (a.eps != 0.0) {
+    converged = false;
+    for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+      double off = 0.0;
+      for (int idx = tid; idx < n * n; idx += kEvsThreads) {
+        int i = idx / n, j = idx % n;
+        if (i < j) {
+          double den = sqrt(fabs(A[i * ld + i] * A[j * ld + j]));
+          double r = fabs(A[i * ld + j]);
+          off = fmax(off, den > 0.0 ? r / den : (r > 0.0 ? 1e300 : 0.0));
+        }
+      }
+      off = block_max_256(off, red);
+      if (off <= a.tol) { converged = true; break; }
+      for (int r = 0; r < m - 1; ++r) {
+        if (tid < m / 2) {
+          int p0, q0;
+          if (tid == 0) { p0 = m - 1; q0 = r; }
+          else { p0 = (r + tid) % (m - 1); q0 = (r - tid + (m - 1)) % (m - 1); }
+          int pp = min(p0, q0), qq = max(p0, q0);
+          double apq = A[pp * ld + qq];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            double tau = (A[qq * ld + qq] - A[pp * ld + pp]) / (2.0 * apq);
+            double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+          pq[2 * tid] = pp;
+          pq[2 * tid + 1] = qq;
+          cs[2 * tid] = c;
+          cs[2 * tid + 1] = s;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (m / 2) * m; idx += kEvsThreads) {
+          int k = idx / m, col = idx % m;
+          int pp = pq[2 * k], qq = pq[2 * k + 1];
+          double c = cs[2 * k], s = cs[2 * k + 1];
+          double ap = A[pp * ld + col], aq = A[qq * ld + col];
+          A[pp * ld + col] = c * ap - s * aq;
+          A[qq * ld + col] = s * ap + c * aq;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (m / 2) * m; idx += kEvsThreads) {
+          int k = idx / m, row = idx % m;
+          int pp = pq[2 * k], qq = pq[2 * k + 1];
+          double c = cs[2 * k], s = cs[2 * k + 1];
+          double ap = A[row * ld + pp], aq = A[row * ld + qq];
+          A[row * ld + pp] = c * ap - s * aq;
+          A[row * ld + qq] = s * ap + c * aq;
+          double vp = V[row * ld + pp], vq = V[row * ld + qq];
+          V[row * ld + pp] = c * vp - s * vq;
+          V[row * ld + qq] = s * vp + c * vq;
+        }
+        __syncthreads();
+      }
+    }
+    // eigenvalues on the diagonal; small set S = {i : lambda_i < f_lambda lambda_max}
+    double lmax = -1e300;
+    for (int i = tid; i < n; i += kEvsThreads) lmax = fmax(lmax, A[i * ld + i]);
+    lmax = block_max_256(lmax, red);
+    double mg = 1e300;
+    for (int i = tid; i < n; i += kEvsThreads) mg = fmin(mg, fabs(A[i * ld + i] / lmax - a.f_lambda));
+    marg = -block_max_256(-mg, red);
+    // diag(M~^s)_k = sum_{i in S} V_ki^2 ; red[k] holds it for k < n (n <= 256)
+    double dk = 0.0;
+    if (tid < n) {
+      for (int i = 0; i < n; ++i)
+        if (A[i * ld + i] < a.f_lambda * lmax) dk += V[tid * ld + i] * V[tid * ld + i];
+    }
+    __syncthreads();
+    const double maxd = block_max_256(tid < n ? dk : 0.0, red);
+    if (tid < n) {
+      double ms = (maxd > 0.0) ? (maxmf / maxd) * dk : 0.0;
+      a.lumped[(int64_t)q * n + tid] = me / tr * dg[tid] + a.eps * ms;
+    }
+  } else {
+    for (int i = tid; i < n; i += kEvsThreads) a.lumped[(int64_t)q * n + i] = me / tr * dg[i];
+  }
+  if (tid == 0) {
+    a.margin[q] = marg;
+    a.fail[q] = converged ? 0 : 1;
+  }
+}
+
+fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda) {
+  if (c.n_cut_cand == 0) return FCW_OK;
+  const int n = c.n_s;
+  if (n > 256) {
+    set_error("eigenvalue stabilisation supports at most 256 nodes per cell (got %d)", n);
+    return FCW_E_UNSUPPORTED;
+  }
+  const int m = (n + 1) / 2 * 2;
+  auto frame = [&](bool full) {
+    size_t b = (size_t)(kEvsThreads + n + m) * sizeof(double) + (size_t)(m + 2) * sizeof(int);
+    b = (b + 7) / 8 * 8;
+    if (full) b += (size_t)2 * m * (m + 1) * sizeof(double);
+    return b;
+  };
+  const size_t shbytes = frame(eps != 0.0);
+  if (shbytes > 160 * 1024) {
+    set_error("eigenvalue stabilisation of n_s=%d does not fit in LDS", n);
+    return FCW_E_UNSUPPORTED;
+  }
+  int32_t* fail = nullptr;
+  FCW_HIP(hipMallocAsync((void**)&fail, c.n_cut_cand * 4, c.stream));
+  EvsArgs ea{};
+  ea.n = n;
+  ea.m = m;
+  ea.mcut = c.d_mcut;
+  ea.mfull = c.d_mfull;
+  ea.eps = eps;
+  ea.f_lambda = f_lambda;
+  ea.max_sweeps = 40;
+  ea.tol = 1e-15;
+  ea.lumped = c.d_lumped;
+  ea.margin = c.d_margin;
+  ea.fail = fail;
+  FCW_HIP(hipFuncSetAttribute((const void*)evs_lump_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shbytes));
+  evs_lump_kernel<<<(unsigned)c.n_cut_cand, kEvsThreads, shbytes, c.stream>>>(ea);
+  FCW_HIP(hipGetLastError());
+  std::vector<int32_t> hf(c.n_cut_cand), hav(c.n_cut_cand);
+  FCW_HIP(hipMemcpyAsync(hf.data(), fail, c.n_cut_cand * 4, hipMemcpyDeviceToHost, c.stream));
+  FCW_HIP(hipMemcpyAsync(hav.data(), c.d_all_void, c.n_cut_cand * 4, hipMemcpyDeviceToHost,
+                         c.stream));
+  FCW_HIP(hipFreeAsync(fail, c.stream));
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  for (int64_t i = 0; i < c.n_cut_cand; ++i) {
+    if (hf[i] && !hav[i]) {
+      set_error("eigenvalue stabilisation did not converge in cut cell %lld",
+                (long long)i);
+      return FCW_E_NOCONV;
+    }
+  }
+  return FCW_OK;
+}
+
+// --------------------------------------------------------------------------------
+// Reclassification, mass assembly, packing
+// --------------------------------------------------------------------------------
+
+__global__ void reclassify_kernel(const int32_t* cut_cells, const int32_t* all_void, int64_t n,
+                                  int8_t* cls, int32_t* info) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  if (all_void[q]) {
+    int cell = cut_cells[q];
+    cls[cell] = kClsOut;
+    info[cell] = kInfoOut;
+  }
+}
+
+struct MassArgs {
+  int dim, p;
+  int n[3], np[3];
+  int64_t nnodes;
+  const int32_t* info;
+  const double* lref;
+  const double* lumped;
+  double* mass;
+  double* invm64;
+};
+
+// diagonal mass per node: sum of the lumped element diagonals of the active cells
+// around it, adjacent cells taken in lexicographic order (z, y, x; lower first)
+__global__ void mass_kernel(MassArgs a) {
+  int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= a.nnodes) return;
+  int idx[3] = {0, 0, 0};
+  int64_t r = node;
+  for (int k = 0; k < a.dim; ++k) { idx[k] = (int)(r % a.np[k]); r /= a.np[k]; }
+  int cl[3], ch[3];
+  for (int k = 0; k < 3; ++k) {
+    if (k >= a.dim) { cl[k] = ch[k] = 0; continue; }
+    int i = idx[k];
+    int hi = i / a.p;
+    int lo = (i % a.p == 0) ? hi - 1 : hi;
+    if (hi > a.n[k] - 1) hi = a.n[k] - 1;
+    if (lo < 0) lo = 0;
+    cl[k] = lo;
+    ch[k] = hi;
+  }
+  const int np1 = a.p + 1;
+  int ns = 1;
+  for (int k = 0; k < a.dim; ++k) ns *= np1;
+  double m = 0.0;
+  for (int cz = cl[2]; cz <= ch[2]; ++cz)
+    for (int cy = cl[1]; cy <= ch[1]; ++cy)
+      for (int cx = cl[0]; cx <= ch[0]; ++cx) {
+        int64_t cell = cx + (int64_t)a.n[0] * (cy + (int64_t)a.n[1] * cz);
+        int inf = a.info[cell];
+        if (inf == kInfoOut) continue;
+        int loc = (idx[0] - cx * a.p);
+        if (a.dim > 1) loc += np1 * (idx[1] - cy * a.p);
+        if (a.dim > 2) loc += np1 * np1 * (idx[2] - cz * a.p);
+        m += (inf == kInfoUncut) ? a.lref[loc] : a.lumped[(int64_t)inf * ns + loc];
+      }
+  a.mass[node] = m;
+  a.invm64[node] = (m > 0.0) ? 1.0 / m : 0.0;
+}
+
+template <typename T>
+__global__ void cast_kernel(const double* in, T* out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+// packed upper triangle, column-major: entry (i, j), i <= j, at j (j + 1) / 2 + i
+template <typename T>
+__global__ void pack_upper_kernel(const double* k, T* out, int nl, int64_t ncut) {
+  const int64_t np = (int64_t)nl * (nl + 1) / 2;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= np * ncut) return;
+  int64_t q = g / np;
+  int lin = (int)(g % np);
+  int j = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= lin) ++j;
+  while (j * (j + 1) / 2 > lin) --j;
+  int i = lin - j * (j + 1) / 2;
+  out[g] = (T)k[q * nl * nl + (int64_t)i * nl + j];
+}
+
+fcw_status setup_reclassify(Ctx& c) {
+  if (c.n_cut_cand > 0) {
+    reclassify_kernel<<<(unsigned)((c.n_cut_cand + 255) / 256), 256, 0, c.stream>>>(
+        c.d_cut_cells, c.d_all_void, c.n_cut_cand, c.d_cls, c.d_info);
+    FCW_HIP(hipGetLastError());
+  }
+  std::vector<int8_t> cls(c.ncell_total);
+  FCW_HIP(hipMemcpyAsync(cls.data(), c.d_cls, cls.size(), hipMemcpyDeviceToHost, c.stream));
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  int64_t cnt[3] = {0, 0, 0};
+  for (int8_t k : cls) cnt[k]++;
+  c.n_out = cnt[kClsOut];
+  c.n_uncut = cnt[kClsUncut];
+  c.n_cut = cnt[kClsCut];
+  return FCW_OK;
+}
+
+fcw_status setup_mass_and_pack(Ctx& c) {
+  MassArgs ma{};
+  ma.dim = c.dim;
+  ma.p = c.p;
+  for (int k = 0; k < 3; ++k) { ma.n[k] = c.ncells[k]; ma.np[k] = c.npts[k]; }
+  ma.nnodes = c.nnodes;
+  ma.info = c.d_info;
+  ma.lref = c.d_lref;
+  ma.lumped = c.d_lumped;
+  ma.mass = c.d_mass;
+  ma.invm64 = c.d_invm64;
+  mass_kernel<<<(unsigned)((c.nnodes + 255) / 256), 256, 0, c.stream>>>(ma);
+  FCW_HIP(hipGetLastError());
+  const int64_t nl = c.n_loc;
+  const int64_t npk = nl * (nl + 1) / 2;
+  const unsigned gn = (unsigned)((c.nnodes + 255) / 256);
+  const unsigned gk = (unsigned)((nl * nl + 255) / 256);
+  const unsigned gp = (unsigned)((npk * c.n_cut_cand + 255) / 256);
+  if (c.precision == FCW_FP64) {
+    cast_kernel<double><<<gn, 256, 0, c.stream>>>(c.d_invm64, (double*)c.d_invm, c.nnodes);
+    cast_kernel<double><<<gk, 256, 0, c.stream>>>(c.d_kref, (double*)c.d_kref_s, nl * nl);
+    if (c.n_cut_cand > 0)
+      pack_upper_kernel<double><<<gp, 256, 0, c.stream>>>(c.d_kcut, (double*)c.d_kcut_s, (int)nl,
+                                                          c.n_cut_cand);
+  } else {
+    cast_kernel<float><<<gn, 256, 0, c.stream>>>(c.d_invm64, (float*)c.d_invm, c.nnodes);
+    cast_kernel<float><<<gk, 256, 0, c.stream>>>(c.d_kref, (float*)c.d_kref_s, nl * nl);
+    if (c.n_cut_cand > 0)
+      pack_upper_kernel<float><<<gp, 256, 0, c.stream>>>(c.d_kcut, (float*)c.d_kcut_s, (int)nl,
+                                                         c.n_cut_cand);
+  }
+  FCW_HIP(hipGetLastError());
+  return FCW_OK;
+}
+
+// --------------------------------------------------------------------------------
+// Point-source load vectors
+// --------------------------------------------------------------------------------
+
+struct SrcArgs {
+  Grid g;
+  int p, ncomp;
+  double rho;
+  const RefTables* tab;
+  int nsrc;
+  const fcw_source* in;
+  SourceDev* out;
+};
+
+template <int NP1>
+__global__ void source_kernel(SrcArgs a) {
+#pragma clang fp contract(off)
+  const int s = blockIdx.x;
+  if (s >= a.nsrc || threadIdx.x != 0) return;
+  const fcw_source& in = a.in[s];
+  SourceDev& o = a.out[s];
+  double L[3][NP1], dL[3][NP1];
+  for (int k = 0; k < 3; ++k) o.cell[k] = 0;
+  for (int k = 0; k < a.g.dim; ++k) {
+    int i = (int)floor((in.x[k] - a.g.lo[k]) / a.g.h);
+    i = max(0, min(i, a.g.n[k] - 1));
+    o.cell[k] = i;
+    double clo = a.g.lo[k] + (double)i * a.g.h;
+    double xi = 2.0 * (in.x[k] - clo) / a.g.h - 1.0;
+    lagrange_1d<NP1>(a.tab->gll_x, xi, L[k], dL[k]);
+  }
+  int ns = 1;
+  for (int k = 0; k < a.g.dim; ++k) ns *= NP1;
+  for (int loc = 0; loc < ns; ++loc) {
+    double N = 1.0;
+    int r = loc;
+    for (int k = 0; k < a.g.dim; ++k) { N *= L[k][r % NP1]; r /= NP1; }
+    for (int cc = 0; cc < a.ncomp; ++cc) {
+      double dc = (a.ncomp == 1) ? 1.0 : in.dir[cc];
+      o.b[cc * ns + loc] = a.rho * in.amp * dc * N;
+    }
+  }
+  o.f0 = in.f0;
+}
+
+constexpr int kMaxSrc = 64;
+
+fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src) {
+  if (nrhs > kMaxSrc) {
+    set_error("at most %d right-hand sides per call (got %d)", kMaxSrc, nrhs);
+    return FCW_E_ARG;
+  }
+  if (!c.d_src) {
+    // SourceDev[kMaxSrc] followed by a staging copy of the caller's fcw_source[kMaxSrc]
+    FCW_HIP(hipMalloc((void**)&c.d_src, kMaxSrc * (sizeof(SourceDev) + sizeof(fcw_source))));
+    c.src_cap = kMaxSrc;
+    c.footprint += kMaxSrc * (sizeof(SourceDev) + sizeof(fcw_source));
+  }
+  fcw_source* staged = (fcw_source*)(c.d_src + kMaxSrc);
+  FCW_HIP(hipMemcpyAsync(staged, src, nrhs * sizeof(fcw_source), hipMemcpyHostToDevice,
+                         c.stream));
+  SrcArgs sa{};
+  sa.g = make_grid(c);
+  sa.p = c.p;
+  sa.ncomp = c.ncomp;
+  sa.rho = c.rho;
+  sa.tab = c.d_tab;
+  sa.nsrc = nrhs;
+  sa.in = staged;
+  sa.out = c.d_src;
+  switch (c.p + 1) {
+    case 2: source_kernel<2><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    case 3: source_kernel<3><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    case 4: source_kernel<4><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    case 5: source_kernel<5><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    case 6: source_kernel<6><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    case 7: source_kernel<7><<<nrhs, 64, 0, c.stream>>>(sa); break;
+    default:
+      set_error("sources not built for p=%d", c.p);
+      return FCW_E_UNSUPPORTED;
+  }
+  FCW_HIP(hipGetLastError());
+  // the staged host array must stay valid until the copy has run
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  return FCW_OK;
+}
+
+}  // namespace fcw

@@ -1,0 +1,198 @@
+"""ctypes binding of the fcw C ABI (include/fcw.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of libfcw.so.
+Device buffers are passed as raw pointers; anything with a ``data_ptr()`` method
+(a torch tensor on the GPU) is accepted as well.  Loading fails loudly when the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfcw.so")
+
+FCW_OK, FCW_E_ARG, FCW_E_NOMEM, FCW_E_DEVICE, FCW_E_STATE, FCW_E_NOCONV, FCW_E_UNSTABLE, \
+    FCW_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+FCW_FP64, FCW_FP32, FCW_BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FCW_FP64, "fp32": FCW_FP32, "bf16": FCW_BF16}
+(ARR_CELL_CLASS, ARR_CUT_CELLS, ARR_K_REF, ARR_K_CUT, ARR_M_CUT, ARR_LUMPED_CUT, ARR_MASS,
+ ARR_EVS_MARGIN) = range(8)
+_ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
+
+# every entry point declared in include/fcw.h
+EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
+           "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
+           "fcw_export", "fcw_destroy", "fcw_last_error")
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("ncomp", C.c_int32), ("ncells", C.c_int32 * 3),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("p", C.c_int32),
+                ("tree_depth", C.c_int32), ("nvoids", C.c_int32),
+                ("void_center", C.POINTER(C.c_double)), ("void_radius", C.POINTER(C.c_double)),
+                ("alpha", C.c_double), ("rho", C.c_double), ("c", C.c_double), ("E", C.c_double),
+                ("nu", C.c_double), ("precision", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Source(C.Structure):
+    _fields_ = [("x", C.c_double * 3), ("dir", C.c_double * 3), ("f0", C.c_double),
+                ("amp", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("ndof", C.c_int64), ("nnodes", C.c_int64), ("ncells", C.c_int64),
+                ("n_cut", C.c_int64), ("n_uncut", C.c_int64), ("n_out", C.c_int64),
+                ("n_loc", C.c_int32), ("precision", C.c_int32), ("footprint_bytes", C.c_int64),
+                ("dt_crit", C.c_double), ("min_evs_margin", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FcwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fcw status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libfcw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_2501_19013_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i32, f64 = C.c_void_p, C.c_int32, C.c_double
+    lib.fcw_assemble_cells.argtypes = [C.POINTER(ProblemDesc), C.POINTER(vp)]
+    lib.fcw_stabilize_cut_cells.argtypes = [vp, f64, f64]
+    lib.fcw_critical_dt.argtypes = [vp, i32, f64, C.POINTER(f64)]
+    lib.fcw_step_explicit.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
+    lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Source), f64, f64, i32]
+    lib.fcw_apply_stiffness.argtypes = [vp, i32, vp, vp]
+    lib.fcw_query.argtypes = [vp, C.POINTER(Info)]
+    lib.fcw_export.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.fcw_destroy.argtypes = [vp]
+    lib.fcw_destroy.restype = None
+    lib.fcw_last_error.argtypes = []
+    lib.fcw_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("fcw_destroy", "fcw_last_error"):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != FCW_OK:
+        raise FcwError(status, load().fcw_last_error().decode())
+    return status
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _sources(srcs):
+    if not srcs:
+        return None
+    arr = (Source * len(srcs))()
+    for i, s in enumerate(srcs):
+        x = tuple(s["x"]) + (0.0,) * (3 - len(s["x"]))
+        d = tuple(s.get("dir", (1.0, 0.0, 0.0)))
+        d = d + (0.0,) * (3 - len(d))
+        arr[i].x[:] = x
+        arr[i].dir[:] = d[:3]
+        arr[i].f0 = float(s.get("f0", 10.0))
+        arr[i].amp = float(s.get("amp", 1.0))
+    return arr
+
+
+def assemble_cells(cfg, precision="fp64", stream=None):
+    """fcw_assemble_cells from a configuration dict (keys as in ``workloads``)."""
+    lib = load()
+    dim = int(cfg["dim"])
+    desc = ProblemDesc()
+    desc.dim = dim
+    desc.ncomp = int(cfg.get("ncomp", 1))
+    nc = list(cfg["ncells"]) + [1] * (3 - dim)
+    desc.ncells[:] = [int(v) for v in nc]
+    desc.lo[:] = list(cfg["lo"]) + [0.0] * (3 - dim)
+    desc.hi[:] = list(cfg["hi"]) + [0.0] * (3 - dim)
+    desc.p = int(cfg["p"])
+    desc.tree_depth = int(cfg.get("tree_depth", 3))
+    vc = np.ascontiguousarray(cfg["void_center"], dtype=np.float64).reshape(-1)
+    vr = np.ascontiguousarray(cfg["void_radius"], dtype=np.float64).reshape(-1)
+    desc.nvoids = len(vr)
+    desc.void_center = vc.ctypes.data_as(C.POINTER(C.c_double))
+    desc.void_radius = vr.ctypes.data_as(C.POINTER(C.c_double))
+    desc.alpha = float(cfg.get("alpha", 1e-12))
+    desc.rho = float(cfg.get("rho", 1.0))
+    desc.c = float(cfg.get("c", 1.0))
+    desc.E = float(cfg.get("E", 1.0))
+    desc.nu = float(cfg.get("nu", 0.3))
+    desc.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    desc.stream = stream
+    ctx = C.c_void_p()
+    _check(lib.fcw_assemble_cells(C.byref(desc), C.byref(ctx)))
+    return ctx
+
+
+def stabilize_cut_cells(ctx, eps, f_lambda):
+    _check(load().fcw_stabilize_cut_cells(ctx, float(eps), float(f_lambda)))
+
+
+def critical_dt(ctx, max_iter=400, rtol=1e-10):
+    out = C.c_double()
+    _check(load().fcw_critical_dt(ctx, int(max_iter), float(rtol), C.byref(out)))
+    return out.value
+
+
+def step_explicit(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):
+    srcs = _sources(sources)
+    _check(load().fcw_step_explicit(ctx, int(nrhs), _ptr(u), _ptr(d), srcs, float(t0),
+                                    float(dt), int(nsteps), int(start)))
+
+
+def step_imex(ctx, nrhs, u, v_c, a_c, sources, t0, dt, nsteps):
+    srcs = _sources(sources)
+    _check(load().fcw_step_imex(ctx, int(nrhs), _ptr(u), _ptr(v_c), _ptr(a_c), srcs,
+                                float(t0), float(dt), int(nsteps)))
+
+
+def apply_stiffness(ctx, nrhs, u, r):
+    _check(load().fcw_apply_stiffness(ctx, int(nrhs), _ptr(u), _ptr(r)))
+
+
+def query(ctx):
+    info = Info()
+    _check(load().fcw_query(ctx, C.byref(info)))
+    return info.as_dict()
+
+
+def export(ctx, which):
+    lib = load()
+    n = C.c_int64()
+    _check(lib.fcw_export(ctx, int(which), None, 0, C.byref(n)))
+    out = np.empty(n.value, dtype=_ARR_DTYPE.get(which, np.float64))
+    _check(lib.fcw_export(ctx, int(which), out.ctypes.data, n.value, C.byref(n)))
+    return out
+
+
+def destroy(ctx):
+    if ctx:
+        load().fcw_destroy(ctx)
+
+
+def last_error():
+    return load().fcw_last_error().decode()

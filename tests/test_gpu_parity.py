@@ -1,0 +1,257 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: the FP64 path computes the same finite recurrence as the oracle with a
+different summation order, so its relative L2 error stays at a few hundred ulps
+(1e-10 is the bar); the FP32 path is held to 1e-4 relative L2 (the bar of the FP32
+form), measured over the active DOFs at every checkpoint.  Integer results (cell
+classes, cut-cell lists) are compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import geometry, problem, timestep
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(cfg, precision):
+    from paper_2501_19013_amd.solver import Solver
+    return Solver(cfg, precision=precision)
+
+
+def _oracle(cfg):
+    return problem.build(problem.Problem.from_config(cfg))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def c1():
+    cfg = workloads.config("c1")
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    return cfg, disc, dt
+
+
+def _setup_parity(cfg, disc, s):
+    from paper_2501_19013_amd import fcw
+    cls = s.export(fcw.ARR_CELL_CLASS)
+    np.testing.assert_array_equal(cls, disc.cls)
+    cand = s.export(fcw.ARR_CUT_CELLS)
+    kept = cand[cls[cand] == geometry.CUT]
+    np.testing.assert_array_equal(kept, disc.cut_cells)
+    nl, ns = disc.prob.n_loc, disc.prob.n_s
+    kref = s.export(fcw.ARR_K_REF).reshape(nl, nl)
+    np.testing.assert_allclose(kref, disc.K_ref, atol=1e-13 * np.abs(disc.K_ref).max())
+    keep = cls[cand] == geometry.CUT
+    kc = s.export(fcw.ARR_K_CUT).reshape(-1, nl, nl)[keep]
+    mc = s.export(fcw.ARR_M_CUT).reshape(-1, ns, ns)[keep]
+    lc = s.export(fcw.ARR_LUMPED_CUT).reshape(-1, ns)[keep]
+    for q in range(len(kept)):
+        sc = np.abs(disc.K_cut[q]).max()
+        assert np.abs(kc[q] - disc.K_cut[q]).max() <= 1e-12 * sc, q
+        assert np.abs(mc[q] - disc.Mo_cut[q]).max() <= 1e-13 * np.abs(disc.Mo_cut[q]).max(), q
+        assert np.abs(lc[q] - disc.lumped_cut[q]).max() <= 1e-10 * np.abs(disc.lumped_cut[q]).max(), q
+    mass = s.export(fcw.ARR_MASS)
+    np.testing.assert_allclose(mass, disc.mass, rtol=1e-10, atol=1e-14 * disc.mass.max())
+
+
+def test_c1_setup_parity(c1):
+    cfg, disc, _ = c1
+    s = _solver(cfg, "fp64")
+    _setup_parity(cfg, disc, s)
+    info = s.info
+    assert info["n_cut"] == len(disc.cut_cells) == 28
+    assert info["n_out"] == 32 and info["n_uncut"] == 196
+    # the eigenvalue split is decided far from rounding in every cut cell
+    assert info["min_evs_margin"] > 1e-10
+    assert abs(info["min_evs_margin"] - disc.evs_margin.min()) < 1e-8
+    s.close()
+
+
+def test_c1_critical_dt(c1):
+    cfg, disc, _ = c1
+    s = _solver(cfg, "fp64")
+    dtc = s.critical_dt(max_iter=2000, rtol=1e-13)
+    ref = timestep.critical_dt(disc)
+    assert abs(dtc - ref) <= 1e-8 * ref
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c1_stiffness_action(c1, precision):
+    import torch
+    cfg, disc, _ = c1
+    s = _solver(cfg, precision)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((2, disc.prob.ndof)) * (disc.mass > 0)
+    ug = torch.tensor(u, dtype=s.dtype, device="cuda")
+    r = s.apply_stiffness(ug).double().cpu().numpy()
+    for k in range(2):
+        ref = problem.apply_K(disc, u[k])
+        tol = 1e-13 if precision == "fp64" else 2e-6
+        assert np.abs(r[k] - ref).max() <= tol * np.abs(ref).max()
+    s.close()
+
+
+def _run_gpu(s, cfg, dt, nsteps, chunks):
+    """Run in chunks (t0 advances), returning u after each chunk end."""
+    import torch
+    u = s.zeros(1)
+    d = s.zeros(1)
+    out = {}
+    k = 0
+    for n in chunks:
+        s.step(u, d, cfg["sources"], dt, n, t0=k * dt, start=(k == 0))
+        k += n
+        torch.cuda.synchronize()
+        out[k] = u[0].double().cpu().numpy().copy()
+    assert k == nsteps
+    return out
+
+
+def test_c1_fp64_run_parity(c1):
+    cfg, disc, dt = c1
+    s = _solver(cfg, "fp64")
+    chunks = [1, 99, 100, 101, 199]   # odd and even chunk lengths, the start step alone
+    got = _run_gpu(s, cfg, dt, 500, chunks)
+    ref = timestep.cdm(disc, dt, 500, sources=cfg["sources"], checkpoints=tuple(got))
+    for k, u in got.items():
+        e = rel_l2(u, ref["snapshots"][k])
+        assert e <= 1e-10, (k, e)
+    s.close()
+
+
+def test_c1_fp32_run_parity(c1):
+    cfg, disc, dt = c1
+    s = _solver(cfg, "fp32")
+    got = _run_gpu(s, cfg, dt, 500, [100] * 5)
+    ref = timestep.cdm(disc, dt, 500, sources=cfg["sources"], checkpoints=tuple(got))
+    for k, u in got.items():
+        e = rel_l2(u, ref["snapshots"][k])
+        assert e <= 1e-4, (k, e)
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    # the c2 void field (seed 2, 40 circles, r in [0.01, 0.05]) on 64x64 cells, p = 4:
+    # several tiles in each direction and a ragged tail in neither; 400 steps
+    cfg = workloads.config("c2")
+    cfg["ncells"] = (64, 64)
+    cfg["nsteps"] = 400
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    return cfg, disc, dt
+
+
+def test_c2_small_setup_parity(c2_small):
+    cfg, disc, _ = c2_small
+    s = _solver(cfg, "fp64")
+    _setup_parity(cfg, disc, s)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_c2_small_run_parity(c2_small, precision, tol):
+    cfg, disc, dt = c2_small
+    s = _solver(cfg, precision)
+    got = _run_gpu(s, cfg, dt, 400, [200, 200])
+    ref = timestep.cdm(disc, dt, 400, sources=cfg["sources"], checkpoints=tuple(got))
+    for k, u in got.items():
+        e = rel_l2(u, ref["snapshots"][k])
+        assert e <= tol, (k, e)
+    s.close()
+
+
+def test_ragged_grid_and_multi_rhs():
+    # non-square grid whose sizes are not multiples of any tile edge, three sources
+    # as three right-hand sides; each must equal its own oracle run
+    import torch
+    cfg = workloads.config("c2")
+    h = 1.0 / 48
+    cfg.update(ncells=(37, 23), hi=(37 * h, 23 * h), p=3, nsteps=150)
+    cc, rr = workloads.random_circles(seed=12, count=8, rmin=0.03, rmax=0.08,
+                                      hi=23 * h, keep_clear=((0.1, 0.1), (0.6, 0.3), (0.3, 0.4)))
+    cfg["void_center"], cfg["void_radius"] = cc, rr
+    srcs = [dict(x=(0.1, 0.1), f0=10.0, amp=1.0), dict(x=(0.6, 0.3), f0=12.0, amp=0.5),
+            dict(x=(0.3, 0.4), f0=8.0, amp=2.0)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    for precision, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        s = _solver(cfg, precision)
+        _setup_parity(cfg, disc, s) if precision == "fp64" else None
+        u = s.zeros(3)
+        d = s.zeros(3)
+        s.step(u, d, srcs, dt, 150, t0=0.0, start=True)
+        torch.cuda.synchronize()
+        ug = u.double().cpu().numpy()
+        for r, src in enumerate(srcs):
+            ref = timestep.cdm(disc, dt, 150, sources=[src])["u"]
+            assert rel_l2(ug[r], ref) <= tol, (precision, r)
+        s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_elastic_3d_parity(precision, tol):
+    cfg = workloads.scaled_config(3, 6, 2, seed=3, ncomp=3, porosity=0.2, nsteps=120)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    s = _solver(cfg, precision)
+    if precision == "fp64":
+        _setup_parity(cfg, disc, s)
+    got = _run_gpu(s, cfg, dt, 120, [60, 60])
+    ref = timestep.cdm(disc, dt, 120, sources=cfg["sources"], checkpoints=tuple(got))
+    for k, u in got.items():
+        assert rel_l2(u, ref["snapshots"][k]) <= tol, k
+    s.close()
+
+
+def test_scalar_3d_parity():
+    cfg = workloads.scaled_config(3, 8, 3, seed=4, porosity=0.15, nsteps=80)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), f0=10.0, amp=1.0)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    s = _solver(cfg, "fp64")
+    _setup_parity(cfg, disc, s)
+    got = _run_gpu(s, cfg, dt, 80, [80])
+    ref = timestep.cdm(disc, dt, 80, sources=cfg["sources"])["u"]
+    assert rel_l2(got[80], ref) <= 1e-10
+    s.close()
+
+
+def test_error_paths():
+    from paper_2501_19013_amd import fcw
+    cfg = workloads.config("c1")
+    s = _solver(cfg, "fp64")
+    u, d = s.zeros(1), s.zeros(1)
+    with pytest.raises(fcw.FcwError) as e:     # source inside the hole
+        s.step(u, d, [dict(x=(0.5, 0.5), f0=10.0)], 1e-3, 3, start=True)
+    assert e.value.status == fcw.FCW_E_ARG
+    with pytest.raises(fcw.FcwError) as e:     # outside the box
+        s.step(u, d, [dict(x=(1.5, 0.5), f0=10.0)], 1e-3, 3, start=True)
+    assert e.value.status == fcw.FCW_E_ARG
+    with pytest.raises(fcw.FcwError) as e:
+        fcw.step_imex(s.ctx, 1, u, d, d, None, 0.0, 1e-3, 1)
+    assert e.value.status == fcw.FCW_E_UNSUPPORTED
+    s.step(u, d, None, 1e-3, 0)               # zero steps is a no-op
+    s.close()
+
+
+def test_bitwise_reproducible(c1):
+    import torch
+    cfg, _, dt = c1
+    outs = []
+    for _ in range(2):
+        s = _solver(cfg, "fp32")
+        u, d = s.run(cfg["sources"], dt, 300)
+        torch.cuda.synchronize()
+        outs.append(u.cpu().numpy().copy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
