@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the explicit spectral-cell wave step on one MI355X.
+
+Workload: 2-D scalar wave on [0,1]^2 with 40 random circular voids (radii 0.01-0.05,
+seed 2), 512 x 512 cells, p = 4 GLL (about 4.2 M DOF), Ricker point source f0 = 10 at
+(0.1, 0.1), dt = 0.9 dt_crit, eps = 1e-4 eigenvalue stabilisation, FP64 setup; the
+stiffness product and the state run in FP32 (matrix cores) and, for reference, in FP64.
+
+A step is one central-difference step of the whole hot path (uncut MFMA contraction,
+cut-cell stream, gather, lumped-mass update) over one right-hand side.  `value` is
+DOF-updates/s of the FP32 path: active DOFs x steps / stepping time, measured with HIP
+events on the solver's stream around exactly --steps steps (inputs resident in HBM).
+The FP32 result is compared with the FP64 GPU path after the same steps (relative L2
+over all DOFs); the FP64 path itself is held to the FP64 oracle by the test suite.
+
+Roofline: algorithmic bytes per step B = 3 s N_dof + s N_cutadj + N_cut (n_loc(n_loc+1)/2
+s + 4) + N_cells / 8 (read u_k and u_{k-1}, write u_{k+1}; the non-analytic inverse
+masses next to cut cells; the packed cut-cell matrices; one class bit per cell), divided
+by the average duration of one step kernel, against 8 TB/s of HBM3E.
+
+cpu_baseline: the FP64 numpy oracle (single BLAS thread) stepping the same full-size
+problem for a bounded number of steps on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cfg, info, cls, s_state):
+    """Per-step algorithmic bytes (see module docstring)."""
+    p, dim = cfg["p"], cfg["dim"]
+    ncells = np.array(cfg["ncells"])
+    nl = info["n_loc"]
+    n_dof = info["ndof"]
+    # nodes touched by at least one cut cell
+    grid = cls.reshape(tuple(ncells[::-1]))
+    cut = (grid == 2)
+    npts = ncells * p + 1
+    mark = np.zeros(tuple(npts[::-1]), dtype=bool)
+    if dim == 2:
+        cy, cx = np.nonzero(cut)
+        for a in range(p + 1):
+            for b in range(p + 1):
+                mark[cy * p + a, cx * p + b] = True
+    else:
+        cz, cy, cx = np.nonzero(cut)
+        for a in range(p + 1):
+            for b in range(p + 1):
+                for c in range(p + 1):
+                    mark[cz * p + a, cy * p + b, cx * p + c] = True
+    n_cutadj = int(mark.sum()) * cfg.get("ncomp", 1)
+    n_cut = info["n_cut"]
+    return (3 * s_state * n_dof + s_state * n_cutadj + n_cut * (nl * (nl + 1) // 2 * s_state + 4)
+            + int(np.prod(ncells)) / 8.0)
+
+
+def run_gpu(cfg, precision, steps, warmup, dt=None):
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+
+    s = Solver(cfg, precision=precision, device="cuda:0")
+    if dt is None:
+        dt = 0.9 * s.critical_dt(max_iter=600, rtol=1e-7)
+    src = cfg["sources"]
+    chosen, table = s.autotune(nrhs=1, nsteps=30)
+    print(f"[bench] {precision} autotune: " + ", ".join(
+        f"{t['tile']}:{t['us_per_step']:.1f}us" for t in table) + f" -> {table[chosen]['tile']}",
+        file=sys.stderr, flush=True)
+    u, d = s.zeros(1), s.zeros(1)
+    if warmup:
+        s.step(u, d, src, dt, warmup, t0=0.0, start=True)
+    stream = s.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(u, d, src, dt, steps, t0=warmup * dt, start=(warmup == 0))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cls = s.export(fcw.ARR_CELL_CLASS)
+    mass = s.export(fcw.ARR_MASS)
+    info = dict(s.info)
+    out = u[0].double().cpu().numpy()
+    s.close()
+    return dict(ms=ms, dt=dt, info=info, cls=cls, active=int((mass > 0).sum()) * cfg.get("ncomp", 1),
+                u=out, tile=table[chosen]["tile"])
+
+
+def cpu_baseline(cfg, dt, nsteps):
+    """Time the FP64 oracle stepping the same problem for ``nsteps`` steps."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import problem, timestep
+    with threadpool_limits(limits=1):
+        disc = problem.build(problem.Problem.from_config(cfg))
+        active = int((disc.mass > 0).sum()) * cfg.get("ncomp", 1)
+        t = time.perf_counter()
+        timestep.cdm(disc, dt, nsteps, sources=cfg["sources"])
+        el = time.perf_counter() - t
+    return dict(value=active * nsteps / el, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=f"{nsteps} steps of the full 512x512 p=4 problem (setup excluded), "
+                       f"FP64 numpy, 1 thread, {el:.1f} s")
+
+
+def calibrate_copy(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1800)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "domain decomposition is a design, not a build, in this repository",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import workloads
+    cfg = workloads.config("c2")
+    r32 = run_gpu(cfg, "fp32", args.steps, args.warmup)
+    print(f"[bench] fp32: {args.steps} steps in {r32['ms']:.2f} ms", file=sys.stderr, flush=True)
+    res = dict(metric="DOF-updates/s at <=1e-4 rel L2 vs FP64 (FP32 path)",
+               unit="DOF-updates/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic")
+    ms_step = r32["ms"] / args.steps
+    res["value"] = r32["active"] * args.steps / (r32["ms"] * 1e-3)
+    res["ms_per_step"] = ms_step
+    info = r32["info"]
+    B = algorithmic_bytes(cfg, info, r32["cls"], 4)
+    achieved = B / (ms_step * 1e-3) / 1e9
+    res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=achieved / HBM_PEAK_GBS, traffic=None,
+                           kernel="fcw::tile_kernel<float,2,4,1,%d,%d,%d,0>" % tuple(r32["tile"]),
+                           algorithmic_bytes_per_step=B)
+    res["config"] = dict(workload="c2: 2-D scalar wave, [0,1]^2, 40 random circular voids "
+                                  "(r 0.01-0.05, seed 2), 512x512 cells, p=4 GLL, FP32 step, "
+                                  "FP64 setup, Ricker f0=10 at (0.1,0.1), dt=0.9 dt_crit",
+                         ndof=info["ndof"], active_dof=r32["active"], n_cut=info["n_cut"],
+                         n_uncut=info["n_uncut"], n_out=info["n_out"], dt=r32["dt"],
+                         dt_crit=info["dt_crit"], total_steps=args.warmup + args.steps)
+    if not args.no_fp64:
+        r64 = run_gpu(cfg, "fp64", args.steps, args.warmup, dt=r32["dt"])
+        print(f"[bench] fp64: {args.steps} steps in {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
+        e = float(np.linalg.norm(r32["u"] - r64["u"]) / np.linalg.norm(r64["u"]))
+        v64 = r64["active"] * args.steps / (r64["ms"] * 1e-3)
+        res["fp64_gpu"] = dict(value=v64, ms_per_step=r64["ms"] / args.steps)
+        res["speedup_vs_fp64_gpu"] = res["value"] / v64
+        res["rel_l2_vs_fp64"] = e
+    res["p99_latency_s"] = None
+    if not args.no_cpu:
+        cb = cpu_baseline(cfg, r32["dt"], args.cpu_steps)
+        res["cpu_baseline"] = cb
+        print(f"[bench] cpu baseline: {cb['sample']}", file=sys.stderr, flush=True)
+    if args.calib:
+        calibrate_copy()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -121,6 +121,21 @@ fcw_status fcw_step_explicit(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
                              const fcw_source* src, double t0, double dt,
                              int32_t nsteps, int32_t start);
 
+/* Autotuner of the step kernel: times every compiled tile configuration for this
+ * problem kind on scratch state (nrhs right-hand sides, nsteps steps each, F = 0) and
+ * keeps the fastest for later fcw_step_explicit calls.  *chosen (may be NULL)
+ * receives its index.  Synchronises; the caller's state is not touched. */
+fcw_status fcw_autotune(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, int32_t* chosen);
+
+/* Tile configuration i of this problem kind: cells per tile (x, y, z) and its time per
+ * step in microseconds from the last fcw_autotune (0 if not timed); *count receives the
+ * number of configurations.  FCW_E_ARG when i is out of range (count still set). */
+fcw_status fcw_tile_config(const fcw_ctx* ctx, int32_t i, int32_t tile[3], double* us_per_step,
+                           int32_t* count);
+
+/* Use tile configuration i (as listed by fcw_tile_config) for later steps. */
+fcw_status fcw_select_tile(fcw_ctx* ctx, int32_t i);
+
 /* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
 fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,
                          const fcw_source* src, double t0, double dt, int32_t nsteps);

@@ -310,6 +310,96 @@ fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const f
   return st;
 }
 
+fcw_status fcw_autotune(fcw_ctx* c, int32_t nrhs, int32_t nsteps, int32_t* chosen) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > 64 || nsteps < 1) {
+    set_error("need 1 <= nrhs <= 64 and nsteps >= 1");
+    return FCW_E_ARG;
+  }
+  const int n = tile_candidates(*c, -1, nullptr);
+  const size_t bytes = (size_t)nrhs * c->ndof * c->state_bytes();
+  void *ua = nullptr, *ub = nullptr, *dd = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (ua) (void)hipFree(ua);
+    if (ub) (void)hipFree(ub);
+    if (dd) (void)hipFree(dd);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&ua, bytes) != hipSuccess || hipMalloc(&ub, bytes) != hipSuccess ||
+      hipMalloc(&dd, bytes) != hipSuccess) {
+    cleanup();
+    set_error("autotune scratch allocation failed");
+    return FCW_E_NOMEM;
+  }
+  if (hipMemsetAsync(ua, 0, bytes, c->stream) != hipSuccess ||
+      hipMemsetAsync(dd, 0, bytes, c->stream) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return hip_fail(hipGetLastError(), "autotune setup");
+  }
+  const SourceDev* saved = c->d_src;
+  c->d_src = nullptr;
+  c->tune_us.assign(n, 0.0);
+  int best = 0;
+  for (int i = 0; i < n && st == FCW_OK; ++i) {
+    for (int w = 0; w < 2 && st == FCW_OK; ++w)
+      st = launch_step_with(*c, i, nrhs, ua, ub, dd, 0.0, 1e-6, 0);
+    (void)hipEventRecord(e0, c->stream);
+    for (int j = 0; j < nsteps && st == FCW_OK; ++j)
+      st = launch_step_with(*c, i, nrhs, (j & 1) ? ub : ua, (j & 1) ? ua : ub, dd, 0.0, 1e-6, 0);
+    (void)hipEventRecord(e1, c->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      st = hip_fail(hipGetLastError(), "autotune timing");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c->tune_us[i] = 1000.0 * ms / nsteps;
+    if (c->tune_us[i] < c->tune_us[best]) best = i;
+  }
+  c->d_src = const_cast<SourceDev*>(saved);
+  cleanup();
+  if (st) return st;
+  c->tile_choice = best;
+  if (chosen) *chosen = best;
+  return FCW_OK;
+}
+
+fcw_status fcw_tile_config(const fcw_ctx* c, int32_t i, int32_t tile[3], double* us_per_step,
+                           int32_t* count) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  int t[3] = {0, 0, 0};
+  const int n = tile_candidates(*c, i, t);
+  if (count) *count = n;
+  if (i < 0 || i >= n) {
+    set_error("tile configuration %d out of range [0, %d)", i, n);
+    return FCW_E_ARG;
+  }
+  if (tile)
+    for (int k = 0; k < 3; ++k) tile[k] = t[k];
+  if (us_per_step) *us_per_step = (i < (int)c->tune_us.size()) ? c->tune_us[i] : 0.0;
+  return FCW_OK;
+}
+
+fcw_status fcw_select_tile(fcw_ctx* c, int32_t i) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  const int n = tile_candidates(*c, -1, nullptr);
+  if (i < 0 || i >= n) {
+    set_error("tile configuration %d out of range [0, %d)", i, n);
+    return FCW_E_ARG;
+  }
+  c->tile_choice = i;
+  return FCW_OK;
+}
+
 fcw_status fcw_step_imex(fcw_ctx* c, int32_t, void*, void*, void*, const fcw_source*, double,
                          double, int32_t) {
   g_err.clear();

@@ -44,6 +44,8 @@ struct Ctx {
   int n_s = 0, n_loc = 0;
   hipStream_t stream = nullptr;
   int state = 0;  // 1 assembled, 2 stabilised
+  int tile_choice = 0;             // step tile configuration (autotuned)
+  std::vector<double> tune_us;     // us per step of each configuration, last autotune
   bool poisoned = false;
   std::vector<double> void_c, void_r;  // host copies
   int nvoids = 0;
@@ -113,6 +115,9 @@ bool step_supported(const Ctx& c);
 fcw_status launch_step(Ctx& c, int nrhs, const void* u_in, void* u_out, void* d,
                        double t, double dt, int start);
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);
+fcw_status launch_step_with(Ctx& c, int choice, int nrhs, const void* u_in, void* u_out,
+                            void* d, double t, double dt, int start);
+int tile_candidates(const Ctx& c, int i, int tile[3]);
 fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
 // lanczos.hip
 fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax);

@@ -21,61 +21,16 @@
 //    neighbouring tiles, so halo rows are shared through that XCD's L2).
 #include <cmath>
 
-#include "common.h"
+#include "step_common.h"
 
 namespace fcw {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mma;
-// Lane layouts (16x16x4, one block): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
-// the output D[i][j] sits in lane j + 16 * (i / 4), item i % 4 for f32 and in lane
-// j + 16 * (i % 4), item i / 4 for f64.
-template <>
-struct Mma<float> {
-  using acc = f32x4;
-  __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
-  __device__ static inline acc mma(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <>
-struct Mma<double> {
-  using acc = f64x4;
-  __device__ static inline int row(int lk, int r) { return 4 * r + lk; }
-  __device__ static inline acc mma(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-
-enum { kModeStep = 0, kModeApply = 1, kModeLanczos = 2 };
-
-template <typename T>
-struct StepArgs {
-  const T* u_in;
-  T* u_out;
-  T* d;
-  const T* invm;
-  const double* invm64;
-  const int32_t* info;
-  const T* kref;
-  const T* kcut;
-  int n[3], np[3], ntile[3];
-  int ntiles, chunk;
-  int64_t nnodes, ndof;
-  T dt2;
-  int start;
-  const SourceDev* src;
-  double t;
-};
-
-__device__ static inline double ricker(double t, double f0) {
-  const double pi = 3.14159265358979323846;
-  const double ts = 2.0 * sqrt(6.0) / (pi * f0);
-  const double q = pi * f0 * (t - ts);
-  return (1.0 - 2.0 * q * q) * exp(-q * q);
+// One wave's 64 consecutive dwords, global -> LDS without passing through registers
+// (gfx950 global_load_lds_dword: lane l lands at lds_base + 4 l).
+__device__ static inline void load_dword_to_lds(const void* gsrc, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_wave_base, 4, 0,
+                                   0);
 }
 
 template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE>
@@ -99,8 +54,18 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   // otherwise stage them in LDS when small enough, else read them through the caches
   constexpr bool ALDS = !AREG && (NMB * 16 * KW * (int)sizeof(T) <= 48 * 1024);
   constexpr int NB = (NRC + 15) / 16;
+  // owned node box of a tile (at most; edge tiles own one more node row)
+  constexpr int OX = TX * P + 1;
+  constexpr int OY = (DIM >= 2) ? TY * P + 1 : 1;
+  constexpr int OZ = (DIM == 3) ? TZ * P + 1 : 1;
+  constexpr int NO = (OX * OY * OZ + 255) / 256;  // owned nodes per thread
+  constexpr int NUV = NCOMP * NRN;                // staged node values
+  constexpr int NUL = (NUV + 255) / 256;          // ... per thread
+  constexpr int NCI = (NRC + 255) / 256;          // staged cell infos per thread
+  // direct global->LDS staging of dword node values (the Lanczos operator scales them)
+  constexpr bool DIRECT = (sizeof(T) == 4) && (MODE != kModeLanczos);
 
-  __shared__ T u_s[NCOMP * NRN];
+  __shared__ T u_s[NUL * 256];
   __shared__ T y_s[NRC * NL];
   __shared__ T a_s[ALDS ? NMB * 16 * KW : 1];
   __shared__ int info_s[NRC];
@@ -112,6 +77,8 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   if (tile >= a.ntiles) return;
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lc = lane & 15, lk = lane >> 4;
   const int tx = tile % a.ntile[0];
   const int ty = (DIM >= 2) ? (tile / a.ntile[0]) % a.ntile[1] : 0;
   const int tz = (DIM == 3) ? tile / (a.ntile[0] * a.ntile[1]) : 0;
@@ -121,29 +88,87 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   const int rcz0 = (DIM == 3) ? cz0 - 1 : 0;
   const int rnx0 = rcx0 * P, rny0 = rcy0 * P, rnz0 = rcz0 * P;
   const T* uin = a.u_in + (int64_t)rhs * a.ndof;
+  const int ox0 = cx0 * P;
+  const int ox1 = (cx0 + TX >= a.n[0]) ? a.np[0] : (cx0 + TX) * P;
+  const int oy0 = (DIM >= 2) ? cy0 * P : 0;
+  const int oy1 = (DIM >= 2) ? ((cy0 + TY >= a.n[1]) ? a.np[1] : (cy0 + TY) * P) : 1;
+  const int oz0 = (DIM == 3) ? cz0 * P : 0;
+  const int oz1 = (DIM == 3) ? ((cz0 + TZ >= a.n[2]) ? a.np[2] : (cz0 + TZ) * P) : 1;
+  const int onx = ox1 - ox0, ony = oy1 - oy0, onz = oz1 - oz0;
 
-  // ---- stage cell info, node values, K_ref, local offsets ----
-  for (int c = tid; c < NRC; c += 256) {
+  // ---- issue every global load of the tile at once (all stay in flight) ----
+  T areg[AREG ? NMB : 1][AREG ? NKS : 1];
+  if (AREG) {
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+      for (int kk = 0; kk < NKS; ++kk) {
+        const int r = mb * 16 + lc, cc = 4 * kk + lk;
+        const T* kp = (MODE == kModeLanczos) ? a.kref : a.kref;
+        const T v = kp[min(r, NL - 1) * NL + min(cc, NL - 1)];
+        areg[AREG ? mb : 0][AREG ? kk : 0] = (r < NL && cc < NL) ? v : T(0);
+      }
+  }
+  int inf_r[NCI];
+#pragma unroll
+  for (int it = 0; it < NCI; ++it) {
+    const int c = tid + it * 256;
     const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
     const int gx = rcx0 + lx, gy = rcy0 + ly, gz = rcz0 + lz;
-    int v = kInfoOut;
-    if (gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 && gz < a.n[2])
-      v = a.info[gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz)];
-    info_s[c] = v;
+    const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
+                    gz < a.n[2];
+    const int64_t cell = in ? gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz) : 0;
+    const int v = a.info[cell];
+    inf_r[it] = in ? v : kInfoOut;
   }
-  for (int comp = 0; comp < NCOMP; ++comp) {
-    const T* uc = uin + (int64_t)comp * a.nnodes;
-    for (int i = tid; i < NRN; i += 256) {
-      const int lx = i % RNX, ly = (i / RNX) % RNY, lz = i / (RNX * RNY);
-      const int gx = rnx0 + lx, gy = rny0 + ly, gz = rnz0 + lz;
-      T v = T(0);
-      if (gx >= 0 && gx < a.np[0] && gy >= 0 && gy < a.np[1] && gz >= 0 && gz < a.np[2]) {
-        const int64_t node = gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz);
-        v = uc[node];
-        if (MODE == kModeLanczos) v = v * (T)sqrt(a.invm64[node]);
-      }
-      u_s[comp * NRN + i] = v;
+  // node values of the region; entries outside the grid belong only to cells outside
+  // the grid (never read), so their address is clamped to node 0 of the component
+  T u_r[DIRECT ? 1 : NUL];
+#pragma unroll
+  for (int it = 0; it < NUL; ++it) {
+    const int i = tid + it * 256;
+    const int comp = min(i / NRN, NCOMP - 1), j = i % NRN;
+    const int lx = j % RNX, ly = (j / RNX) % RNY, lz = j / (RNX * RNY);
+    const int gx = rnx0 + lx, gy = rny0 + ly, gz = rnz0 + lz;
+    const bool in = i < NUV && gx >= 0 && gx < a.np[0] && gy >= 0 && gy < a.np[1] && gz >= 0 &&
+                    gz < a.np[2];
+    const int64_t node = in ? gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz) : 0;
+    const T* src = uin + (int64_t)comp * a.nnodes + node;
+    if (DIRECT) {
+      load_dword_to_lds(src, &u_s[it * 256 + wave * 64]);
+    } else {
+      T v = *src;
+      if (MODE == kModeLanczos) v = v * (T)sqrt(a.invm64[node]);
+      u_r[DIRECT ? 0 : it] = in ? v : T(0);
     }
+  }
+  T d_r[MODE == kModeStep ? NO : 1][NCOMP];
+  T im_r[MODE == kModeStep ? NO : 1];
+  if (MODE == kModeStep) {
+#pragma unroll
+    for (int it = 0; it < NO; ++it) {
+      const int i = tid + it * 256;
+      const int ii = (MODE == kModeStep) ? it : 0;
+      const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
+      const bool own = i < OX * OY * OZ && lx < onx && ly < ony && lz < onz;
+      const int64_t node =
+          own ? (ox0 + lx) + (int64_t)a.np[0] * ((oy0 + ly) + (int64_t)a.np[1] * (oz0 + lz)) : 0;
+      im_r[ii] = a.invm[node];
+#pragma unroll
+      for (int comp = 0; comp < NCOMP; ++comp)
+        d_r[ii][comp] = a.d[(int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node];
+    }
+  }
+
+  // ---- stage cell info, node values, K_ref, local offsets in LDS ----
+#pragma unroll
+  for (int it = 0; it < NCI; ++it) {
+    const int c = tid + it * 256;
+    if (c < NRC) info_s[c] = inf_r[it];
+  }
+  if (!DIRECT) {
+#pragma unroll
+    for (int it = 0; it < NUL; ++it) u_s[tid + it * 256] = u_r[DIRECT ? 0 : it];
   }
   if (ALDS) {
     for (int i = tid; i < NMB * 16 * KW; i += 256) {
@@ -181,40 +206,34 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       }
     }
   }
+  if (DIRECT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  const int lane = tid & 63, wave = tid >> 6;
-  const int lc = lane & 15, lk = lane >> 4;
-
   // ---- uncut cells: batched K_ref contraction on the matrix cores ----
+  // Every non-cut cell of the region gets its row of y_s here: uncut cells their
+  // product, cells outside the domain zeros (their B operand is masked to zero).
   {
     int offk[NKS];
 #pragma unroll
     for (int kk = 0; kk < NKS; ++kk) offk[kk] = off_s[4 * kk + lk];
-    T areg[AREG ? NMB : 1][AREG ? NKS : 1];
-    if (AREG) {
-#pragma unroll
-      for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-        for (int kk = 0; kk < NKS; ++kk) {
-          const int r = mb * 16 + lc, cc = 4 * kk + lk;
-          areg[AREG ? mb : 0][AREG ? kk : 0] = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
-        }
-    }
     for (int b = wave; b < NB; b += 4) {
       const int c = b * 16 + lc;
-      const bool valid = (c < NRC) && (info_s[c] == kInfoUncut);
-      int base = 0;
-      if (c < NRC) {
-        const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
-        base = lx * P + RNX * (ly * P + RNY * (lz * P));
+      const int cs = min(c, NRC - 1);
+      const int inf = info_s[cs];
+      const bool valid = (c < NRC) && (inf == kInfoUncut);
+      const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
+      const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
+      T bv[NKS];
+#pragma unroll
+      for (int kk = 0; kk < NKS; ++kk) {
+        const T v = u_s[base + max(offk[kk], 0)];
+        bv[kk] = (valid && offk[kk] >= 0) ? v : T(0);
       }
       typename Mma<T>::acc acc[NMB];
 #pragma unroll
       for (int mb = 0; mb < NMB; ++mb) acc[mb] = typename Mma<T>::acc{0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < NKS; ++kk) {
-        const T bv = (valid && offk[kk] >= 0) ? u_s[base + offk[kk]] : T(0);
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
           T av;
@@ -226,10 +245,10 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
             const int r = mb * 16 + lc, cc = 4 * kk + lk;
             av = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
           }
-          acc[mb] = Mma<T>::mma(av, bv, acc[mb]);
+          acc[mb] = Mma<T>::mma(av, bv[kk], acc[mb]);
         }
       }
-      if (valid) {
+      if (c < NRC && inf < 0) {
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     int seen = 0;
     for (int c0 = 0; c0 < NRC; c0 += 64) {
       const int cc = c0 + lane;
-      const bool isc = (cc < NRC) && (info_s[cc] >= 0);
+      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
       unsigned long long mask = __ballot(isc);
       while (mask) {
         const int bit = __ffsll((long long)mask) - 1;
@@ -258,15 +277,29 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
         // the FP64 Lanczos operator reads the full FP64 setup matrices
         const T* K = a.kcut + (int64_t)q * (MODE == kModeLanczos ? NL * NL : NPK);
-        for (int i = lane; i < NL; i += 64) {
-          T y = T(0);
-          for (int j = 0; j < NL; ++j) {
+        constexpr int NR = (NL + 63) / 64;
+        // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
+        // small lumped masses of cut-cell nodes amplify any error in their sum
+        double y[NR];
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
+        // straight-line over the columns: every load of the cell is issued before use
+#pragma unroll
+        for (int j = 0; j < NL; ++j) {
+          const T uj = u_s[base + off_s[j]];
+#pragma unroll
+          for (int rr = 0; rr < NR; ++rr) {
+            const int i = min(lane + 64 * rr, NL - 1);
             const int idx = (MODE == kModeLanczos)
                                 ? i * NL + j
                                 : ((i <= j) ? j * (j + 1) / 2 + i : i * (i + 1) / 2 + j);
-            y += K[idx] * u_s[base + off_s[j]];
+            y[rr] += (double)K[idx] * (double)uj;
           }
-          y_s[c * NL + i] = y;
+        }
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          const int i = lane + 64 * rr;
+          if (i < NL) y_s[c * NL + i] = (T)y[rr];
         }
       }
     }
@@ -274,49 +307,63 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   __syncthreads();
 
   // ---- owned nodes: fixed-order gather of element results + update ----
-  const int ox0 = cx0 * P;
-  const int ox1 = (cx0 + TX >= a.n[0]) ? a.np[0] : (cx0 + TX) * P;
-  const int oy0 = (DIM >= 2) ? cy0 * P : 0;
-  const int oy1 = (DIM >= 2) ? ((cy0 + TY >= a.n[1]) ? a.np[1] : (cy0 + TY) * P) : 1;
-  const int oz0 = (DIM == 3) ? cz0 * P : 0;
-  const int oz1 = (DIM == 3) ? ((cz0 + TZ >= a.n[2]) ? a.np[2] : (cz0 + TZ) * P) : 1;
-  const int onx = ox1 - ox0, ony = oy1 - oy0, onz = oz1 - oz0;
-  const int nown = onx * ony * onz;
-  for (int i = tid; i < nown; i += 256) {
-    const int gx = ox0 + i % onx;
-    const int gy = oy0 + (i / onx) % ony;
-    const int gz = oz0 + i / (onx * ony);
-    const int64_t node = gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz);
-    int cl[3], ch[3];
-    const int g3[3] = {gx, gy, gz};
+  // The cells around node g along one axis are a = g/P - 1 (when g is a positive
+  // multiple of P) and b = g/P (when g < n P); cells outside the domain hold zeros.
+#pragma unroll
+  for (int it = 0; it < NO; ++it) {
+    const int i = tid + it * 256;
+    const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
+    if (i >= OX * OY * OZ || lx >= onx || ly >= ony || lz >= onz) continue;
+    const int g3[3] = {ox0 + lx, oy0 + ly, oz0 + lz};
+    const int64_t node = g3[0] + (int64_t)a.np[0] * (g3[1] + (int64_t)a.np[1] * g3[2]);
+    int ca[3], cb[3], la[3], lb[3];
+    bool ua[3], ub[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (k >= DIM) { cl[k] = ch[k] = 0; continue; }
-      int hi = g3[k] / P;
-      int lo = (g3[k] % P == 0) ? hi - 1 : hi;
-      if (hi > a.n[k] - 1) hi = a.n[k] - 1;
-      if (lo < 0) lo = 0;
-      cl[k] = lo;
-      ch[k] = hi;
+      const int rc0 = (k == 0) ? rcx0 : (k == 1 ? rcy0 : rcz0);
+      if (k >= DIM) {
+        ca[k] = cb[k] = 0; la[k] = lb[k] = 0; ua[k] = false; ub[k] = true;
+        continue;
+      }
+      const int g = g3[k];
+      const int q = g / P, rem = g - q * P;
+      ua[k] = (rem == 0) && (g > 0);
+      ub[k] = g < a.n[k] * P;
+      ca[k] = max(q - 1 - rc0, 0);                       // region-local cell index
+      cb[k] = min(q - rc0, (k == 0 ? RCX : (k == 1 ? RCY : RCZ)) - 1);
+      la[k] = P;                                          // local node in cell a
+      lb[k] = rem;                                        // local node in cell b
     }
     T r[NCOMP];
 #pragma unroll
     for (int comp = 0; comp < NCOMP; ++comp) r[comp] = T(0);
-    for (int cz = cl[2]; cz <= ch[2]; ++cz)
-      for (int cy = cl[1]; cy <= ch[1]; ++cy)
-        for (int cx = cl[0]; cx <= ch[0]; ++cx) {
-          const int lcell = (cx - rcx0) + RCX * ((cy - rcy0) + RCY * (cz - rcz0));
-          if (info_s[lcell] == kInfoOut) continue;
-          const int loc = (gx - cx * P) + NP1 * ((gy - cy * P) + NP1 * (gz - cz * P));
 #pragma unroll
-          for (int comp = 0; comp < NCOMP; ++comp) r[comp] += y_s[lcell * NL + comp * NS + loc];
+    for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
+#pragma unroll
+      for (int sy = 0; sy < (DIM >= 2 ? 2 : 1); ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 2; ++sx) {
+          const bool use = (sx ? ub[0] : ua[0]) && (DIM < 2 || (sy ? ub[1] : ua[1])) &&
+                           (DIM < 3 || (sz ? ub[2] : ua[2]));
+          const int lcell = (sx ? cb[0] : ca[0]) +
+                            RCX * ((sy ? cb[1] : ca[1]) + RCY * (sz ? cb[2] : ca[2]));
+          const int loc = (sx ? lb[0] : la[0]) +
+                          NP1 * ((sy ? lb[1] : la[1]) + NP1 * (sz ? lb[2] : la[2]));
+#pragma unroll
+          for (int comp = 0; comp < NCOMP; ++comp) {
+            const T v = y_s[lcell * NL + comp * NS + loc];
+            r[comp] += use ? v : T(0);
+          }
         }
     if (MODE == kModeStep) {
-      const int rl = (gx - rnx0) + RNX * ((gy - rny0) + RNY * (gz - rnz0));
-      const T im = a.invm[node];
+      const int ii = (MODE == kModeStep) ? it : 0;
+      const int rl = (g3[0] - rnx0) + RNX * ((g3[1] - rny0) + RNY * (g3[2] - rnz0));
+      const T im = im_r[ii];
       int sloc = -1;
       if (src_on) {
         const SourceDev& s = a.src[rhs];
-        const int sx = gx - s.cell[0] * P, sy = gy - s.cell[1] * P, sz = gz - s.cell[2] * P;
+        const int sx = g3[0] - s.cell[0] * P, sy = g3[1] - s.cell[1] * P,
+                  sz = g3[2] - s.cell[2] * P;
         if (sx >= 0 && sx <= P && (DIM < 2 || (sy >= 0 && sy <= P)) &&
             (DIM < 3 || (sz >= 0 && sz <= P)))
           sloc = sx + NP1 * ((DIM >= 2 ? sy : 0) + NP1 * (DIM == 3 ? sz : 0));
@@ -328,7 +375,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         if (sloc >= 0) F = (T)(ft_s * a.src[rhs].b[comp * NS + sloc]);
         T acc = a.dt2 * im * (F - r[comp]);
         if (a.start) acc = acc * T(0.5);
-        const T dn = a.d[dof] + acc;
+        const T dn = d_r[ii][comp] + acc;
         a.d[dof] = dn;
         a.u_out[dof] = u_s[comp * NRN + rl] + dn;
       }
@@ -371,10 +418,12 @@ static StepArgs<T> make_args(const Ctx& c, int tx, int ty, int tz) {
   return a;
 }
 
+using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, double, int);
+
 template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ>
 struct TileCfg {
-  static fcw_status run(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
-                        double t, double dt, int start) {
+  static StepArgs<T> args(Ctx& c, const void* uin, void* uout, void* d, double t, double dt,
+                          int start, int mode) {
     StepArgs<T> a = make_args<T>(c, TX, TY, TZ);
     a.u_in = (const T*)uin;
     a.u_out = (T*)uout;
@@ -387,6 +436,12 @@ struct TileCfg {
       a.kref = (const T*)c.d_kref;
       a.kcut = (const T*)c.d_kcut;
     }
+    return a;
+  }
+  // every mode (the default configuration of a problem kind)
+  static fcw_status run(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
+                        double t, double dt, int start) {
+    StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
     if (mode == kModeStep)
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
@@ -397,49 +452,134 @@ struct TileCfg {
     FCW_HIP(hipGetLastError());
     return FCW_OK;
   }
+  // the step only (alternative tile shapes offered to the autotuner)
+  static fcw_status run_step(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
+                             double t, double dt, int start) {
+    if (mode != kModeStep) {
+      set_error("tile configuration built for the step only");
+      return FCW_E_UNSUPPORTED;
+    }
+    StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
+    dim3 grid(8 * a.chunk, nrhs, 1);
+    tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
+    FCW_HIP(hipGetLastError());
+    return FCW_OK;
+  }
 };
 
-using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, double, int);
+struct Cand {
+  RunFn fn;
+  int tile[3];
+};
 
+// Candidate tile shapes per problem kind; entry 0 is the default and serves every mode.
 template <typename T>
-static RunFn select_kernel(const Ctx& c) {
+static int candidates(const Ctx& c, Cand* out) {
   constexpr bool F64 = sizeof(T) == 8;
-#define FCW_CASE(D, PP, NC, TX, TY, TZ)                        \
-  if (c.dim == D && c.p == PP && c.ncomp == NC)                \
-    return &TileCfg<T, D, PP, NC, TX, TY, TZ>::run;
+  int n = 0;
+#define FCW_C0(D, PP, NC, TX, TY, TZ)                  \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run, {TX, TY, TZ}};
+#define FCW_C(D, PP, NC, TX, TY, TZ)                   \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run_step, {TX, TY, TZ}};
   if constexpr (F64) {
-    FCW_CASE(2, 1, 1, 32, 16, 1) FCW_CASE(2, 2, 1, 16, 16, 1) FCW_CASE(2, 3, 1, 16, 8, 1)
-    FCW_CASE(2, 4, 1, 16, 8, 1) FCW_CASE(2, 5, 1, 8, 8, 1) FCW_CASE(2, 6, 1, 8, 8, 1)
-    FCW_CASE(3, 1, 1, 8, 8, 4) FCW_CASE(3, 2, 1, 8, 4, 4) FCW_CASE(3, 3, 1, 4, 4, 4)
-    FCW_CASE(3, 4, 1, 4, 4, 2)
-    FCW_CASE(3, 1, 3, 8, 4, 4) FCW_CASE(3, 2, 3, 4, 4, 2)
+    FCW_C0(2, 1, 1, 32, 16, 1) FCW_C(2, 1, 1, 16, 16, 1)
+    FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1)
+    FCW_C0(2, 3, 1, 16, 8, 1) FCW_C(2, 3, 1, 8, 8, 1)
+    FCW_C0(2, 4, 1, 16, 8, 1) FCW_C(2, 4, 1, 8, 8, 1) FCW_C(2, 4, 1, 8, 4, 1)
+    FCW_C0(2, 5, 1, 8, 8, 1) FCW_C(2, 5, 1, 8, 4, 1)
+    FCW_C0(2, 6, 1, 8, 8, 1) FCW_C(2, 6, 1, 8, 4, 1)
+    FCW_C0(3, 1, 1, 8, 8, 4)
+    FCW_C0(3, 2, 1, 8, 4, 4) FCW_C(3, 2, 1, 4, 4, 4)
+    FCW_C0(3, 3, 1, 4, 4, 4) FCW_C(3, 3, 1, 4, 4, 2)
+    FCW_C0(3, 4, 1, 4, 4, 2) FCW_C(3, 4, 1, 4, 2, 2)
+    FCW_C0(3, 1, 3, 8, 4, 4)
+    FCW_C0(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
   } else {
-    FCW_CASE(2, 1, 1, 32, 32, 1) FCW_CASE(2, 2, 1, 16, 16, 1) FCW_CASE(2, 3, 1, 16, 16, 1)
-    FCW_CASE(2, 4, 1, 16, 16, 1) FCW_CASE(2, 5, 1, 16, 8, 1) FCW_CASE(2, 6, 1, 8, 8, 1)
-    FCW_CASE(3, 1, 1, 8, 8, 8) FCW_CASE(3, 2, 1, 8, 4, 4) FCW_CASE(3, 3, 1, 4, 4, 4)
-    FCW_CASE(3, 4, 1, 4, 4, 2)
-    FCW_CASE(3, 1, 3, 8, 4, 4) FCW_CASE(3, 2, 3, 4, 4, 4)
+    FCW_C0(2, 1, 1, 32, 32, 1) FCW_C(2, 1, 1, 32, 16, 1)
+    FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1) FCW_C(2, 2, 1, 32, 16, 1)
+    FCW_C0(2, 3, 1, 16, 16, 1) FCW_C(2, 3, 1, 16, 8, 1) FCW_C(2, 3, 1, 8, 8, 1)
+    FCW_C0(2, 4, 1, 16, 16, 1) FCW_C(2, 4, 1, 16, 8, 1) FCW_C(2, 4, 1, 8, 8, 1)
+    FCW_C(2, 4, 1, 32, 8, 1) FCW_C(2, 4, 1, 8, 4, 1)
+    FCW_C0(2, 5, 1, 16, 8, 1) FCW_C(2, 5, 1, 8, 8, 1)
+    FCW_C0(2, 6, 1, 8, 8, 1) FCW_C(2, 6, 1, 8, 4, 1)
+    FCW_C0(3, 1, 1, 8, 8, 8)
+    FCW_C0(3, 2, 1, 8, 4, 4) FCW_C(3, 2, 1, 4, 4, 4) FCW_C(3, 2, 1, 8, 8, 4)
+    FCW_C0(3, 3, 1, 4, 4, 4) FCW_C(3, 3, 1, 4, 4, 2)
+    FCW_C0(3, 4, 1, 4, 4, 2) FCW_C(3, 4, 1, 4, 2, 2)
+    FCW_C0(3, 1, 3, 8, 4, 4)
+    FCW_C0(3, 2, 3, 4, 4, 4) FCW_C(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
   }
-#undef FCW_CASE
-  return nullptr;
+#undef FCW_C0
+#undef FCW_C
+  return n;
 }
 
-static RunFn select_for(const Ctx& c, bool fp64) {
-  return fp64 ? select_kernel<double>(c) : select_kernel<float>(c);
+constexpr int kMaxCand = 8;
+
+static int cands_for(const Ctx& c, bool fp64, Cand* out) {
+  return fp64 ? candidates<double>(c, out) : candidates<float>(c, out);
+}
+
+static RunFn select_for(const Ctx& c, bool fp64, int choice = 0) {
+  Cand cs[kMaxCand];
+  const int n = cands_for(c, fp64, cs);
+  if (n == 0) return nullptr;
+  if (choice < 0 || choice >= n) choice = 0;
+  return cs[choice].fn;
 }
 
 bool step_supported(const Ctx& c) {
   return select_for(c, c.precision == FCW_FP64) != nullptr && select_for(c, true) != nullptr;
 }
 
+using Run2d = fcw_status (*)(Ctx&, int, const void*, void*, void*, double, double, int);
+int step2d_candidates(const Ctx& c, int i, Run2d* fn, int tile[3]);
+
+// Step configurations offered to the autotuner: the 2-D kernels of step2d.hip first (for
+// 2-D scalar problems), then the tile shapes of the generic kernel.
+struct StepCand {
+  Run2d f2d = nullptr;
+  RunFn fgen = nullptr;
+  int tile[3] = {0, 0, 0};
+};
+
+static int step_candidates(const Ctx& c, int i, StepCand* out) {
+  const int n2 = step2d_candidates(c, -1, nullptr, nullptr);
+  Cand cs[kMaxCand];
+  const int ng = cands_for(c, c.precision == FCW_FP64, cs);
+  if (out && i >= 0 && i < n2) {
+    step2d_candidates(c, i, &out->f2d, out->tile);
+  } else if (out && i >= n2 && i < n2 + ng) {
+    out->fgen = cs[i - n2].fn;
+    for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
+  }
+  return n2 + ng;
+}
+
+int tile_candidates(const Ctx& c, int i, int tile[3]) {
+  StepCand sc;
+  const int n = step_candidates(c, i, &sc);
+  if (tile && i >= 0 && i < n)
+    for (int k = 0; k < 3; ++k) tile[k] = sc.tile[k];
+  return n;
+}
+
+fcw_status launch_step_with(Ctx& c, int choice, int nrhs, const void* u_in, void* u_out,
+                            void* d, double t, double dt, int start) {
+  StepCand sc;
+  const int n = step_candidates(c, choice, &sc);
+  if (choice < 0 || choice >= n) step_candidates(c, 0, &sc);
+  if (sc.f2d) return sc.f2d(c, nrhs, u_in, u_out, d, t, dt, start);
+  if (sc.fgen) return sc.fgen(c, kModeStep, nrhs, u_in, u_out, d, t, dt, start);
+  set_error("step kernel not built for dim=%d p=%d ncomp=%d", c.dim, c.p, c.ncomp);
+  return FCW_E_UNSUPPORTED;
+}
+
 fcw_status launch_step(Ctx& c, int nrhs, const void* u_in, void* u_out, void* d, double t,
                        double dt, int start) {
-  RunFn f = select_for(c, c.precision == FCW_FP64);
-  if (!f) {
-    set_error("step kernel not built for dim=%d p=%d ncomp=%d", c.dim, c.p, c.ncomp);
-    return FCW_E_UNSUPPORTED;
-  }
-  return f(c, kModeStep, nrhs, u_in, u_out, d, t, dt, start);
+  return launch_step_with(c, c.tile_choice, nrhs, u_in, u_out, d, t, dt, start);
 }
 
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r) {

@@ -25,6 +25,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
+           "fcw_autotune", "fcw_tile_config", "fcw_select_tile",
            "fcw_export", "fcw_destroy", "fcw_last_error")
 
 
@@ -78,6 +79,9 @@ def load(path=LIB_PATH):
     lib.fcw_apply_stiffness.argtypes = [vp, i32, vp, vp]
     lib.fcw_query.argtypes = [vp, C.POINTER(Info)]
     lib.fcw_export.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.fcw_autotune.argtypes = [vp, i32, i32, C.POINTER(i32)]
+    lib.fcw_tile_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(f64), C.POINTER(i32)]
+    lib.fcw_select_tile.argtypes = [vp, i32]
     lib.fcw_destroy.argtypes = [vp]
     lib.fcw_destroy.restype = None
     lib.fcw_last_error.argtypes = []
@@ -172,6 +176,31 @@ def step_imex(ctx, nrhs, u, v_c, a_c, sources, t0, dt, nsteps):
 
 def apply_stiffness(ctx, nrhs, u, r):
     _check(load().fcw_apply_stiffness(ctx, int(nrhs), _ptr(u), _ptr(r)))
+
+
+def autotune(ctx, nrhs=1, nsteps=20):
+    """Time every tile configuration and keep the fastest; returns (chosen, table)."""
+    lib = load()
+    ch = C.c_int32()
+    _check(lib.fcw_autotune(ctx, int(nrhs), int(nsteps), C.byref(ch)))
+    return ch.value, tile_configs(ctx)
+
+
+def tile_configs(ctx):
+    lib = load()
+    n = C.c_int32()
+    lib.fcw_tile_config(ctx, 0, None, None, C.byref(n))
+    out = []
+    for i in range(n.value):
+        t = (C.c_int32 * 3)()
+        us = C.c_double()
+        _check(lib.fcw_tile_config(ctx, i, t, C.byref(us), None))
+        out.append(dict(tile=tuple(t), us_per_step=us.value))
+    return out
+
+
+def select_tile(ctx, i):
+    _check(load().fcw_select_tile(ctx, int(i)))
 
 
 def query(ctx):

@@ -35,6 +35,17 @@ class Solver:
         self.info = fcw.query(self.ctx)
         return dtc
 
+    def autotune(self, nrhs=1, nsteps=20):
+        """Pick the fastest compiled tile configuration of the step for this problem."""
+        chosen, table = fcw.autotune(self.ctx, nrhs, nsteps)
+        return chosen, table
+
+    def select_tile(self, i):
+        fcw.select_tile(self.ctx, i)
+
+    def tile_configs(self):
+        return fcw.tile_configs(self.ctx)
+
     def zeros(self, nrhs=1):
         return self.torch.zeros(nrhs, self.ndof, dtype=self.dtype, device=self.device)
 

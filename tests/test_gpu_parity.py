@@ -199,7 +199,8 @@ def test_ragged_grid_and_multi_rhs():
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_elastic_3d_parity(precision, tol):
-    cfg = workloads.scaled_config(3, 6, 2, seed=3, ncomp=3, porosity=0.2, nsteps=120)
+    # 4^3 cells of the c3 pore-field kind (radii 0.02-0.06), octree depth 3
+    cfg = workloads.scaled_config(3, 4, 2, seed=4, ncomp=3, porosity=0.2, nsteps=120)
     cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
     disc = _oracle(cfg)
     dt = 0.9 * timestep.critical_dt(disc)
@@ -214,7 +215,7 @@ def test_elastic_3d_parity(precision, tol):
 
 
 def test_scalar_3d_parity():
-    cfg = workloads.scaled_config(3, 8, 3, seed=4, porosity=0.15, nsteps=80)
+    cfg = workloads.scaled_config(3, 6, 3, seed=4, porosity=0.15, nsteps=80, depth=2)
     cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), f0=10.0, amp=1.0)]
     disc = _oracle(cfg)
     dt = 0.9 * timestep.critical_dt(disc)
