@@ -121,6 +121,31 @@ fcw_status fcw_step_explicit(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
                              const fcw_source* src, double t0, double dt,
                              int32_t nsteps, int32_t start);
 
+/* One problem's share of a batched run (fcw_run). */
+typedef struct {
+  fcw_ctx* ctx;
+  int32_t nrhs;
+  void* u;                /* device [nrhs][ndof], in/out */
+  void* d;                /* device [nrhs][ndof], in/out (dt * v_0 on a start call) */
+  const fcw_source* src;  /* host [nrhs] or NULL */
+  double t0;              /* time of the first step of this call */
+  double dt;              /* step; <= 0 means 0.9 * dt_crit (fcw_critical_dt must have run) */
+  int32_t nsteps;         /* steps of this problem (problems may differ) */
+  int32_t start;          /* nonzero on the first call of a run (Newmark beta = 0 start-up) */
+} fcw_run_item;
+
+enum { FCW_RUN_GRAPH = 1 };
+
+/* Advance several problems, each by its own nsteps central-difference steps.  Problems
+ * of one kind (2-D scalar, same p and precision) are advanced together: one launch per
+ * step covers every (problem, right-hand side, tile) of the group, problems that have
+ * finished their steps drop out of later launches.  Other problems run one after
+ * another.  All work goes on the stream of the first problem's context.  With
+ * FCW_RUN_GRAPH the launches of a group are captured once into a HIP graph and replayed
+ * (the graph is cached and reused while the group's shape is unchanged).  Sources,
+ * state layout and errors as in fcw_step_explicit. */
+fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags);
+
 /* Autotuner of the step kernel: times every compiled tile configuration for this
  * problem kind on scratch state (nrhs right-hand sides, nsteps steps each, F = 0) and
  * keeps the fastest for later fcw_step_explicit calls.  *chosen (may be NULL)

@@ -50,6 +50,13 @@ static void free_all(Ctx& c) {
   dfree(c.d_mcut); dfree(c.d_lumped); dfree(c.d_margin); dfree(c.d_evs_fail); dfree(c.d_mass);
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf);
   dfree(c.d_src);
+  dfree(c.d_wl);
+  if (c.h_wl) (void)hipHostFree(c.h_wl);
+  c.h_wl = nullptr;
+  if (c.wl_event) (void)hipEventDestroy(c.wl_event);
+  c.wl_event = nullptr;
+  if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+  c.graph_exec = nullptr;
 }
 
 static bool in_any_void(const Ctx& c, const double* x) {
@@ -254,16 +261,15 @@ fcw_status fcw_critical_dt(fcw_ctx* c, int32_t max_iter, double rtol, double* dt
   return FCW_OK;
 }
 
-fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
-                             double t0, double dt, int32_t nsteps, int32_t start) {
-  g_err.clear();
+// checks of one problem's step call; prepares its sources and scratch
+static fcw_status prepare_call(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
+                               double dt, int32_t nsteps) {
   fcw_status st = check_ctx(c, 2);
   if (st) return st;
   if (nrhs < 1 || nrhs > 64 || !u || !d || !(dt > 0.0) || nsteps < 0) {
     set_error("invalid arguments (nrhs in [1,64], u, d non-null, dt > 0, nsteps >= 0)");
     return FCW_E_ARG;
   }
-  if (nsteps == 0) return FCW_OK;
   if (src) {
     for (int s = 0; s < nrhs; ++s) {
       for (int k = 0; k < c->dim; ++k)
@@ -290,23 +296,80 @@ fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const f
     if ((st = dmalloc(*c, &c->d_ubuf, bytes))) return st;
     c->ubuf_bytes = bytes;
   }
-  void* a = u;
-  void* b = c->d_ubuf;
-  if (nsteps % 2 == 1) {
-    FCW_HIP(hipMemcpyAsync(c->d_ubuf, u, bytes, hipMemcpyDeviceToDevice, c->stream));
-    a = c->d_ubuf;
-    b = u;
+  return FCW_OK;
+}
+
+fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
+  g_err.clear();
+  if (!items || n < 1) {
+    set_error("need at least one run item");
+    return FCW_E_ARG;
   }
-  const SourceDev* saved = c->d_src;
+  fcw_ctx* owner = items[0].ctx;
+  fcw_status st = check_ctx(owner, 2);
+  if (st) return st;
+  // validate and prepare every member first (no work is enqueued on error)
+  std::vector<GroupMember> group;
+  std::vector<int> solo;
+  std::vector<double> dts(n);
+  for (int i = 0; i < n; ++i) {
+    const fcw_run_item& r = items[i];
+    if (!r.ctx) { set_error("run item %d has no context", i); return FCW_E_ARG; }
+    double dt = r.dt;
+    if (!(dt > 0.0)) {
+      if (!(r.ctx->dt_crit > 0.0)) {
+        set_error("run item %d: dt <= 0 needs fcw_critical_dt first", i);
+        return FCW_E_STATE;
+      }
+      dt = 0.9 * r.ctx->dt_crit;
+    }
+    dts[i] = dt;
+    for (int k = 0; k < i; ++k)
+      if (items[k].ctx == r.ctx) { set_error("context listed twice in one run"); return FCW_E_ARG; }
+    if ((st = prepare_call(r.ctx, r.nrhs, r.u, r.d, r.src, dt, r.nsteps))) return st;
+    if (!r.src) r.ctx->d_src_active = false;
+    else r.ctx->d_src_active = true;
+    if (groupable_2d(*owner, *r.ctx))
+      group.push_back(GroupMember{r.ctx, r.nrhs, r.u, r.d, r.ctx->d_ubuf, r.t0, dt, r.nsteps,
+                                  r.start});
+    else
+      solo.push_back(i);
+  }
+  // the group runs on the owner's stream; sources of members without any are hidden
+  std::vector<SourceDev*> saved;
+  for (auto& g : group) {
+    saved.push_back(g.ctx->d_src);
+    if (!g.ctx->d_src_active) g.ctx->d_src = nullptr;
+  }
+  if (!group.empty()) st = run_group(*owner, group, (flags & FCW_RUN_GRAPH) != 0);
+  for (size_t k = 0; k < group.size(); ++k) group[k].ctx->d_src = saved[k];
+  if (st) return st;
+  for (int i : solo) {
+    const fcw_run_item& r = items[i];
+    fcw_ctx* c = r.ctx;
+    SourceDev* sv = c->d_src;
+    if (!r.src) c->d_src = nullptr;
+    hipStream_t s0 = c->stream;
+    c->stream = owner->stream;
+    st = run_steps(*c, c->tile_choice, r.nrhs, r.u, r.d, c->d_ubuf, r.t0, dts[i], r.nsteps,
+                   r.start);
+    c->stream = s0;
+    c->d_src = sv;
+    if (st) return st;
+  }
+  return FCW_OK;
+}
+
+fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
+                             double t0, double dt, int32_t nsteps, int32_t start) {
+  g_err.clear();
+  fcw_status st = prepare_call(c, nrhs, u, d, src, dt, nsteps);
+  if (st) return st;
+  if (nsteps == 0) return FCW_OK;
+  SourceDev* saved = c->d_src;
   if (!src) c->d_src = nullptr;
-  for (int j = 0; j < nsteps; ++j) {
-    st = launch_step(*c, nrhs, a, b, d, t0 + j * dt, dt, (start && j == 0) ? 1 : 0);
-    if (st) break;
-    void* t = a;
-    a = b;
-    b = t;
-  }
-  c->d_src = const_cast<SourceDev*>(saved);
+  st = run_steps(*c, c->tile_choice, nrhs, u, d, c->d_ubuf, t0, dt, nsteps, start);
+  c->d_src = saved;
   return st;
 }
 
@@ -345,12 +408,17 @@ fcw_status fcw_autotune(fcw_ctx* c, int32_t nrhs, int32_t nsteps, int32_t* chose
   c->d_src = nullptr;
   c->tune_us.assign(n, 0.0);
   int best = 0;
+  void* sc = nullptr;
+  if (hipMalloc(&sc, bytes) != hipSuccess) {
+    cleanup();
+    set_error("autotune scratch allocation failed");
+    return FCW_E_NOMEM;
+  }
   for (int i = 0; i < n && st == FCW_OK; ++i) {
-    for (int w = 0; w < 2 && st == FCW_OK; ++w)
-      st = launch_step_with(*c, i, nrhs, ua, ub, dd, 0.0, 1e-6, 0);
+    st = run_steps(*c, i, nrhs, ua, dd, sc, 0.0, 1e-6, 2, 0);  // warm-up
+    if (st) break;
     (void)hipEventRecord(e0, c->stream);
-    for (int j = 0; j < nsteps && st == FCW_OK; ++j)
-      st = launch_step_with(*c, i, nrhs, (j & 1) ? ub : ua, (j & 1) ? ua : ub, dd, 0.0, 1e-6, 0);
+    st = run_steps(*c, i, nrhs, ua, dd, sc, 0.0, 1e-6, nsteps, 0);
     (void)hipEventRecord(e1, c->stream);
     if (hipEventSynchronize(e1) != hipSuccess) {
       st = hip_fail(hipGetLastError(), "autotune timing");
@@ -361,6 +429,7 @@ fcw_status fcw_autotune(fcw_ctx* c, int32_t nrhs, int32_t nsteps, int32_t* chose
     c->tune_us[i] = 1000.0 * ms / nsteps;
     if (c->tune_us[i] < c->tune_us[best]) best = i;
   }
+  (void)hipFree(sc);
   c->d_src = const_cast<SourceDev*>(saved);
   cleanup();
   if (st) return st;

@@ -85,7 +85,18 @@ struct Ctx {
   void* d_ubuf = nullptr;
   size_t ubuf_bytes = 0;
   SourceDev* d_src = nullptr;
+  bool d_src_active = false;  // the sources of the current batched call are set
   int src_cap = 0;
+  // work list of the persistent step kernel (device + pinned staging)
+  void* d_wl = nullptr;
+  void* h_wl = nullptr;
+  size_t wl_bytes = 0;
+  hipEvent_t wl_event = nullptr;
+  // cached graph of a batched run: valid for the same launch sequence
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_fn = nullptr;
+  int graph_nitems = 0, graph_nsteps = 0;
+  void* graph_wl = nullptr;
   int64_t footprint = 0;
 
   size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
@@ -112,12 +123,20 @@ fcw_status setup_mass_and_pack(Ctx& c);
 fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
 // step.hip
 bool step_supported(const Ctx& c);
-fcw_status launch_step(Ctx& c, int nrhs, const void* u_in, void* u_out, void* d,
-                       double t, double dt, int start);
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);
-fcw_status launch_step_with(Ctx& c, int choice, int nrhs, const void* u_in, void* u_out,
-                            void* d, double t, double dt, int start);
 int tile_candidates(const Ctx& c, int i, int tile[3]);
+fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scratch, double t0,
+                     double dt, int nsteps, int start);
+// one batched group of 2-D problems (see fcw_run)
+struct GroupMember {
+  Ctx* ctx;
+  int nrhs;
+  void *u, *d, *scratch;
+  double t0, dt;
+  int nsteps, start;
+};
+fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph);
+bool groupable_2d(const Ctx& a, const Ctx& b);
 fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
 // lanczos.hip
 fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax);

@@ -19,7 +19,10 @@
 //    the acceleration (Alg. newmark with beta = 0).
 //  * Tiles are mapped to blocks XCD by XCD (blocks b, b+8, ... run on one XCD and get
 //    neighbouring tiles, so halo rows are shared through that XCD's L2).
+#include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "step_common.h"
 
@@ -534,11 +537,14 @@ bool step_supported(const Ctx& c) {
   return select_for(c, c.precision == FCW_FP64) != nullptr && select_for(c, true) != nullptr;
 }
 
-using Run2d = fcw_status (*)(Ctx&, int, const void*, void*, void*, double, double, int);
-int step2d_candidates(const Ctx& c, int i, Run2d* fn, int tile[3]);
+using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int);
+int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]);
+size_t prob2d_size(int fp64);
+void prob2d_fill(const Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
+                 int nsteps, int start, int tx, int ty, const SourceDev* src);
 
-// Step configurations offered to the autotuner: the 2-D kernels of step2d.hip first (for
-// 2-D scalar problems), then the tile shapes of the generic kernel.
+// Step configurations offered to the autotuner: the work-list 2-D kernels (step2d.hip)
+// for 2-D scalar problems, then the tile shapes of the generic kernel.
 struct StepCand {
   Run2d f2d = nullptr;
   RunFn fgen = nullptr;
@@ -546,14 +552,17 @@ struct StepCand {
 };
 
 static int step_candidates(const Ctx& c, int i, StepCand* out) {
-  const int n2 = step2d_candidates(c, -1, nullptr, nullptr);
+  const int fp64 = c.precision == FCW_FP64;
+  const int n2 = (c.dim == 2 && c.ncomp == 1) ? step2d_candidates(c.p, fp64, -1, nullptr, nullptr) : 0;
   Cand cs[kMaxCand];
-  const int ng = cands_for(c, c.precision == FCW_FP64, cs);
-  if (out && i >= 0 && i < n2) {
-    step2d_candidates(c, i, &out->f2d, out->tile);
-  } else if (out && i >= n2 && i < n2 + ng) {
-    out->fgen = cs[i - n2].fn;
-    for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
+  const int ng = cands_for(c, fp64, cs);
+  if (out) {
+    if (i >= 0 && i < n2) {
+      step2d_candidates(c.p, fp64, i, &out->f2d, out->tile);
+    } else if (i >= n2 && i < n2 + ng) {
+      out->fgen = cs[i - n2].fn;
+      for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
+    }
   }
   return n2 + ng;
 }
@@ -566,20 +575,146 @@ int tile_candidates(const Ctx& c, int i, int tile[3]) {
   return n;
 }
 
-fcw_status launch_step_with(Ctx& c, int choice, int nrhs, const void* u_in, void* u_out,
-                            void* d, double t, double dt, int start) {
+// Device work list (problem records + items) with pinned staging, owned by `c`.
+static fcw_status stage_worklist(Ctx& c, const void* host, size_t bytes) {
+  if (c.wl_bytes < bytes) {
+    if (c.wl_event) FCW_HIP(hipEventSynchronize(c.wl_event));
+    if (c.d_wl) FCW_HIP(hipFree(c.d_wl));
+    if (c.h_wl) FCW_HIP(hipHostFree(c.h_wl));
+    c.d_wl = nullptr;
+    c.h_wl = nullptr;
+    FCW_HIP(hipMalloc(&c.d_wl, bytes));
+    FCW_HIP(hipHostMalloc(&c.h_wl, bytes, hipHostMallocDefault));
+    c.wl_bytes = bytes;
+  }
+  // the pinned staging buffer may still feed a previous copy
+  if (c.wl_event) FCW_HIP(hipEventSynchronize(c.wl_event));
+  else FCW_HIP(hipEventCreateWithFlags(&c.wl_event, hipEventDisableTiming));
+  std::memcpy(c.h_wl, host, bytes);
+  FCW_HIP(hipMemcpyAsync(c.d_wl, c.h_wl, bytes, hipMemcpyHostToDevice, c.stream));
+  FCW_HIP(hipEventRecord(c.wl_event, c.stream));
+  return FCW_OK;
+}
+
+fcw_status run_group2d(Ctx& owner, Run2d fn, const std::vector<char>& records, int nprob,
+                       const std::vector<int4>& items, int nsteps) {
+  const int fp64 = owner.precision == FCW_FP64;
+  const size_t rb = prob2d_size(fp64) * nprob;
+  std::vector<char> host(rb + items.size() * sizeof(int4));
+  std::memcpy(host.data(), records.data(), rb);
+  std::memcpy(host.data() + rb, items.data(), items.size() * sizeof(int4));
+  fcw_status st = stage_worklist(owner, host.data(), host.size());
+  if (st) return st;
+  const int4* ditems = (const int4*)((char*)owner.d_wl + rb);
+  for (int j = 0; j < nsteps; ++j) {
+    st = fn(owner.stream, owner.d_wl, ditems, (int)items.size(), j);
+    if (st) return st;
+  }
+  return FCW_OK;
+}
+
+bool groupable_2d(const Ctx& a, const Ctx& b) {
+  return a.dim == 2 && b.dim == 2 && a.ncomp == 1 && b.ncomp == 1 && a.p == b.p &&
+         a.precision == b.precision;
+}
+
+// A batched group: the first member's configuration choice gives the 2-D kernel (its tile
+// shape applies to every member); one launch per step over all members' items.
+fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) {
+  const int fp64 = owner.precision == FCW_FP64;
+  StepCand sc;
+  step_candidates(owner, owner.tile_choice, &sc);
+  if (!sc.f2d) step_candidates(owner, 0, &sc);
+  if (!sc.f2d) {
+    set_error("batched runs need 2-D scalar problems");
+    return FCW_E_UNSUPPORTED;
+  }
+  const size_t rs = prob2d_size(fp64);
+  std::vector<char> rec(rs * m.size());
+  std::vector<int4> items;
+  int nmax = 0;
+  for (size_t i = 0; i < m.size(); ++i) {
+    const GroupMember& g = m[i];
+    const Ctx& c = *g.ctx;
+    if (g.nsteps <= 0) continue;
+    if (g.nsteps % 2 == 1)
+      FCW_HIP(hipMemcpyAsync(g.scratch, g.u, (size_t)g.nrhs * c.ndof * c.state_bytes(),
+                             hipMemcpyDeviceToDevice, owner.stream));
+    prob2d_fill(c, rec.data() + rs * i, g.u, g.scratch, g.d, g.t0, g.dt, g.nsteps, g.start,
+                sc.tile[0], sc.tile[1], c.d_src);
+    const int ntx = (c.ncells[0] + sc.tile[0] - 1) / sc.tile[0];
+    const int nty = (c.ncells[1] + sc.tile[1] - 1) / sc.tile[1];
+    for (int t = 0; t < ntx * nty; ++t)
+      for (int r = 0; r < g.nrhs; ++r) items.push_back(make_int4((int)i, r, t, 0));
+    nmax = std::max(nmax, g.nsteps);
+  }
+  if (items.empty()) return FCW_OK;
+  if (!graph) return run_group2d(owner, sc.f2d, rec, (int)m.size(), items, nmax);
+  // graph replay: the records live in device memory, so a cached graph stays valid for
+  // the same kernel, item count, step count and work-list buffer
+  std::vector<char> host(rec.size() + items.size() * sizeof(int4));
+  std::memcpy(host.data(), rec.data(), rec.size());
+  std::memcpy(host.data() + rec.size(), items.data(), items.size() * sizeof(int4));
+  fcw_status st = stage_worklist(owner, host.data(), host.size());
+  if (st) return st;
+  const int nitems = (int)items.size();
+  if (!(owner.graph_exec && owner.graph_fn == (const void*)sc.f2d &&
+        owner.graph_nitems == nitems && owner.graph_nsteps == nmax && owner.graph_wl == owner.d_wl)) {
+    if (owner.graph_exec) FCW_HIP(hipGraphExecDestroy(owner.graph_exec));
+    owner.graph_exec = nullptr;
+    const int4* ditems = (const int4*)((char*)owner.d_wl + rec.size());
+    hipGraph_t g = nullptr;
+    FCW_HIP(hipStreamBeginCapture(owner.stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < nmax && st == FCW_OK; ++j)
+      st = sc.f2d(owner.stream, owner.d_wl, ditems, nitems, j);
+    hipError_t e = hipStreamEndCapture(owner.stream, &g);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&owner.graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    owner.graph_fn = (const void*)sc.f2d;
+    owner.graph_nitems = nitems;
+    owner.graph_nsteps = nmax;
+    owner.graph_wl = owner.d_wl;
+  }
+  FCW_HIP(hipGraphLaunch(owner.graph_exec, owner.stream));
+  return FCW_OK;
+}
+
+// Advance nrhs right-hand sides by nsteps steps with configuration `choice`; the final
+// state is in u.  `scratch` holds nrhs*ndof state words.
+fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scratch, double t0,
+                     double dt, int nsteps, int start) {
+  if (nsteps <= 0) return FCW_OK;
+  const size_t bytes = (size_t)nrhs * c.ndof * c.state_bytes();
   StepCand sc;
   const int n = step_candidates(c, choice, &sc);
   if (choice < 0 || choice >= n) step_candidates(c, 0, &sc);
-  if (sc.f2d) return sc.f2d(c, nrhs, u_in, u_out, d, t, dt, start);
-  if (sc.fgen) return sc.fgen(c, kModeStep, nrhs, u_in, u_out, d, t, dt, start);
-  set_error("step kernel not built for dim=%d p=%d ncomp=%d", c.dim, c.p, c.ncomp);
-  return FCW_E_UNSUPPORTED;
-}
-
-fcw_status launch_step(Ctx& c, int nrhs, const void* u_in, void* u_out, void* d, double t,
-                       double dt, int start) {
-  return launch_step_with(c, c.tile_choice, nrhs, u_in, u_out, d, t, dt, start);
+  if (nsteps % 2 == 1) FCW_HIP(hipMemcpyAsync(scratch, u, bytes, hipMemcpyDeviceToDevice, c.stream));
+  if (sc.f2d) {
+    const int fp64 = c.precision == FCW_FP64;
+    const int ntx = (c.ncells[0] + sc.tile[0] - 1) / sc.tile[0];
+    const int nty = (c.ncells[1] + sc.tile[1] - 1) / sc.tile[1];
+    std::vector<char> rec(prob2d_size(fp64));
+    prob2d_fill(c, rec.data(), u, scratch, d, t0, dt, nsteps, start, sc.tile[0], sc.tile[1],
+                c.d_src);
+    std::vector<int4> items;
+    items.reserve((size_t)ntx * nty * nrhs);
+    for (int t = 0; t < ntx * nty; ++t)
+      for (int r = 0; r < nrhs; ++r) items.push_back(make_int4(0, r, t, 0));
+    return run_group2d(c, sc.f2d, rec, 1, items, nsteps);
+  }
+  void* a = (nsteps % 2 == 1) ? scratch : u;
+  void* b = (nsteps % 2 == 1) ? u : scratch;
+  for (int j = 0; j < nsteps; ++j) {
+    fcw_status st = sc.fgen(c, kModeStep, nrhs, a, b, d, t0 + j * dt, dt, (start && j == 0) ? 1 : 0);
+    if (st) return st;
+    void* t = a;
+    a = b;
+    b = t;
+  }
+  return FCW_OK;
 }
 
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r) {

@@ -1,4 +1,7 @@
-// Central-difference step (paper eq. cdm) for 2-D scalar problems, shaped for CDNA4 wave64:
+// Central-difference step (paper eq. cdm) for 2-D scalar problems, shaped for CDNA4 wave64.
+// One launch advances every item of a work list -- (problem, right-hand side, tile) --
+// by one step, so several problems of one kind (same p and precision; any size,
+// geometry and sources) and many right-hand sides share a launch.
 //
 //  * A tile is TX = 64 / P cells wide, so one owned node row of a tile is exactly one
 //    wave (lane = x); TY cells high.  A workgroup (4 waves) stages the node values of
@@ -7,7 +10,7 @@
 //  * The cells of the region are visited in 4 colour classes (cell parity in x and y).
 //    Within a class no two cells share a node, so the element results go straight
 //    into an LDS node accumulator with plain read-add-write (no two lanes or waves of
-//    a class touch the same node, and every add rounds to nearest); the classes are ordered
+//    a class touch the same node); the classes are ordered
 //    by barriers, so every node sums its (at most 4) cell contributions in a fixed
 //    order: bitwise reproducible, no atomics to global memory, no gather pass.
 //  * Uncut cells of a class: 16 per wave on the matrix cores, Y = K_ref [u_e1..u_e16]
@@ -15,10 +18,15 @@
 //    Cut cells of a class: one wave per cell streaming its packed K_e, accumulated in
 //    FP64 whatever the state precision.
 //  * The update d_{k+1} = d_k + dt^2 M^{-1}(F_k - K u_k), u_{k+1} = u_k + d_{k+1} runs
-//    row by row (lane = x), with d and M^{-1} prefetched at kernel entry.
+//    row by row (lane = x); d and M^{-1} rows are staged in LDS at kernel entry.
+#include <cstring>
+#include <type_traits>
+
 #include "step_common.h"
 
 namespace fcw {
+
+using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int);
 
 template <typename T>
 __device__ static inline void buffer_dword_to_lds(__amdgpu_buffer_rsrc_t rsrc, int voffset,
@@ -27,8 +35,28 @@ __device__ static inline void buffer_dword_to_lds(__amdgpu_buffer_rsrc_t rsrc, i
                                            4, voffset, 0, 0, 0);
 }
 
+// Per-problem arguments of a launch (device array, one entry per problem).
+template <typename T>
+struct Prob2d {
+  T* ua;                 // caller state u (the final state of a call lands here)
+  T* ub;                 // scratch (ping-pong partner of ua)
+  T* d;                  // [nrhs][ndof]
+  const T* invm;         // [nnodes]
+  const int32_t* info;   // [ncells]
+  const T* kref;         // [NL*NL]
+  const T* kcut;         // packed cut-cell matrices
+  const SourceDev* src;  // [nrhs] or null
+  int n[2], np[2], ntile[2];
+  int64_t ndof;
+  double t0, dt;
+  T dt2;
+  int nsteps, start;
+};
+
 template <typename T, int P, int TY>
-__global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void step2d_kernel(
+    const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, int nitems, int chunk,
+    int j) {
   constexpr int NP1 = P + 1;
   constexpr int NL = NP1 * NP1;
   constexpr int NMB = (NL + 15) / 16;
@@ -51,31 +79,40 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
 
   __shared__ T u_s[RNY * W];
   __shared__ T r_s[RNY * W];
+  __shared__ T d_s[NRW * 4 * 64];    // owned rows of d, one wave-row each
+  __shared__ T m_s[NRW * 4 * 64];    // owned rows of M^{-1}
   __shared__ int info_s[NRC];
   __shared__ double ft_s;
   __shared__ int src_on;
 
-  const int tile = (int)(blockIdx.x % 8) * a.chunk + (int)(blockIdx.x / 8);
-  if (tile >= a.ntiles) return;
-  const int rhs = blockIdx.y;
+  // blocks b, b+8, ... run on one XCD: give them consecutive items
+  const int item = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+  if (item >= nitems) return;
+  const int4 wi = items[item];
+  const Prob2d<T>& pr = probs[wi.x];
+  if (j >= pr.nsteps) return;  // this problem has finished its steps
+  const int rhs = wi.y;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lc = lane & 15, lk = lane >> 4;
-  const int tx = tile % a.ntile[0], ty = tile / a.ntile[0];
+  const int tx = wi.z % pr.ntile[0], ty = wi.z / pr.ntile[0];
   const int cx0 = tx * TX, cy0 = ty * TY;
   const int rcx0 = cx0 - 1, rcy0 = cy0 - 1;
   const int rnx0 = rcx0 * P, rny0 = rcy0 * P;
-  const int npx = a.np[0], npy = a.np[1];
+  const int npx = pr.np[0], npy = pr.np[1];
   const int ox0 = cx0 * P, oy0 = cy0 * P;
-  const int onx = (cx0 + TX >= a.n[0]) ? npx - ox0 : OWX;  // OWX + 1 on the last full tile
-  const int ony = (cy0 + TY >= a.n[1]) ? npy - oy0 : TY * P;
-  const int64_t roff = (int64_t)rhs * a.ndof;
-  const T* uin = a.u_in + roff;
-  T* dst_d = a.d + roff;
-  T* dst_u = a.u_out + roff;
-  const uint32_t nbytes = (uint32_t)(a.nnodes * (int64_t)sizeof(T));
+  const int onx = (cx0 + TX >= pr.n[0]) ? npx - ox0 : OWX;  // OWX + 1 on the last full tile
+  const int ony = (cy0 + TY >= pr.n[1]) ? npy - oy0 : TY * P;
+  // ping-pong: the last step of a call writes ua
+  const int par = (pr.nsteps - 1 - j) & 1;
+  const int64_t roff = (int64_t)rhs * pr.ndof;
+  const T* uin = (par ? pr.ua : pr.ub) + roff;
+  T* dst_u = (par ? pr.ub : pr.ua) + roff;
+  T* dst_d = pr.d + roff;
+  const uint32_t nbytes = (uint32_t)((pr.n[0] * P + 1) * (int64_t)(pr.n[1] * P + 1) * sizeof(T));
   const __amdgpu_buffer_rsrc_t ursrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)uin, (short)0, (int)nbytes, 0x00020000);
+  const double t = pr.t0 + j * pr.dt;
 
   // ---- entry: issue every load of the tile ----
   T areg[NMB][NKS];
@@ -84,7 +121,7 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
 #pragma unroll
     for (int kk = 0; kk < NKS; ++kk) {
       const int r = mb * 16 + lc, cc = 4 * kk + lk;
-      const T v = a.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
+      const T v = pr.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
       areg[mb][kk] = (r < NL && cc < NL) ? v : T(0);
     }
   int inf_r[NCI];
@@ -92,8 +129,8 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
   for (int it = 0; it < NCI; ++it) {
     const int c = tid + it * 256;
     const int gx = rcx0 + c % RCX, gy = rcy0 + c / RCX;
-    const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1];
-    const int v = a.info[in ? gx + a.n[0] * gy : 0];
+    const bool in = c < NRC && gx >= 0 && gx < pr.n[0] && gy >= 0 && gy < pr.n[1];
+    const int v = pr.info[in ? gx + pr.n[0] * gy : 0];
     inf_r[it] = in ? v : kInfoOut;
   }
   // region rows straight into LDS; lanes left of the grid or past the array read 0,
@@ -109,14 +146,19 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
         buffer_dword_to_lds<T>(ursrc, rowbyte + dw * 4, (uint32_t*)(u_s + ry * W) + ch * 64);
     }
   }
-  T d_r[NRW], im_r[NRW];
+  // owned rows of d and M^{-1}, straight into LDS as well (row oy -> slot oy)
+  const __amdgpu_buffer_rsrc_t drsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dst_d, (short)0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t mrsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)pr.invm, (short)0, (int)nbytes, 0x00020000);
+  for (int oy = wave; oy < ony; oy += 4) {
+    const int rowbyte = ((oy0 + oy) * npx + ox0) * (int)sizeof(T);
 #pragma unroll
-  for (int k = 0; k < NRW; ++k) {
-    const int oy = wave + 4 * k;
-    const bool own = oy < ony && lane < min(onx, OWX);
-    const uint32_t node = own ? (uint32_t)((oy0 + oy) * npx + ox0 + lane) : 0u;
-    d_r[k] = dst_d[node];
-    im_r[k] = a.invm[node];
+    for (int ch = 0; ch < DPE; ++ch) {
+      const int dw = ch * 64 + lane;
+      buffer_dword_to_lds<T>(drsrc, rowbyte + dw * 4, (uint32_t*)(d_s + oy * 64) + ch * 64);
+      buffer_dword_to_lds<T>(mrsrc, rowbyte + dw * 4, (uint32_t*)(m_s + oy * 64) + ch * 64);
+    }
   }
   for (int i = tid; i < RNY * W; i += 256) r_s[i] = T(0);
 #pragma unroll
@@ -127,12 +169,12 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
   if (tid == 0) {
     src_on = 0;
     ft_s = 0.0;
-    if (a.src != nullptr) {
-      const SourceDev& s = a.src[rhs];
+    if (pr.src != nullptr) {
+      const SourceDev& s = pr.src[rhs];
       const int sx0 = s.cell[0] * P, sy0 = s.cell[1] * P;
       if (sx0 + P >= ox0 && sx0 < ox0 + onx && sy0 + P >= oy0 && sy0 < oy0 + ony) {
         src_on = 1;
-        ft_s = ricker(a.t, s.f0);
+        ft_s = ricker(t, s.f0);
       }
     }
   }
@@ -146,6 +188,16 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
     const int j = min(4 * kk + lk, NL - 1);
     offk[kk] = (j % NP1) + (j / NP1) * W;
   }
+  // output rows of this lane (MFMA D layout) and their node offsets in a cell
+  int offo[NMB][4];
+#pragma unroll
+  for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = mb * 16 + Mma<T>::row(lk, r);
+      offo[mb][r] = (i < NL) ? (i % NP1) + (i / NP1) * W : -1;
+    }
+  using Bits = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
 #pragma unroll
   for (int color = 0; color < 4; ++color) {
     const int px = color & 1, py = color >> 1;
@@ -158,11 +210,18 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
       const int c = lx + RCX * ly;
       const bool valid = (b * 16 + lc < ncol) && (info_s[c] == kInfoUncut);
       const int base = lx * P + ly * P * W;
+      // every lane loads; invalid cells and padded rows are masked by bits (the
+      // masked values may be stale LDS contents, never arithmetic on them)
+      const Bits vmask = valid ? ~Bits(0) : Bits(0);
       T bv[NKS];
 #pragma unroll
       for (int kk = 0; kk < NKS; ++kk) {
+        const Bits m = (4 * kk + lk < NL) ? vmask : Bits(0);
         const T v = u_s[base + offk[kk]];
-        bv[kk] = (valid && 4 * kk + lk < NL) ? v : T(0);
+        Bits vb;
+        __builtin_memcpy(&vb, &v, sizeof(T));
+        vb &= m;
+        __builtin_memcpy(&bv[kk], &vb, sizeof(T));
       }
       typename Mma<T>::acc acc[NMB];
 #pragma unroll
@@ -171,14 +230,20 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
       for (int kk = 0; kk < NKS; ++kk)
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) acc[mb] = Mma<T>::mma(areg[mb][kk], bv[kk], acc[mb]);
+      // read-add-write into the node accumulator: no two lanes or waves of a class
+      // touch one node, so every node receives its contributions in class order; all
+      // reads of the lane are issued before the first write
+      T cur[NMB][4];
+#pragma unroll
+      for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cur[mb][r] = r_s[base + max(offo[mb][r], 0)];
       if (valid) {
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = mb * 16 + Mma<T>::row(lk, r);
-            if (i < NL) r_s[base + (i % NP1) + (i / NP1) * W] += acc[mb][r];
-          }
+          for (int r = 0; r < 4; ++r)
+            if (offo[mb][r] >= 0) r_s[base + offo[mb][r]] = cur[mb][r] + acc[mb][r];
       }
     }
     // cut cells of the class: one wave per cell, lanes = rows of K_e
@@ -195,7 +260,7 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
         const int lx = px + 2 * (ci % nxc), ly = py + 2 * (ci / nxc);
         const int q = info_s[lx + RCX * ly];
         const int base = lx * P + ly * P * W;
-        const T* K = a.kcut + (int64_t)q * NPK;
+        const T* K = pr.kcut + (int64_t)q * NPK;
         const int i = min(lane, NL - 1);
         // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
         // small lumped masses of cut-cell nodes amplify any error in their sum
@@ -212,28 +277,45 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
   }
 
   // ---- update, one owned row per wave instruction ----
-  const T dt2 = a.dt2;
-  const bool half = a.start != 0;
-  const SourceDev* src = a.src;
-#pragma unroll
-  for (int k = 0; k < NRW; ++k) {
-    const int oy = wave + 4 * k;
-    if (oy >= ony) continue;
-    for (int xx = lane; xx < onx; xx += 64) {
-      const bool pre = xx < OWX;  // nodes beyond one wave (last column) load here
-      const int gx = ox0 + xx, gy = oy0 + oy;
-      const uint32_t node = (uint32_t)(gy * npx + gx);
-      const int rl = (gx - rnx0) + (gy - rny0) * W;
+  const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
+  const __amdgpu_buffer_rsrc_t drs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dst_d, (short)0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t urs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dst_u, (short)0, (int)nbytes, 0x00020000);
+  const int nx64 = min(onx, OWX);
+  const bool srcflag = src_on != 0;
+  for (int oy = wave; oy < ony; oy += 4) {
+    const int gy = oy0 + oy;
+    const int rowbyte = (gy * npx + ox0) * (int)sizeof(T);
+    const int rl0 = (ox0 - rnx0) + (gy - rny0) * W;
+    if (lane < nx64) {
+      const int rl = rl0 + lane;
       T F = T(0);
-      if (src_on) {
-        const int sx = gx - src[rhs].cell[0] * P, sy = gy - src[rhs].cell[1] * P;
-        if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * src[rhs].b[sx + NP1 * sy]);
+      if (srcflag) {
+        const int sx = ox0 + lane - pr.src[rhs].cell[0] * P, sy = gy - pr.src[rhs].cell[1] * P;
+        if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
       }
-      const T im = pre ? im_r[k] : a.invm[node];
-      const T dv = pre ? d_r[k] : dst_d[node];
-      T acc = dt2 * im * (F - r_s[rl]);
-      if (half) acc = acc * T(0.5);
-      const T dn = dv + acc;
+      const T dn = d_s[oy * 64 + lane] + dt2h * m_s[oy * 64 + lane] * (F - r_s[rl]);
+      const T un = u_s[rl] + dn;
+      const int vo = rowbyte + lane * (int)sizeof(T);
+      if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dn), drs, vo, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, un), urs, vo, 0, 0);
+      } else {
+        dst_d[(uint32_t)(gy * npx + ox0 + lane)] = dn;
+        dst_u[(uint32_t)(gy * npx + ox0 + lane)] = un;
+      }
+    }
+    if (onx > OWX && lane == 0) {  // the last node column of the grid
+      const int gx = ox0 + OWX;
+      const uint32_t node = (uint32_t)(gy * npx + gx);
+      const int rl = rl0 + OWX;
+      T F = T(0);
+      if (srcflag) {
+        const int sx = gx - pr.src[rhs].cell[0] * P, sy = gy - pr.src[rhs].cell[1] * P;
+        if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
+      }
+      const T dn = dst_d[node] + dt2h * pr.invm[node] * (F - r_s[rl]);
       dst_d[node] = dn;
       dst_u[node] = u_s[rl] + dn;
     }
@@ -241,45 +323,17 @@ __global__ __launch_bounds__(256) void step2d_kernel(StepArgs<T> a) {
 }
 
 template <typename T, int P, int TY>
-static fcw_status run2d(Ctx& c, int nrhs, const void* uin, void* uout, void* d, double t,
-                        double dt, int start) {
-  StepArgs<T> a{};
-  constexpr int TX = 64 / P;
-  a.info = c.d_info;
-  a.kref = (const T*)c.d_kref_s;
-  a.kcut = (const T*)c.d_kcut_s;
-  a.invm = (const T*)c.d_invm;
-  a.n[0] = c.ncells[0];
-  a.n[1] = c.ncells[1];
-  a.n[2] = 1;
-  a.np[0] = c.npts[0];
-  a.np[1] = c.npts[1];
-  a.np[2] = 1;
-  a.ntile[0] = (a.n[0] + TX - 1) / TX;
-  a.ntile[1] = (a.n[1] + TY - 1) / TY;
-  a.ntile[2] = 1;
-  a.ntiles = a.ntile[0] * a.ntile[1];
-  a.chunk = (a.ntiles + 7) / 8;
-  a.nnodes = c.nnodes;
-  a.ndof = c.ndof;
-  a.u_in = (const T*)uin;
-  a.u_out = (T*)uout;
-  a.d = (T*)d;
-  a.dt2 = (T)(dt * dt);
-  a.start = start;
-  a.src = c.d_src;
-  a.t = t;
-  dim3 grid(8 * a.chunk, nrhs, 1);
-  step2d_kernel<T, P, TY><<<grid, 256, 0, c.stream>>>(a);
+static fcw_status run2d(hipStream_t stream, const void* probs, const int4* items, int nitems,
+                        int j) {
+  const int chunk = (nitems + 7) / 8;
+  step2d_kernel<T, P, TY><<<8 * chunk, 256, 0, stream>>>((const Prob2d<T>*)probs, items, nitems,
+                                                         chunk, j);
   FCW_HIP(hipGetLastError());
   return FCW_OK;
 }
 
 // 2-D step kernels offered to the autotuner: (P, TY) -> launcher; TX = 64 / P.
-using Run2d = fcw_status (*)(Ctx&, int, const void*, void*, void*, double, double, int);
-
-int step2d_candidates(const Ctx& c, int i, Run2d* fn, int tile[3]) {
-  if (c.dim != 2 || c.ncomp != 1) return 0;
+int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
   struct E { int p, ty; Run2d f32, f64; };
 #define FCW_E(PP, TY) E{PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
@@ -288,14 +342,51 @@ int step2d_candidates(const Ctx& c, int i, Run2d* fn, int tile[3]) {
 #undef FCW_E
   int n = 0;
   for (const E& e : table) {
-    if (e.p != c.p) continue;
+    if (e.p != p) continue;
     if (n == i) {
-      if (fn) *fn = (c.precision == FCW_FP64) ? e.f64 : e.f32;
+      if (fn) *fn = fp64 ? e.f64 : e.f32;
       if (tile) { tile[0] = 64 / e.p; tile[1] = e.ty; tile[2] = 1; }
     }
     ++n;
   }
   return n;
+}
+
+size_t prob2d_size(int fp64) { return fp64 ? sizeof(Prob2d<double>) : sizeof(Prob2d<float>); }
+
+template <typename T>
+static void fill_prob(const Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
+                      int nsteps, int start, int tx, int ty, const SourceDev* src) {
+  Prob2d<T> p{};
+  p.ua = (T*)ua;
+  p.ub = (T*)ub;
+  p.d = (T*)d;
+  p.invm = (const T*)c.d_invm;
+  p.info = c.d_info;
+  p.kref = (const T*)c.d_kref_s;
+  p.kcut = (const T*)c.d_kcut_s;
+  p.src = src;
+  p.n[0] = c.ncells[0];
+  p.n[1] = c.ncells[1];
+  p.np[0] = c.npts[0];
+  p.np[1] = c.npts[1];
+  p.ntile[0] = (c.ncells[0] + tx - 1) / tx;
+  p.ntile[1] = (c.ncells[1] + ty - 1) / ty;
+  p.ndof = c.ndof;
+  p.t0 = t0;
+  p.dt = dt;
+  p.dt2 = (T)(dt * dt);
+  p.nsteps = nsteps;
+  p.start = start;
+  std::memcpy(out, &p, sizeof p);
+}
+
+void prob2d_fill(const Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
+                 int nsteps, int start, int tx, int ty, const SourceDev* src) {
+  if (c.precision == FCW_FP64)
+    fill_prob<double>(c, out, ua, ub, d, t0, dt, nsteps, start, tx, ty, src);
+  else
+    fill_prob<float>(c, out, ua, ub, d, t0, dt, nsteps, start, tx, ty, src);
 }
 
 }  // namespace fcw

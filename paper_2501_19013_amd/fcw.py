@@ -25,7 +25,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
-           "fcw_autotune", "fcw_tile_config", "fcw_select_tile",
+           "fcw_autotune", "fcw_tile_config", "fcw_select_tile", "fcw_run",
            "fcw_export", "fcw_destroy", "fcw_last_error")
 
 
@@ -41,6 +41,15 @@ class ProblemDesc(C.Structure):
 class Source(C.Structure):
     _fields_ = [("x", C.c_double * 3), ("dir", C.c_double * 3), ("f0", C.c_double),
                 ("amp", C.c_double)]
+
+
+class RunItem(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("nrhs", C.c_int32), ("u", C.c_void_p), ("d", C.c_void_p),
+                ("src", C.POINTER(Source)), ("t0", C.c_double), ("dt", C.c_double),
+                ("nsteps", C.c_int32), ("start", C.c_int32)]
+
+
+FCW_RUN_GRAPH = 1
 
 
 class Info(C.Structure):
@@ -82,6 +91,7 @@ def load(path=LIB_PATH):
     lib.fcw_autotune.argtypes = [vp, i32, i32, C.POINTER(i32)]
     lib.fcw_tile_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(f64), C.POINTER(i32)]
     lib.fcw_select_tile.argtypes = [vp, i32]
+    lib.fcw_run.argtypes = [C.POINTER(RunItem), i32, i32]
     lib.fcw_destroy.argtypes = [vp]
     lib.fcw_destroy.restype = None
     lib.fcw_last_error.argtypes = []
@@ -197,6 +207,25 @@ def tile_configs(ctx):
         _check(lib.fcw_tile_config(ctx, i, t, C.byref(us), None))
         out.append(dict(tile=tuple(t), us_per_step=us.value))
     return out
+
+
+def run(entries, graph=False):
+    """fcw_run: entries are dicts with ctx, nrhs, u, d, sources, t0, dt, nsteps, start."""
+    arr = (RunItem * len(entries))()
+    keep = []
+    for i, e in enumerate(entries):
+        srcs = _sources(e.get("sources"))
+        keep.append(srcs)
+        arr[i].ctx = e["ctx"].value if isinstance(e["ctx"], C.c_void_p) else e["ctx"]
+        arr[i].nrhs = int(e["nrhs"])
+        arr[i].u = _ptr(e["u"])
+        arr[i].d = _ptr(e["d"])
+        arr[i].src = C.cast(srcs, C.POINTER(Source)) if srcs is not None else None
+        arr[i].t0 = float(e.get("t0", 0.0))
+        arr[i].dt = float(e.get("dt", 0.0))
+        arr[i].nsteps = int(e["nsteps"])
+        arr[i].start = int(e.get("start", 0))
+    _check(load().fcw_run(arr, len(entries), FCW_RUN_GRAPH if graph else 0))
 
 
 def select_tile(ctx, i):
