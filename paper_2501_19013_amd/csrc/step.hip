@@ -537,7 +537,7 @@ bool step_supported(const Ctx& c) {
   return select_for(c, c.precision == FCW_FP64) != nullptr && select_for(c, true) != nullptr;
 }
 
-using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int);
+using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int, const void*, int);
 int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]);
 size_t prob2d_size(int fp64);
 void prob2d_fill(const Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
@@ -607,7 +607,7 @@ fcw_status run_group2d(Ctx& owner, Run2d fn, const std::vector<char>& records, i
   if (st) return st;
   const int4* ditems = (const int4*)((char*)owner.d_wl + rb);
   for (int j = 0; j < nsteps; ++j) {
-    st = fn(owner.stream, owner.d_wl, ditems, (int)items.size(), j);
+    st = fn(owner.stream, owner.d_wl, ditems, (int)items.size(), j, nullptr, 0);
     if (st) return st;
   }
   return FCW_OK;
@@ -666,7 +666,7 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     hipGraph_t g = nullptr;
     FCW_HIP(hipStreamBeginCapture(owner.stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < nmax && st == FCW_OK; ++j)
-      st = sc.f2d(owner.stream, owner.d_wl, ditems, nitems, j);
+      st = sc.f2d(owner.stream, owner.d_wl, ditems, nitems, j, nullptr, 0);
     hipError_t e = hipStreamEndCapture(owner.stream, &g);
     if (st) return st;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -699,11 +699,13 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
     std::vector<char> rec(prob2d_size(fp64));
     prob2d_fill(c, rec.data(), u, scratch, d, t0, dt, nsteps, start, sc.tile[0], sc.tile[1],
                 c.d_src);
-    std::vector<int4> items;
-    items.reserve((size_t)ntx * nty * nrhs);
-    for (int t = 0; t < ntx * nty; ++t)
-      for (int r = 0; r < nrhs; ++r) items.push_back(make_int4(0, r, t, 0));
-    return run_group2d(c, sc.f2d, rec, 1, items, nsteps);
+    // one problem: its record goes by value, items are implicit (tile-major, rhs fastest)
+    const int nitems = ntx * nty * nrhs;
+    for (int j = 0; j < nsteps; ++j) {
+      fcw_status st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs);
+      if (st) return st;
+    }
+    return FCW_OK;
   }
   void* a = (nsteps % 2 == 1) ? scratch : u;
   void* b = (nsteps % 2 == 1) ? u : scratch;

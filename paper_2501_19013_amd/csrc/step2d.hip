@@ -26,7 +26,7 @@
 
 namespace fcw {
 
-using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int);
+using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int, const void*, int);
 
 template <typename T>
 __device__ static inline void buffer_dword_to_lds(__amdgpu_buffer_rsrc_t rsrc, int voffset,
@@ -53,10 +53,11 @@ struct Prob2d {
   int nsteps, start;
 };
 
-template <typename T, int P, int TY>
+// SINGLE: one problem whose record comes by value; item = tile * nrhs + rhs.
+template <typename T, int P, int TY, bool SINGLE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void step2d_kernel(
-    const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, int nitems, int chunk,
-    int j) {
+    const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, const Prob2d<T> one,
+    int nrhs1, int nitems, int chunk, int j) {
   constexpr int NP1 = P + 1;
   constexpr int NL = NP1 * NP1;
   constexpr int NMB = (NL + 15) / 16;
@@ -88,8 +89,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   // blocks b, b+8, ... run on one XCD: give them consecutive items
   const int item = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
   if (item >= nitems) return;
-  const int4 wi = items[item];
-  const Prob2d<T>& pr = probs[wi.x];
+  const int4 wi = SINGLE ? make_int4(0, item % nrhs1, item / nrhs1, 0) : items[item];
+  const Prob2d<T>& pr = SINGLE ? one : probs[wi.x];
   if (j >= pr.nsteps) return;  // this problem has finished its steps
   const int rhs = wi.y;
   const int tid = threadIdx.x;
@@ -322,12 +323,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   }
 }
 
+// probs/items: device work list; when `one` is given (a host record of a single
+// problem with nrhs1 right-hand sides) it is passed by value instead.
 template <typename T, int P, int TY>
 static fcw_status run2d(hipStream_t stream, const void* probs, const int4* items, int nitems,
-                        int j) {
+                        int j, const void* one, int nrhs1) {
   const int chunk = (nitems + 7) / 8;
-  step2d_kernel<T, P, TY><<<8 * chunk, 256, 0, stream>>>((const Prob2d<T>*)probs, items, nitems,
-                                                         chunk, j);
+  if (one) {
+    Prob2d<T> rec;
+    std::memcpy(&rec, one, sizeof rec);
+    step2d_kernel<T, P, TY, true><<<8 * chunk, 256, 0, stream>>>(nullptr, nullptr, rec, nrhs1,
+                                                                 nitems, chunk, j);
+  } else {
+    step2d_kernel<T, P, TY, false><<<8 * chunk, 256, 0, stream>>>(
+        (const Prob2d<T>*)probs, items, Prob2d<T>{}, 1, nitems, chunk, j);
+  }
   FCW_HIP(hipGetLastError());
   return FCW_OK;
 }
