@@ -161,6 +161,12 @@ fcw_status fcw_tile_config(const fcw_ctx* ctx, int32_t i, int32_t tile[3], doubl
 /* Use tile configuration i (as listed by fcw_tile_config) for later steps. */
 fcw_status fcw_select_tile(fcw_ctx* ctx, int32_t i);
 
+/* Queue the context's later work on another stream (a hipStream_t; NULL means the
+ * default stream), for instance to set a problem up on one stream and step it on
+ * another.  Synchronises the old stream first, so nothing queued there is still
+ * running when work arrives on the new one. */
+fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
+
 /* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
 fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,
                          const fcw_source* src, double t0, double dt, int32_t nsteps);

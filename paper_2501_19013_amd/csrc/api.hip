@@ -469,6 +469,16 @@ fcw_status fcw_select_tile(fcw_ctx* c, int32_t i) {
   return FCW_OK;
 }
 
+fcw_status fcw_set_stream(fcw_ctx* c, void* stream) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  // work already queued on the old stream completes before later work is queued elsewhere
+  FCW_HIP(hipStreamSynchronize(c->stream));
+  c->stream = (hipStream_t)stream;
+  return FCW_OK;
+}
+
 fcw_status fcw_step_imex(fcw_ctx* c, int32_t, void*, void*, void*, const fcw_source*, double,
                          double, int32_t) {
   g_err.clear();

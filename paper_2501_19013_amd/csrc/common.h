@@ -87,6 +87,7 @@ struct Ctx {
   SourceDev* d_src = nullptr;
   bool d_src_active = false;  // the sources of the current batched call are set
   int src_cap = 0;
+  std::vector<fcw_source> src_staged;  // host copy of the sources d_src was computed from
   // work list of the persistent step kernel (device + pinned staging)
   void* d_wl = nullptr;
   void* h_wl = nullptr;
