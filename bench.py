@@ -95,7 +95,30 @@ def run_gpu(cfg, precision, steps, warmup, dt=None):
     out = u[0].double().cpu().numpy()
     s.close()
     return dict(ms=ms, dt=dt, info=info, cls=cls, active=int((mass > 0).sum()) * cfg.get("ncomp", 1),
-                u=out, tile=table[chosen]["tile"])
+                u=out, tile=table[chosen]["tile"], kernel=table[chosen]["kernel"])
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summaries under
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when none
+    was taken or the kernel's source has changed since."""
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("paper_2501_19013_amd/csrc/step2d.hip", "paper_2501_19013_amd/csrc/step_common.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        fields = {}
+        with open(path) as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                if k in ("kernel", "traffic_bytes_per_launch", "source_sha1"):
+                    fields[k] = v.split()[0] if k == "source_sha1" else v.strip()
+        if fields.get("kernel") == kernel and fields.get("source_sha1") == sha:
+            return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(cfg, dt, nsteps):
@@ -155,9 +178,8 @@ def main():
     B = algorithmic_bytes(cfg, info, r32["cls"], 4)
     achieved = B / (ms_step * 1e-3) / 1e9
     res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=achieved / HBM_PEAK_GBS, traffic=None,
-                           kernel="fcw::tile_kernel<float,2,4,1,%d,%d,%d,0>" % tuple(r32["tile"]),
-                           algorithmic_bytes_per_step=B)
+                           frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(r32["kernel"]),
+                           kernel=r32["kernel"], algorithmic_bytes_per_step=B)
     res["config"] = dict(workload="c2: 2-D scalar wave, [0,1]^2, 40 random circular voids "
                                   "(r 0.01-0.05, seed 2), 512x512 cells, p=4 GLL, FP32 step, "
                                   "FP64 setup, Ricker f0=10 at (0.1,0.1), dt=0.9 dt_crit",

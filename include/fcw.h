@@ -158,6 +158,11 @@ fcw_status fcw_autotune(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, int32_t* cho
 fcw_status fcw_tile_config(const fcw_ctx* ctx, int32_t i, int32_t tile[3], double* us_per_step,
                            int32_t* count);
 
+/* Name of the step kernel of tile configuration i, as a profiler prints it (for
+ * example "fcw::step2d_kernel<float, 4, 16, true>"), zero-terminated into buf of cap
+ * bytes.  FCW_E_ARG when i is out of range or buf is too small. */
+fcw_status fcw_tile_name(const fcw_ctx* ctx, int32_t i, char* buf, int32_t cap);
+
 /* Use tile configuration i (as listed by fcw_tile_config) for later steps. */
 fcw_status fcw_select_tile(fcw_ctx* ctx, int32_t i);
 

@@ -456,6 +456,24 @@ fcw_status fcw_tile_config(const fcw_ctx* c, int32_t i, int32_t tile[3], double*
   return FCW_OK;
 }
 
+fcw_status fcw_tile_name(const fcw_ctx* c, int32_t i, char* buf, int32_t cap) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  std::string name;
+  const int n = tile_candidates(*c, i, nullptr, &name);
+  if (i < 0 || i >= n) {
+    set_error("tile configuration %d out of range [0, %d)", i, n);
+    return FCW_E_ARG;
+  }
+  if (!buf || cap < (int32_t)name.size() + 1) {
+    set_error("name buffer needs %d bytes", (int)name.size() + 1);
+    return FCW_E_ARG;
+  }
+  std::memcpy(buf, name.c_str(), name.size() + 1);
+  return FCW_OK;
+}
+
 fcw_status fcw_select_tile(fcw_ctx* c, int32_t i) {
   g_err.clear();
   fcw_status st = check_ctx(c, 1);

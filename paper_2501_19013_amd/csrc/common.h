@@ -125,7 +125,7 @@ fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
 // step.hip
 bool step_supported(const Ctx& c);
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);
-int tile_candidates(const Ctx& c, int i, int tile[3]);
+int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name = nullptr);
 fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scratch, double t0,
                      double dt, int nsteps, int start);
 // one batched group of 2-D problems (see fcw_run)

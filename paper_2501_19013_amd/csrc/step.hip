@@ -21,7 +21,9 @@
 //    neighbouring tiles, so halo rows are shared through that XCD's L2).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "step_common.h"
@@ -567,11 +569,23 @@ static int step_candidates(const Ctx& c, int i, StepCand* out) {
   return n2 + ng;
 }
 
-int tile_candidates(const Ctx& c, int i, int tile[3]) {
+int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name) {
   StepCand sc;
   const int n = step_candidates(c, i, &sc);
-  if (tile && i >= 0 && i < n)
+  if (i < 0 || i >= n) return n;
+  if (tile)
     for (int k = 0; k < 3; ++k) tile[k] = sc.tile[k];
+  if (name) {
+    // the kernel's name as a profiler prints it (single-problem launches)
+    const char* t = c.precision == FCW_FP64 ? "double" : "float";
+    char b[128];
+    if (sc.f2d)
+      std::snprintf(b, sizeof b, "fcw::step2d_kernel<%s, %d, %d, true>", t, c.p, sc.tile[1]);
+    else
+      std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d>", t, c.dim,
+                    c.p, c.ncomp, sc.tile[0], sc.tile[1], sc.tile[2], (int)kModeStep);
+    *name = b;
+  }
   return n;
 }
 

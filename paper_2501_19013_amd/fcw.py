@@ -25,7 +25,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
-           "fcw_autotune", "fcw_tile_config", "fcw_select_tile", "fcw_set_stream", "fcw_run",
+           "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_run",
            "fcw_export", "fcw_destroy", "fcw_last_error")
 
 
@@ -91,6 +91,7 @@ def load(path=LIB_PATH):
     lib.fcw_autotune.argtypes = [vp, i32, i32, C.POINTER(i32)]
     lib.fcw_tile_config.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(f64), C.POINTER(i32)]
     lib.fcw_select_tile.argtypes = [vp, i32]
+    lib.fcw_tile_name.argtypes = [vp, i32, C.c_char_p, i32]
     lib.fcw_set_stream.argtypes = [vp, vp]
     lib.fcw_run.argtypes = [C.POINTER(RunItem), i32, i32]
     lib.fcw_destroy.argtypes = [vp]
@@ -206,7 +207,9 @@ def tile_configs(ctx):
         t = (C.c_int32 * 3)()
         us = C.c_double()
         _check(lib.fcw_tile_config(ctx, i, t, C.byref(us), None))
-        out.append(dict(tile=tuple(t), us_per_step=us.value))
+        name = C.create_string_buffer(256)
+        _check(lib.fcw_tile_name(ctx, i, name, 256))
+        out.append(dict(tile=tuple(t), us_per_step=us.value, kernel=name.value.decode()))
     return out
 
 
