@@ -13,10 +13,13 @@ events on the solver's stream around exactly --steps steps (inputs resident in H
 The FP32 result is compared with the FP64 GPU path after the same steps (relative L2
 over all DOFs); the FP64 path itself is held to the FP64 oracle by the test suite.
 
-Roofline: algorithmic bytes per step B = 3 s N_dof + s N_cutadj + N_cut (n_loc(n_loc+1)/2
-s + 4) + N_cells / 8 (read u_k and u_{k-1}, write u_{k+1}; the non-analytic inverse
-masses next to cut cells; the packed cut-cell matrices; one class bit per cell), divided
-by the average duration of one step kernel, against 8 TB/s of HBM3E.
+Roofline: a step is two kernels, the cut-cell product kernel (it streams the packed
+cut-cell matrices, N_cut (n_loc(n_loc+1)/2 s + 4) bytes) and the main step kernel (the
+state: 3 s N_dof + s N_cutadj + N_cells / 8 bytes -- read u_k and u_{k-1}, write u_{k+1};
+the non-analytic inverse masses next to cut cells; one class bit per cell).  Each
+kernel's algorithmic bytes are divided by its own average launch duration, measured
+with HIP events around every launch on the solver's stream, against 8 TB/s of HBM3E;
+`roofline` reports the main kernel, which dominates the step time.
 
 cpu_baseline: the FP64 numpy oracle (single BLAS thread) stepping the same full-size
 problem for a bounded number of steps on the host.
@@ -37,8 +40,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(cfg, info, cls, s_state):
-    """Per-step algorithmic bytes (see module docstring)."""
+def algorithmic_bytes(cfg, info, cls, s_state, part="step"):
+    """Per-step algorithmic bytes (see module docstring).  part="main": the state terms
+    moved by the main step kernel; part="cut": the packed cut-cell matrices streamed by
+    the cut-cell kernel; "step": both."""
     p, dim = cfg["p"], cfg["dim"]
     ncells = np.array(cfg["ncells"])
     nl = info["n_loc"]
@@ -61,8 +66,9 @@ def algorithmic_bytes(cfg, info, cls, s_state):
                     mark[cz * p + a, cy * p + b, cx * p + c] = True
     n_cutadj = int(mark.sum()) * cfg.get("ncomp", 1)
     n_cut = info["n_cut"]
-    return (3 * s_state * n_dof + s_state * n_cutadj + n_cut * (nl * (nl + 1) // 2 * s_state + 4)
-            + int(np.prod(ncells)) / 8.0)
+    main = 3 * s_state * n_dof + s_state * n_cutadj + int(np.prod(ncells)) / 8.0
+    cut = n_cut * (nl * (nl + 1) // 2 * s_state + 4)
+    return {"main": main, "cut": cut, "step": main + cut}[part]
 
 
 def run_gpu(cfg, precision, steps, warmup, dt=None):
@@ -89,13 +95,26 @@ def run_gpu(cfg, precision, steps, warmup, dt=None):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # per-kernel durations (HIP events around every launch, on the solver's stream) from a
+    # second pass over scratch state, so the timed state above is not disturbed
+    u2, d2 = s.zeros(1), s.zeros(1)
+    fcw.timing(s.ctx, 1)
+    s.step(u2, d2, src, dt, steps, t0=0.0, start=True)
+    kms = {w: fcw.timing_read(s.ctx, w) for w in (0, 1)}
+    fcw.timing(s.ctx, 0)
+    del u2, d2
     cls = s.export(fcw.ARR_CELL_CLASS)
     mass = s.export(fcw.ARR_MASS)
     info = dict(s.info)
     out = u[0].double().cpu().numpy()
     s.close()
-    return dict(ms=ms, dt=dt, info=info, cls=cls, active=int((mass > 0).sum()) * cfg.get("ncomp", 1),
-                u=out, tile=table[chosen]["tile"], kernel=table[chosen]["kernel"])
+    return dict(ms=ms, steps=steps, dt=dt, info=info, cls=cls, active=int((mass > 0).sum()) * cfg.get("ncomp", 1),
+                u=out, tile=table[chosen]["tile"], kernel=table[chosen]["kernel"],
+                main_ms=kms[0][0] / max(kms[0][1], 1), main_launches=kms[0][1],
+                cut_ms=kms[1][0] / max(kms[1][1], 1), cut_launches=kms[1][1],
+                cut_kernel="fcw::cut_apply_kernel<%s, %d, %d, %d, true>" % (
+                    "float" if precision == "fp32" else "double", cfg["dim"], cfg["p"],
+                    cfg.get("ncomp", 1)))
 
 
 def measured_traffic(kernel):
@@ -137,6 +156,52 @@ def cpu_baseline(cfg, dt, nsteps):
                        f"FP64 numpy, 1 thread, {el:.1f} s")
 
 
+def roofline(cfg, r):
+    """Roofline of the dominant (main) step kernel from its own event-timed launches,
+    plus the cut-cell kernel and the whole step."""
+    Bm = algorithmic_bytes(cfg, r["info"], r["cls"], 4, "main")
+    Bc = algorithmic_bytes(cfg, r["info"], r["cls"], 4, "cut")
+    am = Bm / (r["main_ms"] * 1e-3) / 1e9
+    out = dict(bound="hbm", achieved=am, peak=HBM_PEAK_GBS, unit="GB/s", frac=am / HBM_PEAK_GBS,
+               traffic=measured_traffic(r["kernel"]), kernel=r["kernel"],
+               algorithmic_bytes_per_launch=Bm, avg_launch_ms=r["main_ms"],
+               launches_timed=r["main_launches"])
+    if r["cut_launches"]:
+        ac = Bc / (r["cut_ms"] * 1e-3) / 1e9
+        out["cut_kernel"] = dict(kernel=r["cut_kernel"], achieved=ac, frac=ac / HBM_PEAK_GBS,
+                                 algorithmic_bytes_per_launch=Bc, avg_launch_ms=r["cut_ms"],
+                                 launches_timed=r["cut_launches"])
+    ms_step = r["ms"] / r["steps"]
+    out["whole_step"] = dict(achieved=(Bm + Bc) / (ms_step * 1e-3) / 1e9,
+                             frac=(Bm + Bc) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                             algorithmic_bytes=Bm + Bc, ms=ms_step)
+    return out
+
+
+def bench_c3(steps, warmup, with_fp64):
+    """3-D elastic workload: 96^3 cells, p=2, random spherical pores (porosity 0.2)."""
+    import workloads
+    cfg = workloads.config("c3")
+    r32 = run_gpu(cfg, "fp32", steps, warmup)
+    print(f"[bench] c3 fp32: {steps} steps in {r32['ms']:.2f} ms", file=sys.stderr, flush=True)
+    ms_step = r32["ms"] / steps
+    out = dict(workload="c3: 3-D elastic wave, unit cube, random spherical pores (porosity 0.2, "
+                        "r 0.02-0.06, seed 3), 96^3 cells, p=2 GLL, 3 components, FP32 step, FP64 "
+                        "setup, Ricker point force e_x at (0.1,0.1,0.1), dt=0.9 dt_crit",
+               value=r32["active"] * steps / (r32["ms"] * 1e-3), unit="DOF-updates/s",
+               ms_per_step=ms_step, steps=steps, warmup=warmup,
+               ndof=r32["info"]["ndof"], active_dof=r32["active"], n_cut=r32["info"]["n_cut"],
+               dt=r32["dt"], roofline=roofline(cfg, r32))
+    if with_fp64:
+        r64 = run_gpu(cfg, "fp64", steps, warmup, dt=r32["dt"])
+        print(f"[bench] c3 fp64: {steps} steps in {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
+        out["fp64_gpu"] = dict(value=r64["active"] * steps / (r64["ms"] * 1e-3),
+                               ms_per_step=r64["ms"] / steps)
+        out["speedup_vs_fp64_gpu"] = out["value"] / out["fp64_gpu"]["value"]
+        out["rel_l2_vs_fp64"] = float(np.linalg.norm(r32["u"] - r64["u"]) / np.linalg.norm(r64["u"]))
+    return out
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -156,6 +221,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter scale)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
+    ap.add_argument("--c3-steps", type=int, default=1000)
+    ap.add_argument("--c3-warmup", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -175,11 +243,7 @@ def main():
     res["value"] = r32["active"] * args.steps / (r32["ms"] * 1e-3)
     res["ms_per_step"] = ms_step
     info = r32["info"]
-    B = algorithmic_bytes(cfg, info, r32["cls"], 4)
-    achieved = B / (ms_step * 1e-3) / 1e9
-    res["roofline"] = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic(r32["kernel"]),
-                           kernel=r32["kernel"], algorithmic_bytes_per_step=B)
+    res["roofline"] = roofline(cfg, r32)
     res["config"] = dict(workload="c2: 2-D scalar wave, [0,1]^2, 40 random circular voids "
                                   "(r 0.01-0.05, seed 2), 512x512 cells, p=4 GLL, FP32 step, "
                                   "FP64 setup, Ricker f0=10 at (0.1,0.1), dt=0.9 dt_crit",
@@ -199,6 +263,8 @@ def main():
         cb = cpu_baseline(cfg, r32["dt"], args.cpu_steps)
         res["cpu_baseline"] = cb
         print(f"[bench] cpu baseline: {cb['sample']}", file=sys.stderr, flush=True)
+    if not args.no_c3:
+        res["c3"] = bench_c3(args.c3_steps, args.c3_warmup, not args.no_fp64)
     if args.calib:
         calibrate_copy()
     print(json.dumps(res))

@@ -172,6 +172,16 @@ fcw_status fcw_select_tile(fcw_ctx* ctx, int32_t i);
  * running when work arrives on the new one. */
 fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
 
+/* Per-kernel timing of later step calls, for measurement: with enable != 0 every
+ * launch of the step kernels is bracketed by a pair of HIP events on the context's
+ * stream (counts are cleared); 0 turns it off.  Synchronises. */
+fcw_status fcw_timing(fcw_ctx* ctx, int32_t enable);
+
+/* Summed duration in milliseconds and number of launches since fcw_timing(ctx, 1) of
+ * kernel kind `which`: 0 the main step kernel (tile or 2-D kernel), 1 the cut-cell
+ * product kernel.  Synchronises. */
+fcw_status fcw_timing_read(fcw_ctx* ctx, int32_t which, double* ms, int64_t* launches);
+
 /* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
 fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,
                          const fcw_source* src, double t0, double dt, int32_t nsteps);

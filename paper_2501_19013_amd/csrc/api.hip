@@ -48,13 +48,18 @@ static void free_all(Ctx& c) {
   dfree(c.d_cut_cells); dfree(c.d_cut_vptr); dfree(c.d_cut_vidx); dfree(c.d_all_void);
   dfree(c.d_tab); dfree(c.d_kref); dfree(c.d_mfull); dfree(c.d_lref); dfree(c.d_kcut);
   dfree(c.d_mcut); dfree(c.d_lumped); dfree(c.d_margin); dfree(c.d_evs_fail); dfree(c.d_mass);
-  dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf);
+  dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
   dfree(c.d_src);
   dfree(c.d_wl);
   if (c.h_wl) (void)hipHostFree(c.h_wl);
   c.h_wl = nullptr;
   if (c.wl_event) (void)hipEventDestroy(c.wl_event);
   c.wl_event = nullptr;
+  for (int w = 0; w < 2; ++w) {
+    for (hipEvent_t e : c.tev[w]) (void)hipEventDestroy(e);
+    c.tev[w].clear();
+    c.tn[w] = 0;
+  }
   if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
   c.graph_exec = nullptr;
 }
@@ -84,6 +89,26 @@ static fcw_status check_ctx(const fcw_ctx* ctx, int need_state) {
     set_error("call out of order (context state %d, need %d)", ctx->state, need_state);
     return FCW_E_STATE;
   }
+  return FCW_OK;
+}
+
+fcw_status timing_begin(Ctx& c, int w) {
+  if (!c.timing) return FCW_OK;
+  if (c.tev[w].size() < 2 * (c.tn[w] + 1)) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e = nullptr;
+      FCW_HIP(hipEventCreate(&e));
+      c.tev[w].push_back(e);
+    }
+  }
+  FCW_HIP(hipEventRecord(c.tev[w][2 * c.tn[w]], c.stream));
+  return FCW_OK;
+}
+
+fcw_status timing_end(Ctx& c, int w) {
+  if (!c.timing) return FCW_OK;
+  FCW_HIP(hipEventRecord(c.tev[w][2 * c.tn[w] + 1], c.stream));
+  ++c.tn[w];
   return FCW_OK;
 }
 
@@ -494,6 +519,36 @@ fcw_status fcw_set_stream(fcw_ctx* c, void* stream) {
   // work already queued on the old stream completes before later work is queued elsewhere
   FCW_HIP(hipStreamSynchronize(c->stream));
   c->stream = (hipStream_t)stream;
+  return FCW_OK;
+}
+
+fcw_status fcw_timing(fcw_ctx* c, int32_t enable) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  FCW_HIP(hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  c->tn[0] = c->tn[1] = 0;
+  return FCW_OK;
+}
+
+fcw_status fcw_timing_read(fcw_ctx* c, int32_t which, double* ms, int64_t* launches) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 1);
+  if (st) return st;
+  if (which < 0 || which > 1 || !ms) {
+    set_error("which must be 0 (main kernel) or 1 (cut-cell kernel); ms non-null");
+    return FCW_E_ARG;
+  }
+  FCW_HIP(hipStreamSynchronize(c->stream));
+  double sum = 0.0;
+  for (size_t i = 0; i < c->tn[which]; ++i) {
+    float t = 0.0f;
+    FCW_HIP(hipEventElapsedTime(&t, c->tev[which][2 * i], c->tev[which][2 * i + 1]));
+    sum += t;
+  }
+  *ms = sum;
+  if (launches) *launches = (int64_t)c->tn[which];
   return FCW_OK;
 }
 

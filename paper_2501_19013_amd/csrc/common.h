@@ -84,6 +84,8 @@ struct Ctx {
   // scratch
   void* d_ubuf = nullptr;
   size_t ubuf_bytes = 0;
+  void* d_ycut = nullptr;     // [nrhs][n_cut_cand][n_loc] cut-cell products of a step
+  size_t ycut_bytes = 0;
   SourceDev* d_src = nullptr;
   bool d_src_active = false;  // the sources of the current batched call are set
   int src_cap = 0;
@@ -97,8 +99,13 @@ struct Ctx {
   hipGraphExec_t graph_exec = nullptr;
   const void* graph_fn = nullptr;
   int graph_nitems = 0, graph_nsteps = 0;
+  int64_t graph_ncut = 0;
   void* graph_wl = nullptr;
   int64_t footprint = 0;
+  // optional per-kernel timing of step calls: event pairs per kernel kind
+  bool timing = false;
+  std::vector<hipEvent_t> tev[2];
+  size_t tn[2] = {0, 0};
 
   size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
 };
@@ -122,6 +129,18 @@ fcw_status setup_reclassify(Ctx& c);
 fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda);
 fcw_status setup_mass_and_pack(Ctx& c);
 fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
+// per-kernel timing (api.hip): which = kTimeMain (tile / 2-D kernel) or kTimeCut
+enum { kTimeMain = 0, kTimeCut = 1 };
+fcw_status timing_begin(Ctx& c, int which);
+fcw_status timing_end(Ctx& c, int which);
+// cutcell.hip: cut-cell products y = K_e u_e, once per cut cell and step
+fcw_status ensure_ycut(Ctx& c, int nrhs);
+size_t cutprob_size(int fp64);
+int64_t cutprob_fill(const Ctx& c, void* out, const void* ua, const void* ub, int nrhs,
+                     int nsteps, int64_t blk0);
+fcw_status launch_cut(const Ctx& kind, hipStream_t s, const void* probs, int nprob,
+                      const void* one, int64_t nblk, int j);
+fcw_status launch_cut_products(Ctx& c, int nrhs, const void* u);
 // step.hip
 bool step_supported(const Ctx& c);
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);

@@ -8,6 +8,7 @@
 //  - assembly of the diagonal mass and packing of the per-step operands.
 // Geometric predicates and quadrature coordinates are evaluated with contraction
 // disabled so that they follow plain IEEE double arithmetic step by step.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -859,6 +860,252 @@ __global__ __launch_bounds__(kEvsThreads) void evs_lump_kernel(EvsArgs a) {
   }
 }
 
+// Large cut cells (n_s too big for A and V of the Jacobi kernel in LDS, e.g. 3-D p=4):
+// the same stabilised lumped diagonal through a tridiagonal reduction.  One workgroup
+// per cut cell (grid-stride over the cells, one scratch slot per workgroup):
+//  1. Householder reduction M^o = Q T Q^T with M^o in LDS; the reflectors go to the
+//     workgroup's scratch slot in global memory;
+//  2. implicit QL with shifts on T; waves 0 and 1 run the (scalar) recurrence each on
+//     their own copy of T and rotate their own rows of the eigenvector matrix Z in LDS,
+//     so no barrier is needed inside the iteration;
+//  3. the columns of Z whose eigenvalues lie below f_lambda lambda_max are carried back
+//     through the reflectors, X_S = Q Z_S, and diag(M~^s)_k = sum_{i in S} X_ki^2.
+// Eigenvalues and the split come with the absolute accuracy of a symmetric eigensolver,
+// as in the Jacobi kernel.
+struct EvsBigArgs {
+  int n, lda;
+  const double* mcut;
+  const double* mfull;
+  double eps, f_lambda;
+  int64_t ncand;
+  double* scratch;  // [gridDim.x][n * n]
+  double* lumped;
+  double* margin;
+  int32_t* fail;
+};
+
+__device__ static inline double hypot_scaled(double a, double b) {
+  a = fabs(a);
+  b = fabs(b);
+  const double m = fmax(a, b), s = fmin(a, b);
+  if (m == 0.0) return 0.0;
+  const double r = s / m;
+  return m * sqrt(1.0 + r * r);
+}
+
+__global__ __launch_bounds__(kEvsThreads) void evs_big_kernel(EvsBigArgs a) {
+  extern __shared__ double smb[];
+  const int n = a.n, lda = a.lda;
+  double* A = smb;                    // n x lda: M^o, then Z
+  double* red = A + n * lda;          // 256
+  double* vb = red + kEvsThreads;     // n: reflector
+  double* pb = vb + n;                // n: A v, then w
+  double* dg = pb + n;                // n: original diagonal
+  double* dq = dg + n;                // 2 x n: diagonal of T, one copy per wave
+  double* eq = dq + 2 * n;            // 2 x n: off-diagonal of T
+  double* dk = eq + 2 * n;            // n
+  int* cols = (int*)(dk + n);         // n: columns of the small set
+  __shared__ int nsmall, bad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* hv = a.scratch + (int64_t)blockIdx.x * n * n;  // reflector k at k*n, tau at (n-1)*n+k
+
+  for (int64_t q = blockIdx.x; q < a.ncand; q += gridDim.x) {
+    const double* Mo = a.mcut + q * n * n;
+    double s_all = 0.0, s_diag = 0.0, mf = -1e300;
+    for (int idx = tid; idx < n * n; idx += kEvsThreads) {
+      const int i = idx / n, j = idx % n;
+      const double v = Mo[idx];
+      s_all += v;
+      if (i == j) s_diag += v;
+      mf = fmax(mf, a.mfull[idx]);
+      A[i * lda + j] = v;
+    }
+    for (int i = tid; i < n; i += kEvsThreads) dg[i] = Mo[i * n + i];
+    const double me = block_sum_256(s_all, red);
+    const double tr = block_sum_256(s_diag, red);
+    const double maxmf = block_max_256(mf, red);
+
+    // ---- 1. Householder reduction (A stays full and symmetric) ----
+    for (int k = 0; k + 2 < n; ++k) {
+      const int m = n - k - 1;  // length of the reflector
+      double sq = 0.0;
+      for (int i = tid; i < m; i += kEvsThreads) {
+        const double x = A[(k + 1 + i) * lda + k];
+        sq += x * x;
+      }
+      sq = block_sum_256(sq, red);
+      const double x0 = A[(k + 1) * lda + k];
+      const double nx = sqrt(sq);
+      const double alpha = (x0 > 0.0) ? -nx : nx;
+      const double vtv = sq - 2.0 * alpha * x0 + alpha * alpha;
+      const double tau = (nx > 0.0 && vtv > 0.0) ? 2.0 / vtv : 0.0;
+      for (int i = tid; i < m; i += kEvsThreads) {
+        const double v = A[(k + 1 + i) * lda + k] - (i == 0 ? alpha : 0.0);
+        vb[i] = v;
+        hv[k * n + i] = v;
+      }
+      if (tid == 0) {
+        hv[(n - 1) * n + k] = tau;
+        eq[k] = (tau != 0.0) ? alpha : x0;  // T(k+1, k)
+      }
+      __syncthreads();
+      if (tau != 0.0) {
+        // p = tau A22 v
+        for (int i = tid; i < m; i += kEvsThreads) {
+          const double* row = A + (k + 1 + i) * lda + (k + 1);
+          double acc = 0.0;
+          for (int j = 0; j < m; ++j) acc += row[j] * vb[j];
+          pb[i] = tau * acc;
+        }
+        __syncthreads();
+        double vp = 0.0;
+        for (int i = tid; i < m; i += kEvsThreads) vp += vb[i] * pb[i];
+        const double K = 0.5 * tau * block_sum_256(vp, red);
+        // w = p - K v
+        for (int i = tid; i < m; i += kEvsThreads) pb[i] -= K * vb[i];
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        for (int idx = tid; idx < m * m; idx += kEvsThreads) {
+          const int i = idx / m, j = idx % m;
+          A[(k + 1 + i) * lda + (k + 1 + j)] -= vb[i] * pb[j] + pb[i] * vb[j];
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < n; i += kEvsThreads) dq[i] = A[i * lda + i];
+    if (tid == 0) eq[n - 2] = A[(n - 1) * lda + (n - 2)];
+    __syncthreads();
+    // second copy of T for wave 1, Z = I
+    for (int i = tid; i < n; i += kEvsThreads) {
+      dq[n + i] = dq[i];
+      eq[n + i] = (i < n - 1) ? eq[i] : 0.0;
+      if (i == n - 1) eq[i] = 0.0;
+    }
+    for (int idx = tid; idx < n * n; idx += kEvsThreads) {
+      const int i = idx / n, j = idx % n;
+      A[i * lda + j] = (i == j) ? 1.0 : 0.0;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+
+    // ---- 2. implicit QL, waves 0 and 1, no barriers ----
+    if (wave < 2) {
+      double* d = dq + wave * n;
+      double* e = eq + wave * n;
+      const int row = wave * 64 + lane;
+      double* z = A + min(row, n - 1) * lda;
+      const bool own = row < n;
+      const double eps = 2.220446049250313e-16;
+      for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+          int m = l;
+          while (m < n - 1 && !(fabs(e[m]) <= eps * (fabs(d[m]) + fabs(d[m + 1])))) ++m;
+          if (m == l) break;
+          if (iter >= 60) {
+            if (lane == 0) bad = 1;
+            break;
+          }
+          double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+          double r = hypot_scaled(g, 1.0);
+          g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+          double sn = 1.0, cs = 1.0, pp = 0.0;
+          bool deflated = false;
+          for (int i = m - 1; i >= l; --i) {
+            const double f = sn * e[i], b = cs * e[i];
+            r = hypot_scaled(f, g);
+            if (lane == 0) e[i + 1] = r;
+            __builtin_amdgcn_wave_barrier();
+            if (r == 0.0) {
+              if (lane == 0) {
+                d[i + 1] -= pp;
+                e[m] = 0.0;
+              }
+              __builtin_amdgcn_wave_barrier();
+              deflated = true;
+              break;
+            }
+            sn = f / r;
+            cs = g / r;
+            g = d[i + 1] - pp;
+            r = (d[i] - g) * sn + 2.0 * cs * b;
+            pp = sn * r;
+            if (lane == 0) d[i + 1] = g + pp;
+            __builtin_amdgcn_wave_barrier();
+            g = cs * r - b;
+            if (own) {
+              const double z1 = z[i + 1], z0 = z[i];
+              z[i + 1] = sn * z0 + cs * z1;
+              z[i] = cs * z0 - sn * z1;
+            }
+          }
+          if (deflated) continue;
+          if (lane == 0) {
+            d[l] -= pp;
+            e[l] = g;
+            e[m] = 0.0;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- 3. small set, back-transformation of its columns, lumped diagonal ----
+    double lm = -1e300;
+    for (int i = tid; i < n; i += kEvsThreads) lm = fmax(lm, dq[i]);
+    const double lmax = block_max_256(lm, red);
+    double mg = 1e300;
+    for (int i = tid; i < n; i += kEvsThreads) mg = fmin(mg, fabs(dq[i] / lmax - a.f_lambda));
+    const double marg = -block_max_256(-mg, red);
+    if (tid == 0) {
+      int k = 0;
+      for (int i = 0; i < n; ++i)
+        if (dq[i] < a.f_lambda * lmax) cols[k++] = i;
+      nsmall = k;
+    }
+    __syncthreads();
+    const int ks = nsmall;
+    for (int k = n - 3; k >= 0 && ks > 0; --k) {
+      const int m = n - k - 1;
+      for (int i = tid; i < m; i += kEvsThreads) vb[i] = hv[k * n + i];
+      const double tau = hv[(n - 1) * n + k];
+      __syncthreads();
+      if (tau != 0.0) {
+        for (int s = wave; s < ks; s += 4) {
+          const int c = cols[s];
+          double part = 0.0;
+          for (int i = lane; i < m; i += 64) part += vb[i] * A[(k + 1 + i) * lda + c];
+#pragma unroll
+          for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+          const double w = tau * part;
+          for (int i = lane; i < m; i += 64) A[(k + 1 + i) * lda + c] -= vb[i] * w;
+        }
+      }
+      __syncthreads();
+    }
+    double dmax = 0.0;
+    for (int r = tid; r < n; r += kEvsThreads) {
+      double acc = 0.0;
+      for (int s = 0; s < ks; ++s) {
+        const double x = A[r * lda + cols[s]];
+        acc += x * x;
+      }
+      dk[r] = acc;
+      dmax = fmax(dmax, acc);
+    }
+    const double maxd = block_max_256(dmax, red);
+    for (int r = tid; r < n; r += kEvsThreads) {
+      const double ms = (maxd > 0.0) ? (maxmf / maxd) * dk[r] : 0.0;
+      a.lumped[q * n + r] = me / tr * dg[r] + a.eps * ms;
+    }
+    if (tid == 0) {
+      a.margin[q] = marg;
+      a.fail[q] = bad;
+    }
+    __syncthreads();
+  }
+}
+
 fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda) {
   if (c.n_cut_cand == 0) return FCW_OK;
   const int n = c.n_s;
@@ -874,12 +1121,39 @@ fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda) {
     return b;
   };
   const size_t shbytes = frame(eps != 0.0);
-  if (shbytes > 160 * 1024) {
+  const int lda = (n % 2 == 1) ? n : n + 1;
+  const size_t big_bytes = ((size_t)n * lda + kEvsThreads + 9 * (size_t)n) * sizeof(double) +
+                           (size_t)n * sizeof(int);
+  const bool big = shbytes > 160 * 1024;
+  if (big && big_bytes > 160 * 1024) {
     set_error("eigenvalue stabilisation of n_s=%d does not fit in LDS", n);
     return FCW_E_UNSUPPORTED;
   }
   int32_t* fail = nullptr;
   FCW_HIP(hipMallocAsync((void**)&fail, c.n_cut_cand * 4, c.stream));
+  if (big) {
+    // one workgroup per CU, grid-stride over the cut cells; reflectors in scratch slots
+    const int grid = (int)std::min<int64_t>(c.n_cut_cand, 256);
+    double* scratch = nullptr;
+    FCW_HIP(hipMallocAsync((void**)&scratch, (size_t)grid * n * n * sizeof(double), c.stream));
+    EvsBigArgs eb{};
+    eb.n = n;
+    eb.lda = lda;
+    eb.mcut = c.d_mcut;
+    eb.mfull = c.d_mfull;
+    eb.eps = eps;
+    eb.f_lambda = f_lambda;
+    eb.ncand = c.n_cut_cand;
+    eb.scratch = scratch;
+    eb.lumped = c.d_lumped;
+    eb.margin = c.d_margin;
+    eb.fail = fail;
+    FCW_HIP(hipFuncSetAttribute((const void*)evs_big_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)big_bytes));
+    evs_big_kernel<<<grid, kEvsThreads, big_bytes, c.stream>>>(eb);
+    FCW_HIP(hipGetLastError());
+    FCW_HIP(hipFreeAsync(scratch, c.stream));
+  }
   EvsArgs ea{};
   ea.n = n;
   ea.m = m;
@@ -893,10 +1167,12 @@ fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda) {
   ea.lumped = c.d_lumped;
   ea.margin = c.d_margin;
   ea.fail = fail;
-  FCW_HIP(hipFuncSetAttribute((const void*)evs_lump_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shbytes));
-  evs_lump_kernel<<<(unsigned)c.n_cut_cand, kEvsThreads, shbytes, c.stream>>>(ea);
-  FCW_HIP(hipGetLastError());
+  if (!big) {
+    FCW_HIP(hipFuncSetAttribute((const void*)evs_lump_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shbytes));
+    evs_lump_kernel<<<(unsigned)c.n_cut_cand, kEvsThreads, shbytes, c.stream>>>(ea);
+    FCW_HIP(hipGetLastError());
+  }
   std::vector<int32_t> hf(c.n_cut_cand), hav(c.n_cut_cand);
   FCW_HIP(hipMemcpyAsync(hf.data(), fail, c.n_cut_cand * 4, hipMemcpyDeviceToHost, c.stream));
   FCW_HIP(hipMemcpyAsync(hav.data(), c.d_all_void, c.n_cut_cand * 4, hipMemcpyDeviceToHost,

@@ -54,7 +54,6 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   constexpr int RNY = (DIM >= 2) ? RCY * P + 1 : 1;
   constexpr int RNZ = (DIM == 3) ? RCZ * P + 1 : 1;
   constexpr int NRN = RNX * RNY * RNZ;
-  constexpr int NPK = NL * (NL + 1) / 2;
   constexpr bool AREG = NMB * NKS <= 32;  // keep K_ref fragments in VGPRs
   // otherwise stage them in LDS when small enough, else read them through the caches
   constexpr bool ALDS = !AREG && (NMB * 16 * KW * (int)sizeof(T) <= 48 * 1024);
@@ -265,8 +264,25 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     }
   }
 
-  // ---- cut cells: own packed stiffness streamed from HBM, one wave per cell ----
-  {
+  // ---- cut cells: products computed once per step by the cut-cell kernel ----
+  if (MODE != kModeLanczos) {
+    int seen = 0;
+    for (int c0 = 0; c0 < NRC; c0 += 64) {
+      const int cc = c0 + lane;
+      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
+      unsigned long long mask = __ballot(isc);
+      while (mask) {
+        const int bit = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        if ((seen++ & 3) != wave) continue;
+        const int c = c0 + bit;
+        const T* yq = a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL;
+        for (int i = lane; i < NL; i += 64) y_s[c * NL + i] = yq[i];
+      }
+    }
+  }
+  // ---- Lanczos operator: full FP64 setup matrices streamed per tile, one wave per cell ----
+  if (MODE == kModeLanczos) {
     int seen = 0;
     for (int c0 = 0; c0 < NRC; c0 += 64) {
       const int cc = c0 + lane;
@@ -280,8 +296,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         const int q = info_s[c];
         const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
         const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
-        // the FP64 Lanczos operator reads the full FP64 setup matrices
-        const T* K = a.kcut + (int64_t)q * (MODE == kModeLanczos ? NL * NL : NPK);
+        const T* K = a.kcut + (int64_t)q * NL * NL;
         constexpr int NR = (NL + 63) / 64;
         // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
         // small lumped masses of cut-cell nodes amplify any error in their sum
@@ -295,10 +310,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
 #pragma unroll
           for (int rr = 0; rr < NR; ++rr) {
             const int i = min(lane + 64 * rr, NL - 1);
-            const int idx = (MODE == kModeLanczos)
-                                ? i * NL + j
-                                : ((i <= j) ? j * (j + 1) / 2 + i : i * (i + 1) / 2 + j);
-            y[rr] += (double)K[idx] * (double)uj;
+            y[rr] += (double)K[i * NL + j] * (double)uj;
           }
         }
 #pragma unroll
@@ -441,16 +453,27 @@ struct TileCfg {
       a.kref = (const T*)c.d_kref;
       a.kcut = (const T*)c.d_kcut;
     }
+    a.ycut = (const T*)c.d_ycut;
+    a.ncand = c.n_cut_cand;
     return a;
   }
   // every mode (the default configuration of a problem kind)
   static fcw_status run(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
                         double t, double dt, int start) {
+    if (mode != kModeLanczos) {
+      fcw_status st = launch_cut_products(c, nrhs, uin);
+      if (st) return st;
+    }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
-    if (mode == kModeStep)
+    if (mode == kModeStep) {
+      fcw_status st = timing_begin(c, kTimeMain);
+      if (st) return st;
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
-    else if (mode == kModeApply)
+      FCW_HIP(hipGetLastError());
+      return timing_end(c, kTimeMain);
+    }
+    if (mode == kModeApply)
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply><<<grid, 256, 0, c.stream>>>(a);
     else
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos><<<grid, 256, 0, c.stream>>>(a);
@@ -464,11 +487,14 @@ struct TileCfg {
       set_error("tile configuration built for the step only");
       return FCW_E_UNSUPPORTED;
     }
+    fcw_status st = launch_cut_products(c, nrhs, uin);
+    if (st) return st;
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
+    if ((st = timing_begin(c, kTimeMain))) return st;
     tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
     FCW_HIP(hipGetLastError());
-    return FCW_OK;
+    return timing_end(c, kTimeMain);
   }
 };
 
@@ -610,21 +636,15 @@ static fcw_status stage_worklist(Ctx& c, const void* host, size_t bytes) {
   return FCW_OK;
 }
 
-fcw_status run_group2d(Ctx& owner, Run2d fn, const std::vector<char>& records, int nprob,
-                       const std::vector<int4>& items, int nsteps) {
-  const int fp64 = owner.precision == FCW_FP64;
-  const size_t rb = prob2d_size(fp64) * nprob;
-  std::vector<char> host(rb + items.size() * sizeof(int4));
-  std::memcpy(host.data(), records.data(), rb);
-  std::memcpy(host.data() + rb, items.data(), items.size() * sizeof(int4));
-  fcw_status st = stage_worklist(owner, host.data(), host.size());
-  if (st) return st;
-  const int4* ditems = (const int4*)((char*)owner.d_wl + rb);
-  for (int j = 0; j < nsteps; ++j) {
-    st = fn(owner.stream, owner.d_wl, ditems, (int)items.size(), j, nullptr, 0);
+// The launches of one step of a batched group: the cut-cell products of every member
+// that has cut cells, then the 2-D kernel over all items.
+static fcw_status group_step(Ctx& owner, Run2d fn, const void* dprobs, const int4* ditems,
+                             int nitems, const void* dcut, int ncutprob, int64_t ncutblk, int j) {
+  if (ncutblk > 0) {
+    fcw_status st = launch_cut(owner, owner.stream, dcut, ncutprob, nullptr, ncutblk, j);
     if (st) return st;
   }
-  return FCW_OK;
+  return fn(owner.stream, dprobs, ditems, nitems, j, nullptr, 0);
 }
 
 bool groupable_2d(const Ctx& a, const Ctx& b) {
@@ -644,13 +664,23 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     return FCW_E_UNSUPPORTED;
   }
   const size_t rs = prob2d_size(fp64);
-  std::vector<char> rec(rs * m.size());
+  const size_t cs = cutprob_size(fp64);
+  std::vector<char> rec(rs * m.size()), cut;
   std::vector<int4> items;
-  int nmax = 0;
+  int nmax = 0, ncutprob = 0;
+  int64_t ncutblk = 0;
   for (size_t i = 0; i < m.size(); ++i) {
     const GroupMember& g = m[i];
-    const Ctx& c = *g.ctx;
+    Ctx& c = *g.ctx;
     if (g.nsteps <= 0) continue;
+    fcw_status st = ensure_ycut(c, g.nrhs);
+    if (st) return st;
+    if (c.n_cut_cand > 0) {
+      cut.resize(cs * (ncutprob + 1));
+      ncutblk += cutprob_fill(c, cut.data() + cs * ncutprob, g.u, g.scratch, g.nrhs, g.nsteps,
+                              ncutblk);
+      ++ncutprob;
+    }
     if (g.nsteps % 2 == 1)
       FCW_HIP(hipMemcpyAsync(g.scratch, g.u, (size_t)g.nrhs * c.ndof * c.state_bytes(),
                              hipMemcpyDeviceToDevice, owner.stream));
@@ -663,24 +693,34 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     nmax = std::max(nmax, g.nsteps);
   }
   if (items.empty()) return FCW_OK;
-  if (!graph) return run_group2d(owner, sc.f2d, rec, (int)m.size(), items, nmax);
-  // graph replay: the records live in device memory, so a cached graph stays valid for
-  // the same kernel, item count, step count and work-list buffer
-  std::vector<char> host(rec.size() + items.size() * sizeof(int4));
+  // work list in device memory: 2-D records, items, cut-cell records
+  std::vector<char> host(rec.size() + items.size() * sizeof(int4) + cut.size());
   std::memcpy(host.data(), rec.data(), rec.size());
   std::memcpy(host.data() + rec.size(), items.data(), items.size() * sizeof(int4));
+  if (!cut.empty())
+    std::memcpy(host.data() + rec.size() + items.size() * sizeof(int4), cut.data(), cut.size());
   fcw_status st = stage_worklist(owner, host.data(), host.size());
   if (st) return st;
   const int nitems = (int)items.size();
+  const int4* ditems = (const int4*)((char*)owner.d_wl + rec.size());
+  const void* dcut = (const char*)owner.d_wl + rec.size() + items.size() * sizeof(int4);
+  if (!graph) {
+    for (int j = 0; j < nmax; ++j)
+      if ((st = group_step(owner, sc.f2d, owner.d_wl, ditems, nitems, dcut, ncutprob, ncutblk, j)))
+        return st;
+    return FCW_OK;
+  }
+  // graph replay: the records live in device memory, so a cached graph stays valid for
+  // the same kernels, item and cut-block counts, step count and work-list buffer
   if (!(owner.graph_exec && owner.graph_fn == (const void*)sc.f2d &&
-        owner.graph_nitems == nitems && owner.graph_nsteps == nmax && owner.graph_wl == owner.d_wl)) {
+        owner.graph_nitems == nitems && owner.graph_nsteps == nmax &&
+        owner.graph_ncut == ncutblk && owner.graph_wl == owner.d_wl)) {
     if (owner.graph_exec) FCW_HIP(hipGraphExecDestroy(owner.graph_exec));
     owner.graph_exec = nullptr;
-    const int4* ditems = (const int4*)((char*)owner.d_wl + rec.size());
     hipGraph_t g = nullptr;
     FCW_HIP(hipStreamBeginCapture(owner.stream, hipStreamCaptureModeThreadLocal));
     for (int j = 0; j < nmax && st == FCW_OK; ++j)
-      st = sc.f2d(owner.stream, owner.d_wl, ditems, nitems, j, nullptr, 0);
+      st = group_step(owner, sc.f2d, owner.d_wl, ditems, nitems, dcut, ncutprob, ncutblk, j);
     hipError_t e = hipStreamEndCapture(owner.stream, &g);
     if (st) return st;
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -690,6 +730,7 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     owner.graph_fn = (const void*)sc.f2d;
     owner.graph_nitems = nitems;
     owner.graph_nsteps = nmax;
+    owner.graph_ncut = ncutblk;
     owner.graph_wl = owner.d_wl;
   }
   FCW_HIP(hipGraphLaunch(owner.graph_exec, owner.stream));
@@ -708,6 +749,10 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
   if (nsteps % 2 == 1) FCW_HIP(hipMemcpyAsync(scratch, u, bytes, hipMemcpyDeviceToDevice, c.stream));
   if (sc.f2d) {
     const int fp64 = c.precision == FCW_FP64;
+    fcw_status st = ensure_ycut(c, nrhs);
+    if (st) return st;
+    char crec[256];
+    const int64_t ncutblk = cutprob_fill(c, crec, u, scratch, nrhs, nsteps, 0);
     const int ntx = (c.ncells[0] + sc.tile[0] - 1) / sc.tile[0];
     const int nty = (c.ncells[1] + sc.tile[1] - 1) / sc.tile[1];
     std::vector<char> rec(prob2d_size(fp64));
@@ -716,8 +761,16 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
     // one problem: its record goes by value, items are implicit (tile-major, rhs fastest)
     const int nitems = ntx * nty * nrhs;
     for (int j = 0; j < nsteps; ++j) {
-      fcw_status st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs);
-      if (st) return st;
+      if (c.n_cut_cand > 0) {
+        if ((st = timing_begin(c, kTimeCut)) ||
+            (st = launch_cut(c, c.stream, nullptr, 1, crec, ncutblk, j)) ||
+            (st = timing_end(c, kTimeCut)))
+          return st;
+      }
+      if ((st = timing_begin(c, kTimeMain)) ||
+          (st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs)) ||
+          (st = timing_end(c, kTimeMain)))
+        return st;
     }
     return FCW_OK;
   }

@@ -15,8 +15,8 @@
 //    order: bitwise reproducible, no atomics to global memory, no gather pass.
 //  * Uncut cells of a class: 16 per wave on the matrix cores, Y = K_ref [u_e1..u_e16]
 //    (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64; K_ref fragments held in VGPRs).
-//    Cut cells of a class: one wave per cell streaming its packed K_e, accumulated in
-//    FP64 whatever the state precision.
+//    Cut cells of a class add their products y_e = K_e u_e, computed once per step by
+//    the cut-cell kernel (FP64 accumulation, rounded to the state precision).
 //  * The update d_{k+1} = d_k + dt^2 M^{-1}(F_k - K u_k), u_{k+1} = u_k + d_{k+1} runs
 //    row by row (lane = x); d and M^{-1} rows are staged in LDS at kernel entry.
 #include <cstring>
@@ -44,7 +44,8 @@ struct Prob2d {
   const T* invm;         // [nnodes]
   const int32_t* info;   // [ncells]
   const T* kref;         // [NL*NL]
-  const T* kcut;         // packed cut-cell matrices
+  const T* ycut;         // [nrhs][ncand][NL] cut-cell products of this step
+  int64_t ncand;
   const SourceDev* src;  // [nrhs] or null
   int n[2], np[2], ntile[2];
   int64_t ndof;
@@ -62,7 +63,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   constexpr int NL = NP1 * NP1;
   constexpr int NMB = (NL + 15) / 16;
   constexpr int NKS = (NL + 3) / 4;
-  constexpr int NPK = NL * (NL + 1) / 2;
   constexpr int TX = 64 / P;                 // one owned node row = one wave
   constexpr int OWX = TX * P;
   constexpr int RCX = TX + 1, RCY = TY + 1;  // region cells (tile + low ring)
@@ -247,7 +247,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
             if (offo[mb][r] >= 0) r_s[base + offo[mb][r]] = cur[mb][r] + acc[mb][r];
       }
     }
-    // cut cells of the class: one wave per cell, lanes = rows of K_e
+    // cut cells of the class: their products come from the cut-cell kernel; one wave
+    // per cell, lane = row
     int seen = 0;
     for (int c0 = 0; c0 < ncol; c0 += 64) {
       const int idx = min(c0 + lane, ncol - 1);
@@ -261,17 +262,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
         const int lx = px + 2 * (ci % nxc), ly = py + 2 * (ci / nxc);
         const int q = info_s[lx + RCX * ly];
         const int base = lx * P + ly * P * W;
-        const T* K = pr.kcut + (int64_t)q * NPK;
         const int i = min(lane, NL - 1);
-        // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
-        // small lumped masses of cut-cell nodes amplify any error in their sum
-        double y = 0.0;
-#pragma unroll
-        for (int j = 0; j < NL; ++j) {
-          const int kidx = (i <= j) ? j * (j + 1) / 2 + i : i * (i + 1) / 2 + j;
-          y += (double)K[kidx] * (double)u_s[base + (j % NP1) + (j / NP1) * W];
-        }
-        if (lane < NL) r_s[base + (i % NP1) + (i / NP1) * W] += (T)y;
+        const T y = pr.ycut[((int64_t)rhs * pr.ncand + q) * NL + i];
+        if (lane < NL) r_s[base + (i % NP1) + (i / NP1) * W] += y;
       }
     }
     __syncthreads();
@@ -374,7 +367,8 @@ static void fill_prob(const Ctx& c, void* out, void* ua, void* ub, void* d, doub
   p.invm = (const T*)c.d_invm;
   p.info = c.d_info;
   p.kref = (const T*)c.d_kref_s;
-  p.kcut = (const T*)c.d_kcut_s;
+  p.ycut = (const T*)c.d_ycut;
+  p.ncand = c.n_cut_cand;
   p.src = src;
   p.n[0] = c.ncells[0];
   p.n[1] = c.ncells[1];

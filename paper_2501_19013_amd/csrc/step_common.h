@@ -51,6 +51,8 @@ struct StepArgs {
   int start;
   const SourceDev* src;
   double t;
+  const T* ycut;  // [nrhs][ncand][n_loc] cut-cell products of this step (step / apply)
+  int64_t ncand;
 };
 
 __device__ static inline double ricker(double t, double f0) {

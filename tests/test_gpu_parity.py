@@ -227,6 +227,46 @@ def test_scalar_3d_parity():
     s.close()
 
 
+def test_scalar_3d_p4_large_cell_stabilisation():
+    # n_s = 125: the tridiagonal (Householder + QL) path of the stabilisation; cut cells
+    # of a 6^3 pore field checked one by one against the oracle (cells with 0, 1 and 3
+    # small eigenvalues; margins 1e-5 .. 1e-4)
+    from paper_2501_19013_amd import fcw
+    cfg = workloads.scaled_config(3, 6, 4, seed=6, porosity=0.2, nsteps=40, depth=2)
+    cells = [98, 171, 206, 1, 95, 128]
+    disc = problem.build(problem.Problem.from_config(cfg), cut_subset=cells)
+    assert sorted(set(disc.evs_nsmall.tolist())) == [0, 1, 3]
+    s = _solver(cfg, "fp64")
+    cand = s.export(fcw.ARR_CUT_CELLS)
+    lc = s.export(fcw.ARR_LUMPED_CUT).reshape(-1, 125)
+    mc = s.export(fcw.ARR_M_CUT).reshape(-1, 125, 125)
+    slot = {int(c): q for q, c in enumerate(cand)}
+    for k, cell in enumerate(disc.cut_cells):
+        q = slot[int(cell)]
+        ref = disc.lumped_cut[k]
+        assert np.abs(mc[q] - disc.Mo_cut[k]).max() <= 1e-13 * np.abs(disc.Mo_cut[k]).max()
+        assert np.abs(lc[q] - ref).max() <= 1e-10 * np.abs(ref).max(), int(cell)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_scalar_3d_p4_run_parity(precision, tol):
+    # 3^3 cells, p=4, one offset ball (24 cut cells, one with 112 small eigenvalues),
+    # octree depth 1
+    cfg = workloads._base(3, (3, 3, 3), 4, [(0.55, 0.5, 0.45)], [0.3], tree_depth=1,
+                          nsteps=60)
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    s = _solver(cfg, precision)
+    if precision == "fp64":
+        _setup_parity(cfg, disc, s)
+    got = _run_gpu(s, cfg, dt, 60, [25, 35])
+    ref = timestep.cdm(disc, dt, 60, sources=cfg["sources"], checkpoints=tuple(got))
+    for k, u in got.items():
+        assert rel_l2(u, ref["snapshots"][k]) <= tol, k
+    s.close()
+
+
 def test_error_paths():
     from paper_2501_19013_amd import fcw
     cfg = workloads.config("c1")

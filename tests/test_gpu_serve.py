@@ -14,9 +14,11 @@ from oracle import problem, timestep
 pytestmark = pytest.mark.gpu
 
 # (dim, cells per side, p, void seed, steps, arrival in s)
-SPECS = [(2, 24, 4, 31, 60, 0.0), (2, 17, 3, 32, 45, 0.0), (3, 5, 2, 33, 40, 0.01),
-         (2, 30, 4, 34, 80, 0.02), (3, 4, 3, 35, 30, 0.03), (2, 21, 2, 36, 50, 0.04),
-         (2, 13, 4, 37, 35, 0.05), (3, 6, 2, 38, 25, 0.06)]
+# (step counts are large enough that a request stays resident for many quanta while
+# later ones are set up and join)
+SPECS = [(2, 24, 4, 31, 1500, 0.0), (2, 17, 3, 32, 900, 0.0), (3, 5, 2, 33, 600, 0.01),
+         (2, 30, 4, 34, 1200, 0.02), (3, 4, 3, 35, 500, 0.03), (2, 21, 2, 36, 800, 0.04),
+         (2, 13, 4, 37, 700, 0.05), (3, 6, 2, 38, 400, 0.06)]
 
 
 def _requests():
