@@ -49,6 +49,7 @@ static void free_all(Ctx& c) {
   dfree(c.d_tab); dfree(c.d_kref); dfree(c.d_mfull); dfree(c.d_lref); dfree(c.d_kcut);
   dfree(c.d_mcut); dfree(c.d_lumped); dfree(c.d_margin); dfree(c.d_evs_fail); dfree(c.d_mass);
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
+  dfree(c.d_invw); dfree(c.d_mflag);
   dfree(c.d_src);
   dfree(c.d_wl);
   if (c.h_wl) (void)hipHostFree(c.h_wl);

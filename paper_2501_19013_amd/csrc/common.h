@@ -80,6 +80,13 @@ struct Ctx {
   void* d_kref_s = nullptr;   // [n_loc^2]
   void* d_kcut_s = nullptr;   // [n_cut_cand * n_loc(n_loc+1)/2], packed upper, column-major
   double* d_invm64 = nullptr; // [nnodes] FP64 copy for the Lanczos iteration
+  // analytic inverse mass of nodes whose cells are all uncut: invm = cm * invw_x * invw_y
+  // (* invw_z), with the 1-D inverse assembled GLL weights invw; mflag has one bit per
+  // node (rows of np[0] nodes, mflag_wpr words each) set where invm must be read instead
+  double* d_invw = nullptr;       // [np0 + np1 + np2]
+  uint32_t* d_mflag = nullptr;    // [np1 * np2][mflag_wpr]
+  int mflag_wpr = 0;
+  double cm = 0.0;
 
   // scratch
   void* d_ubuf = nullptr;
@@ -109,6 +116,14 @@ struct Ctx {
 
   size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
 };
+
+// The analytic inverse mass of a node all of whose cells are uncut (the assembled GLL
+// diagonal factorises over the directions); setup and step kernels use this one
+// expression so the stored and the computed values agree bit for bit.
+template <typename T>
+__host__ __device__ inline T analytic_invm(double cm, double iwx, double iwy, double iwz) {
+  return (T)(((cm * iwx) * iwy) * iwz);
+}
 
 // error reporting (thread-local message)
 void set_error(const char* fmt, ...);

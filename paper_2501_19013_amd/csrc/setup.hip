@@ -1253,6 +1253,82 @@ __global__ void mass_kernel(MassArgs a) {
   a.invm64[node] = (m > 0.0) ? 1.0 / m : 0.0;
 }
 
+// 1-D inverse assembled GLL weights per direction: node g of direction k collects
+// w[g % p] inside a cell, w[p] + w[0] where two cells meet, one of them at the box faces
+__global__ void invw_kernel(const RefTables* tab, int dim, int p, int n0, int n1, int n2,
+                            double* invw) {
+  const int np[3] = {n0 * p + 1, n1 * p + 1, n2 * p + 1};
+  const int n[3] = {n0, n1, n2};
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  int off = 0;
+  for (int k = 0; k < dim; ++k) {
+    if (g < np[k]) {
+      const int r = g % p;
+      double w;
+      if (r != 0) w = tab->gll_w[r];
+      else w = (g > 0 ? tab->gll_w[p] : 0.0) + (g < n[k] * p ? tab->gll_w[0] : 0.0);
+      invw[off + g] = 1.0 / w;
+      return;
+    }
+    g -= np[k];
+    off += np[k];
+  }
+}
+
+// per node: does its mass differ from the analytic uncut value (a cell around it is cut
+// or outside)?  Then the stored inverse is the assembled one, else the analytic one.
+struct InvmArgs {
+  int dim, p;
+  int n[3], np[3];
+  int64_t nnodes;
+  const int32_t* info;
+  const double* invm64;
+  const double* invw;
+  double cm;
+  int8_t* needs;
+};
+
+template <typename T>
+__global__ void invm_kernel(InvmArgs a, T* out) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= a.nnodes) return;
+  int idx[3] = {0, 0, 0};
+  int64_t r = node;
+  for (int k = 0; k < a.dim; ++k) { idx[k] = (int)(r % a.np[k]); r /= a.np[k]; }
+  int cl[3] = {0, 0, 0}, ch[3] = {0, 0, 0};
+  for (int k = 0; k < a.dim; ++k) {
+    const int i = idx[k];
+    int hi = i / a.p;
+    int lo = (i % a.p == 0) ? hi - 1 : hi;
+    cl[k] = max(lo, 0);
+    ch[k] = min(hi, a.n[k] - 1);
+  }
+  bool needs = false;
+  for (int cz = cl[2]; cz <= ch[2]; ++cz)
+    for (int cy = cl[1]; cy <= ch[1]; ++cy)
+      for (int cx = cl[0]; cx <= ch[0]; ++cx)
+        if (a.info[cx + (int64_t)a.n[0] * (cy + (int64_t)a.n[1] * cz)] != kInfoUncut) needs = true;
+  a.needs[node] = needs ? 1 : 0;
+  const double iy = (a.dim > 1) ? a.invw[a.np[0] + idx[1]] : 1.0;
+  const double iz = (a.dim > 2) ? a.invw[a.np[0] + a.np[1] + idx[2]] : 1.0;
+  out[node] = needs ? (T)a.invm64[node] : analytic_invm<T>(a.cm, a.invw[idx[0]], iy, iz);
+}
+
+// bit b of word w of node row R: node (32 w + b) of that row needs the stored inverse
+__global__ void mflag_kernel(const int8_t* needs, uint32_t* words, int npx, int64_t nrows,
+                             int wpr) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nrows * wpr) return;
+  const int64_t row = w / wpr;
+  const int wi = (int)(w % wpr);
+  uint32_t bits = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int gx = wi * 32 + b;
+    if (gx < npx && needs[row * npx + gx]) bits |= 1u << b;
+  }
+  words[w] = bits;
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* in, T* out, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1309,20 +1385,55 @@ fcw_status setup_mass_and_pack(Ctx& c) {
   const unsigned gn = (unsigned)((c.nnodes + 255) / 256);
   const unsigned gk = (unsigned)((nl * nl + 255) / 256);
   const unsigned gp = (unsigned)((npk * c.n_cut_cand + 255) / 256);
+  // analytic inverse masses and the per-node flags
+  const int npsum = c.npts[0] + (c.dim > 1 ? c.npts[1] : 0) + (c.dim > 2 ? c.npts[2] : 0);
+  const int64_t nrows = c.nnodes / c.npts[0];
+  c.mflag_wpr = (c.npts[0] + 31) / 32 + 3;  // room for a 64-node row read from any start
+  if (!c.d_invw) {
+    FCW_HIP(hipMalloc((void**)&c.d_invw, (size_t)npsum * sizeof(double)));
+    FCW_HIP(hipMalloc((void**)&c.d_mflag, (size_t)nrows * c.mflag_wpr * sizeof(uint32_t)));
+    c.footprint += (int64_t)npsum * 8 + nrows * c.mflag_wpr * 4;
+  }
+  {
+    double m = c.rho;
+    for (int k = 0; k < c.dim; ++k) m *= 0.5 * c.h;
+    c.cm = 1.0 / m;
+  }
+  invw_kernel<<<(npsum + 255) / 256, 256, 0, c.stream>>>(c.d_tab, c.dim, c.p, c.ncells[0],
+                                                        c.dim > 1 ? c.ncells[1] : 1,
+                                                        c.dim > 2 ? c.ncells[2] : 1, c.d_invw);
+  FCW_HIP(hipGetLastError());
+  int8_t* needs = nullptr;
+  FCW_HIP(hipMallocAsync((void**)&needs, c.nnodes, c.stream));
+  InvmArgs ia{};
+  ia.dim = c.dim;
+  ia.p = c.p;
+  for (int k = 0; k < 3; ++k) { ia.n[k] = c.ncells[k]; ia.np[k] = c.npts[k]; }
+  ia.nnodes = c.nnodes;
+  ia.info = c.d_info;
+  ia.invm64 = c.d_invm64;
+  ia.invw = c.d_invw;
+  ia.cm = c.cm;
+  ia.needs = needs;
   if (c.precision == FCW_FP64) {
-    cast_kernel<double><<<gn, 256, 0, c.stream>>>(c.d_invm64, (double*)c.d_invm, c.nnodes);
+    invm_kernel<double><<<gn, 256, 0, c.stream>>>(ia, (double*)c.d_invm);
     cast_kernel<double><<<gk, 256, 0, c.stream>>>(c.d_kref, (double*)c.d_kref_s, nl * nl);
     if (c.n_cut_cand > 0)
       pack_upper_kernel<double><<<gp, 256, 0, c.stream>>>(c.d_kcut, (double*)c.d_kcut_s, (int)nl,
                                                           c.n_cut_cand);
   } else {
-    cast_kernel<float><<<gn, 256, 0, c.stream>>>(c.d_invm64, (float*)c.d_invm, c.nnodes);
+    invm_kernel<float><<<gn, 256, 0, c.stream>>>(ia, (float*)c.d_invm);
     cast_kernel<float><<<gk, 256, 0, c.stream>>>(c.d_kref, (float*)c.d_kref_s, nl * nl);
     if (c.n_cut_cand > 0)
       pack_upper_kernel<float><<<gp, 256, 0, c.stream>>>(c.d_kcut, (float*)c.d_kcut_s, (int)nl,
                                                          c.n_cut_cand);
   }
   FCW_HIP(hipGetLastError());
+  const int64_t nw = nrows * c.mflag_wpr;
+  mflag_kernel<<<(unsigned)((nw + 255) / 256), 256, 0, c.stream>>>(needs, c.d_mflag, c.npts[0],
+                                                                   nrows, c.mflag_wpr);
+  FCW_HIP(hipGetLastError());
+  FCW_HIP(hipFreeAsync(needs, c.stream));
   return FCW_OK;
 }
 

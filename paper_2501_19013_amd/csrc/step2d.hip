@@ -7,18 +7,19 @@
 //    wave (lane = x); TY cells high.  A workgroup (4 waves) stages the node values of
 //    the tile plus one ring of cells on the low side in LDS, one region row per
 //    buffer_load ... lds pair (no VGPRs, out-of-range lanes read zero).
-//  * The cells of the region are visited in 4 colour classes (cell parity in x and y).
-//    Within a class no two cells share a node, so the element results go straight
-//    into an LDS node accumulator with plain read-add-write (no two lanes or waves of
-//    a class touch the same node); the classes are ordered
-//    by barriers, so every node sums its (at most 4) cell contributions in a fixed
-//    order: bitwise reproducible, no atomics to global memory, no gather pass.
-//  * Uncut cells of a class: 16 per wave on the matrix cores, Y = K_ref [u_e1..u_e16]
-//    (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64; K_ref fragments held in VGPRs).
-//    Cut cells of a class add their products y_e = K_e u_e, computed once per step by
-//    the cut-cell kernel (FP64 accumulation, rounded to the state precision).
-//  * The update d_{k+1} = d_k + dt^2 M^{-1}(F_k - K u_k), u_{k+1} = u_k + d_{k+1} runs
-//    row by row (lane = x); d and M^{-1} rows are staged in LDS at kernel entry.
+//  * Element products of every cell of the region land in LDS (y_e per cell): uncut
+//    cells 16 per wave on the matrix cores, Y = K_ref [u_e1..u_e16]
+//    (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64; K_ref fragments held in VGPRs);
+//    cut cells copy their products y_e = K_e u_e, computed once per step by the cut-cell
+//    kernel (FP64 accumulation, rounded to the state precision).
+//  * The update runs one owned node row per wave instruction (lane = x): each node
+//    gathers its (at most 4) cell products in a fixed order -- lower cell row first,
+//    lower cell first within a row -- so the sum is atomic-free and bitwise
+//    reproducible; then d_{k+1} = d_k + dt^2 M^{-1}(F_k - K u_k), u_{k+1} = u_k + d_{k+1}.
+//  * M^{-1} of a node whose cells are all uncut is the analytic product of 1-D inverse
+//    GLL weights; only nodes flagged in a per-node bitmap (next to cut or outside cells)
+//    read the stored inverse mass.  d and M^{-1} are loaded into registers during the
+//    matrix-core phase.
 #include <cstring>
 #include <type_traits>
 
@@ -41,7 +42,11 @@ struct Prob2d {
   T* ua;                 // caller state u (the final state of a call lands here)
   T* ub;                 // scratch (ping-pong partner of ua)
   T* d;                  // [nrhs][ndof]
-  const T* invm;         // [nnodes]
+  const T* invm;         // [nnodes], read where the node's flag bit is set
+  const uint32_t* mflag; // [npy][wpr] per-node flag bits
+  const double* invw;    // [npx + npy] 1-D inverse assembled GLL weights
+  double cm;             // 1 / (rho (h/2)^2)
+  int wpr;
   const int32_t* info;   // [ncells]
   const T* kref;         // [NL*NL]
   const T* ycut;         // [nrhs][ncand][NL] cut-cell products of this step
@@ -56,17 +61,21 @@ struct Prob2d {
 
 // SINGLE: one problem whose record comes by value; item = tile * nrhs + rhs.
 template <typename T, int P, int TY, bool SINGLE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void step2d_kernel(
+__global__ __launch_bounds__(256) void step2d_kernel(
     const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, const Prob2d<T> one,
     int nrhs1, int nitems, int chunk, int j) {
   constexpr int NP1 = P + 1;
   constexpr int NL = NP1 * NP1;
   constexpr int NMB = (NL + 15) / 16;
   constexpr int NKS = (NL + 3) / 4;
+  // y_s stride per cell: the padded MFMA rows plus 3, which spreads both the MFMA row
+  // writes of 16 cells and the gather of a node row over the LDS banks
+  constexpr int NLP = NMB * 16 + 3;
   constexpr int TX = 64 / P;                 // one owned node row = one wave
   constexpr int OWX = TX * P;
   constexpr int RCX = TX + 1, RCY = TY + 1;  // region cells (tile + low ring)
   constexpr int NRC = RCX * RCY;
+  constexpr int NB = (NRC + 15) / 16;        // MFMA batches of 16 cells
   constexpr int RNX = RCX * P + 1, RNY = RCY * P + 1;
   constexpr int W = RNX;                     // LDS row stride (elements)
   constexpr int DPE = sizeof(T) / 4;         // dwords per element
@@ -79,9 +88,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   static_assert(NMB * NKS <= 32, "K_ref fragments kept in registers");
 
   __shared__ T u_s[RNY * W];
-  __shared__ T r_s[RNY * W];
-  __shared__ T d_s[NRW * 4 * 64];    // owned rows of d, one wave-row each
-  __shared__ T m_s[NRW * 4 * 64];    // owned rows of M^{-1}
+  __shared__ T y_s[NRC * NLP];
   __shared__ int info_s[NRC];
   __shared__ double ft_s;
   __shared__ int src_on;
@@ -110,29 +117,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
   const T* uin = (par ? pr.ua : pr.ub) + roff;
   T* dst_u = (par ? pr.ub : pr.ua) + roff;
   T* dst_d = pr.d + roff;
-  const uint32_t nbytes = (uint32_t)((pr.n[0] * P + 1) * (int64_t)(pr.n[1] * P + 1) * sizeof(T));
+  const uint32_t nbytes = (uint32_t)((int64_t)npx * npy * sizeof(T));
   const __amdgpu_buffer_rsrc_t ursrc =
       __builtin_amdgcn_make_buffer_rsrc((void*)uin, (short)0, (int)nbytes, 0x00020000);
   const double t = pr.t0 + j * pr.dt;
 
-  // ---- entry: issue every load of the tile ----
-  T areg[NMB][NKS];
-#pragma unroll
-  for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-    for (int kk = 0; kk < NKS; ++kk) {
-      const int r = mb * 16 + lc, cc = 4 * kk + lk;
-      const T v = pr.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
-      areg[mb][kk] = (r < NL && cc < NL) ? v : T(0);
-    }
+  // ---- entry: every load of the tile is issued here and stays in flight ----
+  // Nothing loaded is consumed before the single wait at the end of the entry: a use
+  // would wait for every load issued before it (vmcnt counts in order).
   int inf_r[NCI];
 #pragma unroll
   for (int it = 0; it < NCI; ++it) {
     const int c = tid + it * 256;
     const int gx = rcx0 + c % RCX, gy = rcy0 + c / RCX;
     const bool in = c < NRC && gx >= 0 && gx < pr.n[0] && gy >= 0 && gy < pr.n[1];
-    const int v = pr.info[in ? gx + pr.n[0] * gy : 0];
-    inf_r[it] = in ? v : kInfoOut;
+    inf_r[it] = pr.info[in ? gx + pr.n[0] * gy : 0];
+  }
+  int scell[2] = {-1 << 20, -1 << 20};
+  double sf0 = 1.0;
+  if (tid == 0 && pr.src != nullptr) {
+    scell[0] = pr.src[rhs].cell[0];
+    scell[1] = pr.src[rhs].cell[1];
+    sf0 = pr.src[rhs].f0;
+  }
+  // flag words of the owned rows (uniform: scalar loads); the 64 nodes of a row from
+  // ox0 on span at most three words
+  uint32_t fw_r[NRW][3];
+#pragma unroll
+  for (int r = 0; r < NRW; ++r) {
+    const int gy = min(oy0 + wave + 4 * r, npy - 1);
+    const uint32_t* fw = pr.mflag + (size_t)gy * pr.wpr + (ox0 >> 5);
+    fw_r[r][0] = fw[0];
+    fw_r[r][1] = fw[1];
+    fw_r[r][2] = fw[2];
   }
   // region rows straight into LDS; lanes left of the grid or past the array read 0,
   // lanes past a row end read the next row: both feed only cells outside the grid
@@ -147,128 +164,129 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
         buffer_dword_to_lds<T>(ursrc, rowbyte + dw * 4, (uint32_t*)(u_s + ry * W) + ch * 64);
     }
   }
-  // owned rows of d and M^{-1}, straight into LDS as well (row oy -> slot oy)
-  const __amdgpu_buffer_rsrc_t drsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)dst_d, (short)0, (int)nbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t mrsrc =
-      __builtin_amdgcn_make_buffer_rsrc((void*)pr.invm, (short)0, (int)nbytes, 0x00020000);
-  for (int oy = wave; oy < ony; oy += 4) {
-    const int rowbyte = ((oy0 + oy) * npx + ox0) * (int)sizeof(T);
-#pragma unroll
-    for (int ch = 0; ch < DPE; ++ch) {
-      const int dw = ch * 64 + lane;
-      buffer_dword_to_lds<T>(drsrc, rowbyte + dw * 4, (uint32_t*)(d_s + oy * 64) + ch * 64);
-      buffer_dword_to_lds<T>(mrsrc, rowbyte + dw * 4, (uint32_t*)(m_s + oy * 64) + ch * 64);
-    }
-  }
-  for (int i = tid; i < RNY * W; i += 256) r_s[i] = T(0);
-#pragma unroll
-  for (int it = 0; it < NCI; ++it) {
-    const int c = tid + it * 256;
-    if (c < NRC) info_s[c] = inf_r[it];
-  }
-  if (tid == 0) {
-    src_on = 0;
-    ft_s = 0.0;
-    if (pr.src != nullptr) {
-      const SourceDev& s = pr.src[rhs];
-      const int sx0 = s.cell[0] * P, sy0 = s.cell[1] * P;
-      if (sx0 + P >= ox0 && sx0 < ox0 + onx && sy0 + P >= oy0 && sy0 < oy0 + ony) {
-        src_on = 1;
-        ft_s = ricker(t, s.f0);
-      }
-    }
-  }
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-
-  // ---- element products, colour class by colour class ----
-  int offk[NKS];
-#pragma unroll
-  for (int kk = 0; kk < NKS; ++kk) {
-    const int j = min(4 * kk + lk, NL - 1);
-    offk[kk] = (j % NP1) + (j / NP1) * W;
-  }
-  // output rows of this lane (MFMA D layout) and their node offsets in a cell
-  int offo[NMB][4];
+  T areg[NMB][NKS];
 #pragma unroll
   for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = mb * 16 + Mma<T>::row(lk, r);
-      offo[mb][r] = (i < NL) ? (i % NP1) + (i / NP1) * W : -1;
+    for (int kk = 0; kk < NKS; ++kk) {
+      const int r = mb * 16 + lc, cc = 4 * kk + lk;
+      areg[mb][kk] = pr.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
     }
-  using Bits = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+  // d of the owned rows (lane = x) and the 1-D inverse weights of the analytic masses
+  const int gx = ox0 + lane;
+  const bool xin = lane < min(onx, OWX);
+  const uint32_t node0 = (uint32_t)(oy0 * npx + gx);
+  const double iwx = pr.invw[min(gx, npx - 1)];
+  T d_r[NRW], im_r[NRW];
+  double iwy_r[NRW];
 #pragma unroll
-  for (int color = 0; color < 4; ++color) {
-    const int px = color & 1, py = color >> 1;
-    const int nxc = (RCX - px + 1) / 2, nyc = (RCY - py + 1) / 2;
-    const int ncol = nxc * nyc;
-    // uncut cells of the class: 16 per wave on the matrix cores
-    for (int b = wave; b * 16 < ncol; b += 4) {
-      const int idx = min(b * 16 + lc, ncol - 1);
-      const int lx = px + 2 * (idx % nxc), ly = py + 2 * (idx / nxc);
-      const int c = lx + RCX * ly;
-      const bool valid = (b * 16 + lc < ncol) && (info_s[c] == kInfoUncut);
-      const int base = lx * P + ly * P * W;
-      // every lane loads; invalid cells and padded rows are masked by bits (the
-      // masked values may be stale LDS contents, never arithmetic on them)
-      const Bits vmask = valid ? ~Bits(0) : Bits(0);
-      T bv[NKS];
+  for (int r = 0; r < NRW; ++r) {
+    const int oy = wave + 4 * r;
+    // lanes and rows outside the owned box load node 0 (discarded): no branch, no
+    // address outside the array
+    const bool own = xin && oy < ony;
+    const uint32_t node = own ? node0 + (uint32_t)(oy * npx) : 0u;
+    const T dv = dst_d[node];
+    d_r[r] = own ? dv : T(0);
+    iwy_r[r] = pr.invw[npx + min(oy0 + oy, npy - 1)];
+  }
+  // stored inverse masses where the row's flag bit is set (the flags are scalar loads,
+  // counted apart from the vector loads above)
+  const int wsel = ((ox0 & 31) + lane) >> 5, wbit = (ox0 + lane) & 31;
+  bool st_r[NRW];
 #pragma unroll
-      for (int kk = 0; kk < NKS; ++kk) {
-        const Bits m = (4 * kk + lk < NL) ? vmask : Bits(0);
-        const T v = u_s[base + offk[kk]];
-        Bits vb;
-        __builtin_memcpy(&vb, &v, sizeof(T));
-        vb &= m;
-        __builtin_memcpy(&bv[kk], &vb, sizeof(T));
-      }
-      typename Mma<T>::acc acc[NMB];
+  for (int r = 0; r < NRW; ++r) {
+    const int oy = wave + 4 * r;
+    const uint32_t word = (wsel == 0) ? fw_r[r][0] : (wsel == 1 ? fw_r[r][1] : fw_r[r][2]);
+    st_r[r] = xin && oy < ony && ((word >> wbit) & 1u);
+    im_r[r] = T(0);
+    if (st_r[r]) im_r[r] = pr.invm[node0 + (uint32_t)(oy * npx)];
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
-      for (int mb = 0; mb < NMB; ++mb) acc[mb] = typename Mma<T>::acc{0, 0, 0, 0};
+  for (int it = 0; it < NCI; ++it) {
+    const int c = tid + it * 256;
+    const int gx = rcx0 + c % RCX, gy = rcy0 + c / RCX;
+    const bool in = c < NRC && gx >= 0 && gx < pr.n[0] && gy >= 0 && gy < pr.n[1];
+    if (c < NRC) info_s[c] = in ? inf_r[it] : kInfoOut;
+  }
+  if (tid == 0) {
+    const int sx0 = scell[0] * P, sy0 = scell[1] * P;
+    const bool hit = pr.src != nullptr && sx0 + P >= ox0 && sx0 < ox0 + onx &&
+                     sy0 + P >= oy0 && sy0 < oy0 + ony;
+    src_on = hit ? 1 : 0;
+    ft_s = hit ? ricker(t, sf0) : 0.0;
+  }
+  __syncthreads();
+
+  // ---- element products of every region cell into y_s (stride NLP) ----
+  {
+    // B operand offsets of this lane's k rows; padded k rows read the cell's first node
+    // (any finite value: the matching K_ref columns are zero)
+    int offk[NKS];
+#pragma unroll
+    for (int kk = 0; kk < NKS; ++kk) {
+      const int jj = 4 * kk + lk;
+      offk[kk] = (jj < NL) ? (jj % NP1) + (jj / NP1) * W : 0;
+    }
+#pragma unroll
+    for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
       for (int kk = 0; kk < NKS; ++kk)
+        if (!(mb * 16 + lc < NL && 4 * kk + lk < NL)) areg[mb][kk] = T(0);
+    // two batches of 16 cells per iteration: four independent accumulator chains
+    for (int b0 = wave; b0 < NB; b0 += 8) {
+      typename Mma<T>::acc acc[2][NMB];
+      int cc[2], inf[2];
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) acc[mb] = Mma<T>::mma(areg[mb][kk], bv[kk], acc[mb]);
-      // read-add-write into the node accumulator: no two lanes or waves of a class
-      // touch one node, so every node receives its contributions in class order; all
-      // reads of the lane are issued before the first write
-      T cur[NMB][4];
+      for (int h = 0; h < 2; ++h) {
+        const int c = (b0 + 4 * h) * 16 + lc;
+        const int cs = min(c, NRC - 1);
+        cc[h] = c;
+        inf[h] = info_s[cs];
+        const int base = (cs % RCX) * P + (cs / RCX) * P * W;
+        T bv[NKS];
 #pragma unroll
-      for (int mb = 0; mb < NMB; ++mb)
+        for (int kk = 0; kk < NKS; ++kk) bv[kk] = u_s[base + offk[kk]];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cur[mb][r] = r_s[base + max(offo[mb][r], 0)];
-      if (valid) {
+        for (int mb = 0; mb < NMB; ++mb) acc[h][mb] = typename Mma<T>::acc{0, 0, 0, 0};
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
+        for (int kk = 0; kk < NKS; ++kk)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (offo[mb][r] >= 0) r_s[base + offo[mb][r]] = cur[mb][r] + acc[mb][r];
+          for (int mb = 0; mb < NMB; ++mb)
+            acc[h][mb] = Mma<T>::mma(areg[mb][kk], bv[kk], acc[h][mb]);
+      }
+      // uncut cells their product, outside cells zeros (a select: their operands may be
+      // anything); cut cells are filled below
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (cc[h] < NRC && inf[h] < 0) {
+          const bool on = inf[h] == kInfoUncut;
+          T* yo = y_s + cc[h] * NLP;
+#pragma unroll
+          for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              yo[mb * 16 + Mma<T>::row(lk, r)] = on ? acc[h][mb][r] : T(0);
+        }
       }
     }
-    // cut cells of the class: their products come from the cut-cell kernel; one wave
-    // per cell, lane = row
+    // cut cells: their products from the cut-cell kernel, one wave per cell
     int seen = 0;
-    for (int c0 = 0; c0 < ncol; c0 += 64) {
-      const int idx = min(c0 + lane, ncol - 1);
-      const int c = (px + 2 * (idx % nxc)) + RCX * (py + 2 * (idx / nxc));
-      unsigned long long mask = __ballot(c0 + lane < ncol && info_s[c] >= 0);
+    for (int c0 = 0; c0 < NRC; c0 += 64) {
+      const int cq = c0 + lane;
+      unsigned long long mask = __ballot(cq < NRC && info_s[min(cq, NRC - 1)] >= 0);
       while (mask) {
         const int bit = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
         if ((seen++ & 3) != wave) continue;
-        const int ci = c0 + bit;
-        const int lx = px + 2 * (ci % nxc), ly = py + 2 * (ci / nxc);
-        const int q = info_s[lx + RCX * ly];
-        const int base = lx * P + ly * P * W;
-        const int i = min(lane, NL - 1);
-        const T y = pr.ycut[((int64_t)rhs * pr.ncand + q) * NL + i];
-        if (lane < NL) r_s[base + (i % NP1) + (i / NP1) * W] += y;
+        const int c = c0 + bit;
+        const T* yq = pr.ycut + ((int64_t)rhs * pr.ncand + info_s[c]) * NL;
+        if (lane < NL) y_s[c * NLP + lane] = yq[lane];
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   // ---- update, one owned row per wave instruction ----
   const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
@@ -276,42 +294,66 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
       __builtin_amdgcn_make_buffer_rsrc((void*)dst_d, (short)0, (int)nbytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t urs =
       __builtin_amdgcn_make_buffer_rsrc((void*)dst_u, (short)0, (int)nbytes, 0x00020000);
-  const int nx64 = min(onx, OWX);
   const bool srcflag = src_on != 0;
-  for (int oy = wave; oy < ony; oy += 4) {
+  // cells around node x = ox0 + lane (region-local): qx = lane / P + 1 with local lx, and
+  // qx - 1 with local P when lx == 0 (lanes past the owned row, which store nothing,
+  // are clamped into the region)
+  const int qx = min(lane / P + 1, RCX - 1), lxl = lane % P;
+  const T xam = (lxl == 0) ? T(1) : T(0);
+  const int ymain = qx * NLP + lxl, ycorner = (qx - 1) * NLP + P;
+  const int rxu = min(lane + P, RNX - 1);
+#pragma unroll
+  for (int r = 0; r < NRW; ++r) {
+    const int oy = wave + 4 * r;
+    if (oy >= ony) break;
     const int gy = oy0 + oy;
-    const int rowbyte = (gy * npx + ox0) * (int)sizeof(T);
-    const int rl0 = (ox0 - rnx0) + (gy - rny0) * W;
-    if (lane < nx64) {
-      const int rl = rl0 + lane;
-      T F = T(0);
-      if (srcflag) {
-        const int sx = ox0 + lane - pr.src[rhs].cell[0] * P, sy = gy - pr.src[rhs].cell[1] * P;
-        if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
-      }
-      const T dn = d_s[oy * 64 + lane] + dt2h * m_s[oy * 64 + lane] * (F - r_s[rl]);
-      const T un = u_s[rl] + dn;
-      const int vo = rowbyte + lane * (int)sizeof(T);
-      if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dn), drs, vo, 0, 0);
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, un), urs, vo, 0, 0);
-      } else {
-        dst_d[(uint32_t)(gy * npx + ox0 + lane)] = dn;
-        dst_u[(uint32_t)(gy * npx + ox0 + lane)] = un;
-      }
+    const int ry = oy + P;  // region-local node row
+    const int qy = ry / P, lyl = ry % P;
+    // fixed order: the cell row below (when the node row is its top), then the row above
+    // (when it exists); within a row the cell to the left first
+    T acc = T(0);
+    if (lyl == 0) {
+      const T* yr = y_s + (qy - 1) * RCX * NLP + P * NP1;
+      acc = acc + xam * yr[ycorner];
+      acc = acc + yr[ymain];
     }
-    if (onx > OWX && lane == 0) {  // the last node column of the grid
-      const int gx = ox0 + OWX;
-      const uint32_t node = (uint32_t)(gy * npx + gx);
-      const int rl = rl0 + OWX;
+    if (gy < pr.n[1] * P) {
+      const T* yr = y_s + qy * RCX * NLP + lyl * NP1;
+      acc = acc + xam * yr[ycorner];
+      acc = acc + yr[ymain];
+    }
+    if (xin) {
       T F = T(0);
       if (srcflag) {
         const int sx = gx - pr.src[rhs].cell[0] * P, sy = gy - pr.src[rhs].cell[1] * P;
         if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
       }
-      const T dn = dst_d[node] + dt2h * pr.invm[node] * (F - r_s[rl]);
+      const T im = st_r[r] ? im_r[r] : analytic_invm<T>(pr.cm, iwx, iwy_r[r], 1.0);
+      const T dn = d_r[r] + dt2h * im * (F - acc);
+      const T un = u_s[ry * W + rxu] + dn;
+      const int vo = (gy * npx + gx) * (int)sizeof(T);
+      if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dn), drs, vo, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, un), urs, vo, 0, 0);
+      } else {
+        dst_d[(uint32_t)(gy * npx + gx)] = dn;
+        dst_u[(uint32_t)(gy * npx + gx)] = un;
+      }
+    }
+    if (onx > OWX && lane == 0) {  // the last node column of the grid (x = n_x P)
+      const int gxe = ox0 + OWX;
+      const uint32_t node = (uint32_t)(gy * npx + gxe);
+      T acc2 = T(0);
+      if (lyl == 0) acc2 = acc2 + y_s[((qy - 1) * RCX + RCX - 1) * NLP + P * NP1 + P];
+      if (gy < pr.n[1] * P) acc2 = acc2 + y_s[(qy * RCX + RCX - 1) * NLP + lyl * NP1 + P];
+      T F = T(0);
+      if (srcflag) {
+        const int sx = gxe - pr.src[rhs].cell[0] * P, sy = gy - pr.src[rhs].cell[1] * P;
+        if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
+      }
+      const T dn = dst_d[node] + dt2h * pr.invm[node] * (F - acc2);
       dst_d[node] = dn;
-      dst_u[node] = u_s[rl] + dn;
+      dst_u[node] = u_s[ry * W + OWX + P] + dn;
     }
   }
 }
@@ -340,7 +382,7 @@ int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
   struct E { int p, ty; Run2d f32, f64; };
 #define FCW_E(PP, TY) E{PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
-      FCW_E(1, 16), FCW_E(1, 32), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
+      FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
       FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8)};
 #undef FCW_E
   int n = 0;
@@ -365,6 +407,10 @@ static void fill_prob(const Ctx& c, void* out, void* ua, void* ub, void* d, doub
   p.ub = (T*)ub;
   p.d = (T*)d;
   p.invm = (const T*)c.d_invm;
+  p.mflag = c.d_mflag;
+  p.invw = c.d_invw;
+  p.cm = c.cm;
+  p.wpr = c.mflag_wpr;
   p.info = c.d_info;
   p.kref = (const T*)c.d_kref_s;
   p.ycut = (const T*)c.d_ycut;
