@@ -202,6 +202,28 @@ def bench_c3(steps, warmup, with_fp64):
     return out
 
 
+def bench_serve(count, scale, rate, quantum):
+    """Serving loop over the first `count` requests of the request stream (seed 5),
+    cell counts per side scaled by `scale`; Poisson arrivals at `rate` requests/s
+    (None: all at t=0)."""
+    import workloads
+    from paper_2501_19013_amd.serve import Server, requests_from_stream
+    reqs = requests_from_stream(workloads.request_stream(seed=5, count=count, rate=rate),
+                                scale=scale)
+    srv = Server(precision="fp32", quantum=quantum)
+    m = srv.run(reqs)
+    srv.close()
+    n2 = sum(1 for r in reqs if r.cfg["dim"] == 2)
+    m.update(requests=count, scale=scale, rate_per_s=rate, quantum=quantum,
+             mix=f"{n2} 2-D, {count - n2} 3-D scalar; p in 2-4; 200-2000 steps",
+             workload=f"first {count} requests of the serving stream (seed 5), cell counts per "
+                      f"side x{scale:g}, FP32 step, FP64 setup per request, arrivals "
+                      + ("all at t=0" if rate is None else f"Poisson {rate:g}/s"))
+    print(f"[bench] serving: {m['n']} requests in {m['makespan_s']:.1f} s, p50 "
+          f"{m['p50_latency_s']:.2f} s, p99 {m['p99_latency_s']:.2f} s", file=sys.stderr, flush=True)
+    return m
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -224,6 +246,10 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--c3-warmup", type=int, default=10)
+    ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.5, help="cell counts per side x this")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per s (<=0: all at 0)")
+    ap.add_argument("--serve-quantum", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -265,6 +291,11 @@ def main():
         print(f"[bench] cpu baseline: {cb['sample']}", file=sys.stderr, flush=True)
     if not args.no_c3:
         res["c3"] = bench_c3(args.c3_steps, args.c3_warmup, not args.no_fp64)
+    if args.serve_count > 0:
+        res["serving"] = bench_serve(args.serve_count, args.serve_scale,
+                                     None if args.serve_rate <= 0 else args.serve_rate,
+                                     args.serve_quantum)
+        res["p99_latency_s"] = res["serving"]["p99_latency_s"]
     if args.calib:
         calibrate_copy()
     print(json.dumps(res))

@@ -39,6 +39,7 @@ class Request:
     # filled by the server
     admitted: float = None
     dt: float = None
+    setup_s: float = None     # wall time of its set-up (classification .. critical step)
     done: float = None
     dofs: int = 0
     state: object = None      # final u (host copy) when keep_results
@@ -91,6 +92,7 @@ class Server:
     # -- setup on the side stream (background thread) --
     def _setup(self, req):
         torch = self.torch
+        t_setup = time.perf_counter()
         with torch.cuda.device(self.device):
             ctx = fcw.assemble_cells(req.cfg, self.precision,
                                      stream=self.setup_stream.cuda_stream)
@@ -117,6 +119,7 @@ class Server:
         fp = info["footprint_bytes"] + 3 * u.numel() * u.element_size()
         req.dofs = int(info["ndof"]) * nrhs
         req.dt = dt
+        req.setup_s = time.perf_counter() - t_setup
         return _Resident(req=req, ctx=ctx, u=u, d=d, dt=dt, footprint=fp)
 
     def run(self, requests, time_scale=1.0):
@@ -130,6 +133,7 @@ class Server:
         now = lambda: (time.perf_counter() - t_start) / time_scale
         total_updates = 0
         max_resident = peak_reserved = quanta = 0
+        step_s = 0.0
         pi = 0
         while pi < len(pending) or waiting or resident or setting_up:
             t = now()
@@ -162,6 +166,7 @@ class Server:
             # one quantum for every resident problem, fused by kind
             max_resident = max(max_resident, len(resident))
             quanta += 1
+            t_q = time.perf_counter()
             groups = {}
             for r in resident:
                 c = r.req.cfg
@@ -181,6 +186,7 @@ class Server:
                         for e in entries:
                             fcw.run([e])
             self.stream.synchronize()
+            step_s += time.perf_counter() - t_q
             t = now()
             still = []
             for r in resident:
@@ -199,7 +205,11 @@ class Server:
             resident = still
         makespan = now()
         lat = np.array([r.done - r.arrival for r in finished])
+        setup = np.array([r.setup_s for r in finished])
         return dict(n=len(finished), makespan_s=makespan, quanta=quanta,
+                    setup_s_total=float(setup.sum()) if len(setup) else 0.0,
+                    setup_s_max=float(setup.max()) if len(setup) else 0.0,
+                    stepping_s=step_s,
                     max_resident=max_resident, peak_reserved_bytes=peak_reserved,
                     dof_updates_per_s=total_updates / max(makespan, 1e-12),
                     p50_latency_s=float(np.percentile(lat, 50)) if len(lat) else None,

@@ -143,6 +143,7 @@ def request_stream(seed=5, count=256, rate=None):
     times; ``None`` gives arrival time 0 for all (closed-loop).
     """
     rng = np.random.default_rng(seed)
+    arr = np.random.default_rng([seed, 1])  # arrivals apart: the requests do not depend on rate
     reqs = []
     t = 0.0
     for i in range(count):
@@ -151,7 +152,7 @@ def request_stream(seed=5, count=256, rate=None):
         p = int(rng.integers(2, 5))
         steps = int(rng.integers(200, 2001))
         if rate is not None:
-            t += rng.exponential(1.0 / rate)
+            t += arr.exponential(1.0 / rate)
         reqs.append(dict(id=i, dim=dim, n=side, p=p, nsteps=steps, void_seed=1000 + i,
                          arrival=t))
     return reqs
