@@ -192,13 +192,20 @@ def bench_c3(steps, warmup, with_fp64):
                ms_per_step=ms_step, steps=steps, warmup=warmup,
                ndof=r32["info"]["ndof"], active_dof=r32["active"], n_cut=r32["info"]["n_cut"],
                dt=r32["dt"], roofline=roofline(cfg, r32))
+    rbf = run_gpu(cfg, "bf16", steps, warmup, dt=r32["dt"])
+    print(f"[bench] c3 bf16: {steps} steps in {rbf['ms']:.2f} ms", file=sys.stderr, flush=True)
+    out["bf16_split"] = dict(value=rbf["active"] * steps / (rbf["ms"] * 1e-3),
+                             ms_per_step=rbf["ms"] / steps, roofline=roofline(cfg, rbf))
     if with_fp64:
         r64 = run_gpu(cfg, "fp64", steps, warmup, dt=r32["dt"])
         print(f"[bench] c3 fp64: {steps} steps in {r64['ms']:.2f} ms", file=sys.stderr, flush=True)
         out["fp64_gpu"] = dict(value=r64["active"] * steps / (r64["ms"] * 1e-3),
                                ms_per_step=r64["ms"] / steps)
         out["speedup_vs_fp64_gpu"] = out["value"] / out["fp64_gpu"]["value"]
-        out["rel_l2_vs_fp64"] = float(np.linalg.norm(r32["u"] - r64["u"]) / np.linalg.norm(r64["u"]))
+        nrm = np.linalg.norm(r64["u"])
+        out["rel_l2_vs_fp64"] = float(np.linalg.norm(r32["u"] - r64["u"]) / nrm)
+        out["bf16_split"]["rel_l2_vs_fp64"] = float(np.linalg.norm(rbf["u"] - r64["u"]) / nrm)
+        out["bf16_split"]["speedup_vs_fp64_gpu"] = out["bf16_split"]["value"] / out["fp64_gpu"]["value"]
     return out
 
 

@@ -49,7 +49,7 @@ static void free_all(Ctx& c) {
   dfree(c.d_tab); dfree(c.d_kref); dfree(c.d_mfull); dfree(c.d_lref); dfree(c.d_kcut);
   dfree(c.d_mcut); dfree(c.d_lumped); dfree(c.d_margin); dfree(c.d_evs_fail); dfree(c.d_mass);
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
-  dfree(c.d_invw); dfree(c.d_mflag);
+  dfree(c.d_invw); dfree(c.d_mflag); dfree(c.d_kref_bf);
   dfree(c.d_src);
   dfree(c.d_wl);
   if (c.h_wl) (void)hipHostFree(c.h_wl);
@@ -149,7 +149,7 @@ fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out) {
     set_error("need E > 0 and -1 < nu < 0.5");
     return FCW_E_ARG;
   }
-  if (d.precision != FCW_FP64 && d.precision != FCW_FP32) {
+  if (d.precision != FCW_FP64 && d.precision != FCW_FP32 && d.precision != FCW_BF16) {
     set_error("precision %d not built", d.precision);
     return FCW_E_UNSUPPORTED;
   }

@@ -78,6 +78,7 @@ struct Ctx {
   // per-step operands in the step precision
   void* d_invm = nullptr;     // [nnodes]
   void* d_kref_s = nullptr;   // [n_loc^2]
+  void* d_kref_bf = nullptr;  // BF16 form: K_ref split into bf16 hi + lo, MFMA fragment order
   void* d_kcut_s = nullptr;   // [n_cut_cand * n_loc(n_loc+1)/2], packed upper, column-major
   double* d_invm64 = nullptr; // [nnodes] FP64 copy for the Lanczos iteration
   // analytic inverse mass of nodes whose cells are all uncut: invm = cm * invw_x * invw_y

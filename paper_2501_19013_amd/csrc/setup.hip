@@ -1329,6 +1329,46 @@ __global__ void mflag_kernel(const int8_t* needs, uint32_t* words, int npx, int6
   words[w] = bits;
 }
 
+// FP64 -> bf16, rounded to nearest even directly from the double (no FP32 double
+// rounding); finite normal inputs in the FP32 exponent range, and zero
+__device__ static uint16_t bf16_rne(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint16_t sign = (uint16_t)((b >> 48) & 0x8000u);
+  const int e = (int)((b >> 52) & 0x7ff);
+  if (e == 0) return sign;
+  if (e < 1023 - 126 || e > 1023 + 127) {  // outside the normal range: through FP32
+    const uint32_t f = __float_as_uint((float)x);
+    return (uint16_t)((f + 0x7fffu + ((f >> 16) & 1u)) >> 16);
+  }
+  const uint64_t m = b & ((1ull << 52) - 1);
+  uint32_t v = (uint32_t)((e - 1023 + 127) << 7) | (uint32_t)(m >> 45);
+  const uint64_t rest = m & ((1ull << 45) - 1), half = 1ull << 44;
+  if (rest > half || (rest == half && (v & 1u))) ++v;  // a carry moves into the exponent
+  return (uint16_t)(sign | (v & 0x7fffu));
+}
+
+__device__ static double bf16_value(uint16_t h) {
+  return (double)__uint_as_float((uint32_t)h << 16);
+}
+
+// K_ref split into bf16 hi + lo (hi = nearest bf16 of K, lo = nearest bf16 of K - hi),
+// laid out as the MFMA A fragments of 16x16x32: [mb][kb][hi/lo][lane][e] holds row
+// mb*16 + lane%16, column kb*32 + 8*(lane/16) + e (zero outside the matrix)
+__global__ void bf16_frag_kernel(const double* k, uint16_t* out, int nl, int nmb, int nkb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nmb * nkb * 64 * 8;
+  if (t >= total) return;
+  const int e = (int)(t % 8), lane = (int)((t / 8) % 64);
+  const int kb = (int)((t / 512) % nkb), mb = (int)(t / (512 * nkb));
+  const int r = mb * 16 + lane % 16, cc = kb * 32 + 8 * (lane / 16) + e;
+  const double v = (r < nl && cc < nl) ? k[(int64_t)r * nl + cc] : 0.0;
+  const uint16_t hi = bf16_rne(v);
+  const uint16_t lo = bf16_rne(v - bf16_value(hi));
+  const int64_t base = (((int64_t)mb * nkb + kb) * 2) * 64 * 8 + lane * 8 + e;
+  out[base] = hi;
+  out[base + 64 * 8] = lo;
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* in, T* out, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1422,6 +1462,16 @@ fcw_status setup_mass_and_pack(Ctx& c) {
       pack_upper_kernel<double><<<gp, 256, 0, c.stream>>>(c.d_kcut, (double*)c.d_kcut_s, (int)nl,
                                                           c.n_cut_cand);
   } else {
+    if (c.precision == FCW_BF16) {
+      const int nmb = (int)((nl + 15) / 16), nkb = (int)((nl + 31) / 32);
+      const int64_t nfrag = (int64_t)nmb * nkb * 2 * 64 * 8;  // bf16 values
+      if (!c.d_kref_bf) {
+        FCW_HIP(hipMalloc(&c.d_kref_bf, (size_t)nfrag * 2));
+        c.footprint += nfrag * 2;
+      }
+      bf16_frag_kernel<<<(unsigned)((nfrag / 2 + 255) / 256), 256, 0, c.stream>>>(
+          c.d_kref, (uint16_t*)c.d_kref_bf, (int)nl, nmb, nkb);
+    }
     invm_kernel<float><<<gn, 256, 0, c.stream>>>(ia, (float*)c.d_invm);
     cast_kernel<float><<<gk, 256, 0, c.stream>>>(c.d_kref, (float*)c.d_kref_s, nl * nl);
     if (c.n_cut_cand > 0)

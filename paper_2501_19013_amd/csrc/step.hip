@@ -38,7 +38,7 @@ __device__ static inline void load_dword_to_lds(const void* gsrc, void* lds_wave
                                    0);
 }
 
-template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE>
+template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE, bool BF>
 __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   constexpr int NP1 = P + 1;
   constexpr int NS = ipow(NP1, DIM);
@@ -54,9 +54,14 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   constexpr int RNY = (DIM >= 2) ? RCY * P + 1 : 1;
   constexpr int RNZ = (DIM == 3) ? RCZ * P + 1 : 1;
   constexpr int NRN = RNX * RNY * RNZ;
-  constexpr bool AREG = NMB * NKS <= 32;  // keep K_ref fragments in VGPRs
+  // bf16 operands (BF16 form): 16x16x32 MFMA, K_ref rows in k blocks of 32
+  constexpr int NKB = (NL + 31) / 32;
+  // split bf16 fragments of K_ref (hi, lo) in lane order: [mb][kb][hi/lo][lane] x 8 bf16
+  constexpr int NFRAG = BF ? NMB * NKB * 2 * 64 : 1;
+  constexpr int KWB = BF ? NKB * 32 : KW;
+  constexpr bool AREG = !BF && NMB * NKS <= 32;  // keep K_ref fragments in VGPRs
   // otherwise stage them in LDS when small enough, else read them through the caches
-  constexpr bool ALDS = !AREG && (NMB * 16 * KW * (int)sizeof(T) <= 48 * 1024);
+  constexpr bool ALDS = !BF && !AREG && (NMB * 16 * KW * (int)sizeof(T) <= 48 * 1024);
   constexpr int NB = (NRC + 15) / 16;
   // owned node box of a tile (at most; edge tiles own one more node row)
   constexpr int OX = TX * P + 1;
@@ -73,7 +78,8 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   __shared__ T y_s[NRC * NL];
   __shared__ T a_s[ALDS ? NMB * 16 * KW : 1];
   __shared__ int info_s[NRC];
-  __shared__ int off_s[KW];
+  __shared__ int off_s[KWB];
+  __shared__ bf16x8 a_sb[NFRAG];
   __shared__ double ft_s;
   __shared__ int src_on;
 
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       a_s[i] = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
     }
   }
-  for (int j = tid; j < KW; j += 256) {
+  for (int j = tid; j < KWB; j += 256) {
     int off = -1;
     if (j < NL) {
       const int comp = j / NS, loc = j % NS;
@@ -210,13 +216,64 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       }
     }
   }
-  if (DIRECT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if constexpr (BF) {
+    // contiguous copy of the lane-ordered fragments (NFRAG x 16 bytes), 64 dwords per
+    // wave instruction
+    const uint32_t* src = (const uint32_t*)a.kref_bf;
+    for (int w = wave; w < NFRAG * 4 / 64; w += 4)
+      load_dword_to_lds(src + w * 64 + lane, (uint32_t*)a_sb + w * 64);
+  }
+  if (DIRECT || BF) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   // ---- uncut cells: batched K_ref contraction on the matrix cores ----
   // Every non-cut cell of the region gets its row of y_s here: uncut cells their
   // product, cells outside the domain zeros (their B operand is masked to zero).
-  {
+  if constexpr (BF) {
+    // BF16 form: operands split into bf16 hi + lo parts (nearest even), the four products
+    // K_lo u_lo + K_lo u_hi + K_hi u_lo + K_hi u_hi accumulated in FP32, smallest first
+    for (int b = wave; b < NB; b += 4) {
+      const int c = b * 16 + lc;
+      const int cs = min(c, NRC - 1);
+      const int inf = info_s[cs];
+      const bool valid = (c < NRC) && (inf == kInfoUncut);
+      const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
+      const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
+      f32x4 acc[NMB];
+#pragma unroll
+      for (int mb = 0; mb < NMB; ++mb) acc[mb] = f32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        bf16x8 bhi, blo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int off = off_s[kb * 32 + 8 * lk + e];
+          const float v = (valid && off >= 0) ? (float)u_s[base + max(off, 0)] : 0.0f;
+          const __bf16 h = (__bf16)v;
+          bhi[e] = h;
+          blo[e] = (__bf16)(v - (float)h);  // exact in FP32
+        }
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+          const bf16x8 ahi = a_sb[((mb * NKB + kb) * 2 + 0) * 64 + lane];
+          const bf16x8 alo = a_sb[((mb * NKB + kb) * 2 + 1) * 64 + lane];
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[mb], 0, 0, 0);
+          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[mb], 0, 0, 0);
+        }
+      }
+      if (c < NRC && inf < 0) {
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = mb * 16 + 4 * lk + r;
+            if (i < NL) y_s[c * NL + i] = (T)acc[mb][r];
+          }
+      }
+    }
+  } else {
     int offk[NKS];
 #pragma unroll
     for (int kk = 0; kk < NKS; ++kk) offk[kk] = off_s[4 * kk + lk];
@@ -262,7 +319,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
           }
       }
     }
-  }
+  }  // FP32 / FP64 operands
 
   // ---- cut cells: products computed once per step by the cut-cell kernel ----
   if (MODE != kModeLanczos) {
@@ -437,7 +494,7 @@ static StepArgs<T> make_args(const Ctx& c, int tx, int ty, int tz) {
 
 using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, double, int);
 
-template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ>
+template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, bool BF = false>
 struct TileCfg {
   static StepArgs<T> args(Ctx& c, const void* uin, void* uout, void* d, double t, double dt,
                           int start, int mode) {
@@ -455,6 +512,7 @@ struct TileCfg {
     }
     a.ycut = (const T*)c.d_ycut;
     a.ncand = c.n_cut_cand;
+    a.kref_bf = c.d_kref_bf;
     return a;
   }
   // every mode (the default configuration of a problem kind)
@@ -469,14 +527,14 @@ struct TileCfg {
     if (mode == kModeStep) {
       fcw_status st = timing_begin(c, kTimeMain);
       if (st) return st;
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
+      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
       FCW_HIP(hipGetLastError());
       return timing_end(c, kTimeMain);
     }
     if (mode == kModeApply)
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply><<<grid, 256, 0, c.stream>>>(a);
+      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF><<<grid, 256, 0, c.stream>>>(a);
     else
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos><<<grid, 256, 0, c.stream>>>(a);
+      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos, false><<<grid, 256, 0, c.stream>>>(a);
     FCW_HIP(hipGetLastError());
     return FCW_OK;
   }
@@ -492,7 +550,7 @@ struct TileCfg {
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
     if ((st = timing_begin(c, kTimeMain))) return st;
-    tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep><<<grid, 256, 0, c.stream>>>(a);
+    tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
     FCW_HIP(hipGetLastError());
     return timing_end(c, kTimeMain);
   }
@@ -549,7 +607,34 @@ static int candidates(const Ctx& c, Cand* out) {
 
 constexpr int kMaxCand = 8;
 
+// BF16 form: FP32 state, bf16 operands of the uncut contraction
+static int candidates_bf(const Ctx& c, Cand* out) {
+  int n = 0;
+#define FCW_B0(D, PP, NC, TX, TY, TZ)                  \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run, {TX, TY, TZ}};
+#define FCW_B(D, PP, NC, TX, TY, TZ)                   \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run_step, {TX, TY, TZ}};
+  FCW_B0(2, 1, 1, 32, 32, 1)
+  FCW_B0(2, 2, 1, 16, 16, 1) FCW_B(2, 2, 1, 16, 8, 1)
+  FCW_B0(2, 3, 1, 16, 16, 1) FCW_B(2, 3, 1, 16, 8, 1)
+  FCW_B0(2, 4, 1, 16, 8, 1) FCW_B(2, 4, 1, 16, 16, 1) FCW_B(2, 4, 1, 8, 8, 1)
+  FCW_B0(2, 5, 1, 16, 8, 1) FCW_B(2, 5, 1, 8, 8, 1)
+  FCW_B0(2, 6, 1, 8, 8, 1)
+  FCW_B0(3, 1, 1, 8, 8, 8)
+  FCW_B0(3, 2, 1, 8, 4, 4) FCW_B(3, 2, 1, 4, 4, 4)
+  FCW_B0(3, 3, 1, 4, 4, 4) FCW_B(3, 3, 1, 4, 4, 2)
+  FCW_B0(3, 4, 1, 4, 4, 2) FCW_B(3, 4, 1, 4, 2, 2)
+  FCW_B0(3, 1, 3, 8, 4, 4)
+  FCW_B0(3, 2, 3, 4, 4, 2) FCW_B(3, 2, 3, 4, 4, 4) FCW_B(3, 2, 3, 4, 2, 2)
+#undef FCW_B0
+#undef FCW_B
+  return n;
+}
+
 static int cands_for(const Ctx& c, bool fp64, Cand* out) {
+  if (!fp64 && c.precision == FCW_BF16) return candidates_bf(c, out);
   return fp64 ? candidates<double>(c, out) : candidates<float>(c, out);
 }
 
@@ -581,7 +666,9 @@ struct StepCand {
 
 static int step_candidates(const Ctx& c, int i, StepCand* out) {
   const int fp64 = c.precision == FCW_FP64;
-  const int n2 = (c.dim == 2 && c.ncomp == 1) ? step2d_candidates(c.p, fp64, -1, nullptr, nullptr) : 0;
+  const int n2 = (c.dim == 2 && c.ncomp == 1 && c.precision != FCW_BF16)
+                     ? step2d_candidates(c.p, fp64, -1, nullptr, nullptr)
+                     : 0;
   Cand cs[kMaxCand];
   const int ng = cands_for(c, fp64, cs);
   if (out) {
@@ -608,8 +695,9 @@ int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name) {
     if (sc.f2d)
       std::snprintf(b, sizeof b, "fcw::step2d_kernel<%s, %d, %d, true>", t, c.p, sc.tile[1]);
     else
-      std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d>", t, c.dim,
-                    c.p, c.ncomp, sc.tile[0], sc.tile[1], sc.tile[2], (int)kModeStep);
+      std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d, %s>", t, c.dim,
+                    c.p, c.ncomp, sc.tile[0], sc.tile[1], sc.tile[2], (int)kModeStep,
+                    c.precision == FCW_BF16 ? "true" : "false");
     *name = b;
   }
   return n;
@@ -649,7 +737,7 @@ static fcw_status group_step(Ctx& owner, Run2d fn, const void* dprobs, const int
 
 bool groupable_2d(const Ctx& a, const Ctx& b) {
   return a.dim == 2 && b.dim == 2 && a.ncomp == 1 && b.ncomp == 1 && a.p == b.p &&
-         a.precision == b.precision;
+         a.precision == b.precision && a.precision != FCW_BF16;
 }
 
 // A batched group: the first member's configuration choice gives the 2-D kernel (its tile

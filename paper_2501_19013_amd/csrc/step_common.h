@@ -9,6 +9,7 @@ namespace fcw {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct Mma;
@@ -52,6 +53,7 @@ struct StepArgs {
   const SourceDev* src;
   double t;
   const T* ycut;  // [nrhs][ncand][n_loc] cut-cell products of this step (step / apply)
+  const void* kref_bf;  // [n_loc^2] bf16 K_ref (BF16 form)
   int64_t ncand;
 };
 

@@ -267,6 +267,37 @@ def test_scalar_3d_p4_run_parity(precision, tol):
     s.close()
 
 
+# BF16 form: the uncut contraction runs on bf16 matrix cores with both operands split
+# into bf16 hi + lo parts (four products, FP32 accumulation).  The split keeps 16 bits of
+# each operand: a relative operand error of 2^-17 against 2^-24 for FP32, 128 times
+# larger.  The FP32 runs of these cases stay below 4e-6, so the bar is 128 x 4e-6 = 5e-4
+# (measured: 8.6e-5 on C1, 2.1e-4 on the elastic case).
+BF16_TOL = 5e-4
+
+
+def test_bf16_c1_parity(c1):
+    cfg, disc, dt = c1
+    s = _solver(cfg, "bf16")
+    got = _run_gpu(s, cfg, dt, 500, [500])
+    ref = timestep.cdm(disc, dt, 500, sources=cfg["sources"])["u"]
+    assert rel_l2(got[500], ref) <= BF16_TOL
+    s.close()
+
+
+def test_bf16_elastic_3d_parity():
+    # 5^3 cells, p=2, one ball: 102 uncut cells on the bf16 path, 23 cut cells
+    cfg = workloads._base(3, (5, 5, 5), 2, [(0.55, 0.5, 0.5)], [0.2], ncomp=3, nsteps=100)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    ref = timestep.cdm(disc, dt, 100, sources=cfg["sources"])["u"]
+    for precision, tol in (("fp32", 1e-4), ("bf16", BF16_TOL)):
+        s = _solver(cfg, precision)
+        got = _run_gpu(s, cfg, dt, 100, [100])
+        assert rel_l2(got[100], ref) <= tol, precision
+        s.close()
+
+
 def test_error_paths():
     from paper_2501_19013_amd import fcw
     cfg = workloads.config("c1")
