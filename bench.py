@@ -17,9 +17,10 @@ Roofline: a step is two kernels, the cut-cell product kernel (it streams the pac
 cut-cell matrices, N_cut (n_loc(n_loc+1)/2 s + 4) bytes) and the main step kernel (the
 state: 3 s N_dof + s N_cutadj + N_cells / 8 bytes -- read u_k and u_{k-1}, write u_{k+1};
 the non-analytic inverse masses next to cut cells; one class bit per cell).  Each
-kernel's algorithmic bytes are divided by its own average launch duration, measured
-with HIP events around every launch on the solver's stream, against 8 TB/s of HBM3E;
-`roofline` reports the main kernel, which dominates the step time.
+kernel's algorithmic bytes are divided by its own average launch duration, measured with
+HIP events on the solver's stream around --steps launches of that kernel back to back
+(fcw_kernel_times), against 8 TB/s of HBM3E; `roofline` reports the main kernel, which
+dominates the step time.
 
 cpu_baseline: the FP64 numpy oracle (single BLAS thread) stepping the same full-size
 problem for a bounded number of steps on the host.
@@ -95,14 +96,9 @@ def run_gpu(cfg, precision, steps, warmup, dt=None):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    # per-kernel durations (HIP events around every launch, on the solver's stream) from a
-    # second pass over scratch state, so the timed state above is not disturbed
-    u2, d2 = s.zeros(1), s.zeros(1)
-    fcw.timing(s.ctx, 1)
-    s.step(u2, d2, src, dt, steps, t0=0.0, start=True)
-    kms = {w: fcw.timing_read(s.ctx, w) for w in (0, 1)}
-    fcw.timing(s.ctx, 0)
-    del u2, d2
+    # per-kernel launch durations: each kernel timed over `steps` launches back to back
+    # with HIP events on the solver's stream, on the library's scratch state
+    main_us, cut_us = fcw.kernel_times(s.ctx, 1, steps)
     cls = s.export(fcw.ARR_CELL_CLASS)
     mass = s.export(fcw.ARR_MASS)
     info = dict(s.info)
@@ -110,33 +106,42 @@ def run_gpu(cfg, precision, steps, warmup, dt=None):
     s.close()
     return dict(ms=ms, steps=steps, dt=dt, info=info, cls=cls, active=int((mass > 0).sum()) * cfg.get("ncomp", 1),
                 u=out, tile=table[chosen]["tile"], kernel=table[chosen]["kernel"],
-                main_ms=kms[0][0] / max(kms[0][1], 1), main_launches=kms[0][1],
-                cut_ms=kms[1][0] / max(kms[1][1], 1), cut_launches=kms[1][1],
+                main_ms=main_us * 1e-3, main_launches=steps,
+                cut_ms=cut_us * 1e-3, cut_launches=steps if cut_us > 0 else 0,
                 cut_kernel="fcw::cut_apply_kernel<%s, %d, %d, %d, true>" % (
-                    "float" if precision == "fp32" else "double", cfg["dim"], cfg["p"],
+                    "double" if precision == "fp64" else "float", cfg["dim"], cfg["p"],
                     cfg.get("ncomp", 1)))
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed counter summaries under
     profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when none
-    was taken or the kernel's source has changed since."""
+    was taken or the kernel's sources have changed since (each summary names the files
+    its sha1 covers)."""
     import glob
     import hashlib
-    h = hashlib.sha1()
-    for f in ("paper_2501_19013_amd/csrc/step2d.hip", "paper_2501_19013_amd/csrc/step_common.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    sha = h.hexdigest()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
-        fields = {}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
-            for line in fh:
-                k, _, v = line.partition(":")
-                if k in ("kernel", "traffic_bytes_per_launch", "source_sha1"):
-                    fields[k] = v.split()[0] if k == "source_sha1" else v.strip()
-        if fields.get("kernel") == kernel and fields.get("source_sha1") == sha:
-            return float(fields["traffic_bytes_per_launch"])
+            lines = fh.read().splitlines()
+        for i, line in enumerate(lines):
+            if line.strip() != f"kernel: {kernel}":
+                continue
+            fields = {}
+            for l2 in lines[i + 1:i + 4]:
+                k, _, v = l2.partition(":")
+                fields[k.strip()] = v.strip()
+            if "traffic_bytes_per_launch" not in fields or "source_sha1" not in fields:
+                continue
+            sha, _, files = fields["source_sha1"].partition(" ")
+            h = hashlib.sha1()
+            names = files.strip("() ").replace("sha1 over ", "").split(", ")
+            if not all(os.path.exists(os.path.join(ROOT, f)) for f in names):
+                continue
+            for f in names:
+                with open(os.path.join(ROOT, f), "rb") as fh:
+                    h.update(fh.read())
+            if h.hexdigest() == sha:
+                return float(fields["traffic_bytes_per_launch"])
     return None
 
 
@@ -248,7 +253,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 reference run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter scale)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
     ap.add_argument("--c3-steps", type=int, default=1000)

@@ -172,15 +172,13 @@ fcw_status fcw_select_tile(fcw_ctx* ctx, int32_t i);
  * running when work arrives on the new one. */
 fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
 
-/* Per-kernel timing of later step calls, for measurement: with enable != 0 every
- * launch of the step kernels is bracketed by a pair of HIP events on the context's
- * stream (counts are cleared); 0 turns it off.  Synchronises. */
-fcw_status fcw_timing(fcw_ctx* ctx, int32_t enable);
-
-/* Summed duration in milliseconds and number of launches since fcw_timing(ctx, 1) of
- * kernel kind `which`: 0 the main step kernel (tile or 2-D kernel), 1 the cut-cell
- * product kernel.  Synchronises. */
-fcw_status fcw_timing_read(fcw_ctx* ctx, int32_t which, double* ms, int64_t* launches);
+/* Average duration in microseconds of one launch of the step's main kernel (*main_us:
+ * the tile or 2-D kernel of the selected configuration) and of the cut-cell product
+ * kernel (*cut_us; 0 without cut cells), each timed over nsteps launches back to back
+ * with HIP events on the context's stream, on scratch state with nrhs right-hand sides.
+ * For measurement; the caller's state is not touched.  Synchronises. */
+fcw_status fcw_kernel_times(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, double* main_us,
+                            double* cut_us);
 
 /* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
 fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,

@@ -56,11 +56,6 @@ static void free_all(Ctx& c) {
   c.h_wl = nullptr;
   if (c.wl_event) (void)hipEventDestroy(c.wl_event);
   c.wl_event = nullptr;
-  for (int w = 0; w < 2; ++w) {
-    for (hipEvent_t e : c.tev[w]) (void)hipEventDestroy(e);
-    c.tev[w].clear();
-    c.tn[w] = 0;
-  }
   if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
   c.graph_exec = nullptr;
 }
@@ -90,26 +85,6 @@ static fcw_status check_ctx(const fcw_ctx* ctx, int need_state) {
     set_error("call out of order (context state %d, need %d)", ctx->state, need_state);
     return FCW_E_STATE;
   }
-  return FCW_OK;
-}
-
-fcw_status timing_begin(Ctx& c, int w) {
-  if (!c.timing) return FCW_OK;
-  if (c.tev[w].size() < 2 * (c.tn[w] + 1)) {
-    for (int k = 0; k < 2; ++k) {
-      hipEvent_t e = nullptr;
-      FCW_HIP(hipEventCreate(&e));
-      c.tev[w].push_back(e);
-    }
-  }
-  FCW_HIP(hipEventRecord(c.tev[w][2 * c.tn[w]], c.stream));
-  return FCW_OK;
-}
-
-fcw_status timing_end(Ctx& c, int w) {
-  if (!c.timing) return FCW_OK;
-  FCW_HIP(hipEventRecord(c.tev[w][2 * c.tn[w] + 1], c.stream));
-  ++c.tn[w];
   return FCW_OK;
 }
 
@@ -523,34 +498,68 @@ fcw_status fcw_set_stream(fcw_ctx* c, void* stream) {
   return FCW_OK;
 }
 
-fcw_status fcw_timing(fcw_ctx* c, int32_t enable) {
+fcw_status fcw_kernel_times(fcw_ctx* c, int32_t nrhs, int32_t nsteps, double* main_us,
+                            double* cut_us) {
   g_err.clear();
-  fcw_status st = check_ctx(c, 1);
+  fcw_status st = check_ctx(c, 2);
   if (st) return st;
-  FCW_HIP(hipStreamSynchronize(c->stream));
-  c->timing = enable != 0;
-  c->tn[0] = c->tn[1] = 0;
-  return FCW_OK;
-}
-
-fcw_status fcw_timing_read(fcw_ctx* c, int32_t which, double* ms, int64_t* launches) {
-  g_err.clear();
-  fcw_status st = check_ctx(c, 1);
-  if (st) return st;
-  if (which < 0 || which > 1 || !ms) {
-    set_error("which must be 0 (main kernel) or 1 (cut-cell kernel); ms non-null");
+  if (nrhs < 1 || nrhs > 64 || nsteps < 1 || !main_us || !cut_us) {
+    set_error("need 1 <= nrhs <= 64, nsteps >= 1 and non-null outputs");
     return FCW_E_ARG;
   }
-  FCW_HIP(hipStreamSynchronize(c->stream));
-  double sum = 0.0;
-  for (size_t i = 0; i < c->tn[which]; ++i) {
-    float t = 0.0f;
-    FCW_HIP(hipEventElapsedTime(&t, c->tev[which][2 * i], c->tev[which][2 * i + 1]));
-    sum += t;
+  const size_t bytes = (size_t)nrhs * c->ndof * c->state_bytes();
+  void *ua = nullptr, *dd = nullptr, *sc = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  auto cleanup = [&]() {
+    if (ua) (void)hipFree(ua);
+    if (dd) (void)hipFree(dd);
+    if (sc) (void)hipFree(sc);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (hipMalloc(&ua, bytes) != hipSuccess || hipMalloc(&dd, bytes) != hipSuccess ||
+      hipMalloc(&sc, bytes) != hipSuccess) {
+    cleanup();
+    set_error("kernel timing scratch allocation failed");
+    return FCW_E_NOMEM;
   }
-  *ms = sum;
-  if (launches) *launches = (int64_t)c->tn[which];
-  return FCW_OK;
+  for (hipEvent_t& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      cleanup();
+      return hip_fail(hipGetLastError(), "kernel timing events");
+    }
+  if (hipMemsetAsync(ua, 0, bytes, c->stream) != hipSuccess ||
+      hipMemsetAsync(dd, 0, bytes, c->stream) != hipSuccess) {
+    cleanup();
+    return hip_fail(hipGetLastError(), "kernel timing setup");
+  }
+  const SourceDev* saved = c->d_src;
+  c->d_src = nullptr;
+  // the cut-cell kernel back to back, then the main kernel back to back on its products
+  if (!(st = run_steps(*c, c->tile_choice, nrhs, ua, dd, sc, 0.0, 1e-6, 2, 1))) {
+    (void)hipEventRecord(ev[0], c->stream);
+    for (int k = 0; k < nsteps && !st; ++k) st = launch_cut_products(*c, nrhs, ua);
+    (void)hipEventRecord(ev[1], c->stream);
+  }
+  if (!st) {
+    c->skip_cut = true;
+    (void)hipEventRecord(ev[2], c->stream);
+    st = run_steps(*c, c->tile_choice, nrhs, ua, dd, sc, 0.0, 1e-6, nsteps, 0);
+    (void)hipEventRecord(ev[3], c->stream);
+    c->skip_cut = false;
+  }
+  c->d_src = const_cast<SourceDev*>(saved);
+  if (!st) {
+    float t0 = 0.0f, t1 = 0.0f;
+    if (hipEventSynchronize(ev[3]) != hipSuccess ||
+        hipEventElapsedTime(&t0, ev[0], ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t1, ev[2], ev[3]) != hipSuccess)
+      st = hip_fail(hipGetLastError(), "kernel timing");
+    *cut_us = c->n_cut_cand > 0 ? 1e3 * t0 / nsteps : 0.0;
+    *main_us = 1e3 * t1 / nsteps;
+  }
+  cleanup();
+  return st;
 }
 
 fcw_status fcw_step_imex(fcw_ctx* c, int32_t, void*, void*, void*, const fcw_source*, double,

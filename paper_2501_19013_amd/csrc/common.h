@@ -110,10 +110,7 @@ struct Ctx {
   int64_t graph_ncut = 0;
   void* graph_wl = nullptr;
   int64_t footprint = 0;
-  // optional per-kernel timing of step calls: event pairs per kernel kind
-  bool timing = false;
-  std::vector<hipEvent_t> tev[2];
-  size_t tn[2] = {0, 0};
+  bool skip_cut = false;  // step calls launch the main kernel only (kernel timing)
 
   size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
 };
@@ -145,10 +142,6 @@ fcw_status setup_reclassify(Ctx& c);
 fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda);
 fcw_status setup_mass_and_pack(Ctx& c);
 fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
-// per-kernel timing (api.hip): which = kTimeMain (tile / 2-D kernel) or kTimeCut
-enum { kTimeMain = 0, kTimeCut = 1 };
-fcw_status timing_begin(Ctx& c, int which);
-fcw_status timing_end(Ctx& c, int which);
 // cutcell.hip: cut-cell products y = K_e u_e, once per cut cell and step
 fcw_status ensure_ycut(Ctx& c, int nrhs);
 size_t cutprob_size(int fp64);

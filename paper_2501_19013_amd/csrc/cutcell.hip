@@ -266,9 +266,7 @@ fcw_status launch_cut_products(Ctx& c, int nrhs, const void* u) {
   if (st) return st;
   char rec[sizeof(CutProb<double>)];
   const int64_t nblk = cutprob_fill(c, rec, u, u, nrhs, 1, 0);
-  if ((st = timing_begin(c, kTimeCut)) || (st = launch_cut(c, c.stream, nullptr, 1, rec, nblk, 0)))
-    return st;
-  return timing_end(c, kTimeCut);
+  return launch_cut(c, c.stream, nullptr, 1, rec, nblk, 0);
 }
 
 }  // namespace fcw

@@ -1428,7 +1428,7 @@ fcw_status setup_mass_and_pack(Ctx& c) {
   // analytic inverse masses and the per-node flags
   const int npsum = c.npts[0] + (c.dim > 1 ? c.npts[1] : 0) + (c.dim > 2 ? c.npts[2] : 0);
   const int64_t nrows = c.nnodes / c.npts[0];
-  c.mflag_wpr = (c.npts[0] + 31) / 32 + 3;  // room for a 64-node row read from any start
+  c.mflag_wpr = (c.npts[0] + 31) / 32 + 6;  // room for the words a kernel row read spans
   if (!c.d_invw) {
     FCW_HIP(hipMalloc((void**)&c.d_invw, (size_t)npsum * sizeof(double)));
     FCW_HIP(hipMalloc((void**)&c.d_mflag, (size_t)nrows * c.mflag_wpr * sizeof(uint32_t)));

@@ -226,6 +226,30 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   if (DIRECT || BF) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
+  // ---- cut cells: their products (cut-cell kernel) go global -> LDS by DMA, one wave
+  // per cell, all copies in flight while the matrix cores work below ----
+  if (MODE != kModeLanczos) {
+    constexpr int DPE = (int)(sizeof(T) / 4);
+    constexpr int RDW = NL * DPE;  // dwords of one cell's products
+    int seen = 0;
+    for (int c0 = 0; c0 < NRC; c0 += 64) {
+      const int cc = c0 + lane;
+      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
+      unsigned long long mask = __ballot(isc);
+      while (mask) {
+        const int bit = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        if ((seen++ & 3) != wave) continue;
+        const int c = c0 + bit;
+        const uint32_t* src =
+            (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL);
+        uint32_t* dst = (uint32_t*)(y_s + c * NL);
+#pragma unroll
+        for (int ch = 0; ch < (RDW + 63) / 64; ++ch)
+          if (ch * 64 + lane < RDW) load_dword_to_lds(src + ch * 64 + lane, dst + ch * 64);
+      }
+    }
+  }
   // ---- uncut cells: batched K_ref contraction on the matrix cores ----
   // Every non-cut cell of the region gets its row of y_s here: uncut cells their
   // product, cells outside the domain zeros (their B operand is masked to zero).
@@ -321,23 +345,6 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     }
   }  // FP32 / FP64 operands
 
-  // ---- cut cells: products computed once per step by the cut-cell kernel ----
-  if (MODE != kModeLanczos) {
-    int seen = 0;
-    for (int c0 = 0; c0 < NRC; c0 += 64) {
-      const int cc = c0 + lane;
-      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
-      unsigned long long mask = __ballot(isc);
-      while (mask) {
-        const int bit = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        if ((seen++ & 3) != wave) continue;
-        const int c = c0 + bit;
-        const T* yq = a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL;
-        for (int i = lane; i < NL; i += 64) y_s[c * NL + i] = yq[i];
-      }
-    }
-  }
   // ---- Lanczos operator: full FP64 setup matrices streamed per tile, one wave per cell ----
   if (MODE == kModeLanczos) {
     int seen = 0;
@@ -378,6 +385,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       }
     }
   }
+  if (MODE != kModeLanczos) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   // ---- owned nodes: fixed-order gather of element results + update ----
@@ -518,18 +526,16 @@ struct TileCfg {
   // every mode (the default configuration of a problem kind)
   static fcw_status run(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
                         double t, double dt, int start) {
-    if (mode != kModeLanczos) {
+    if (mode != kModeLanczos && !c.skip_cut) {
       fcw_status st = launch_cut_products(c, nrhs, uin);
       if (st) return st;
     }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
     if (mode == kModeStep) {
-      fcw_status st = timing_begin(c, kTimeMain);
-      if (st) return st;
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
       FCW_HIP(hipGetLastError());
-      return timing_end(c, kTimeMain);
+      return FCW_OK;
     }
     if (mode == kModeApply)
       tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF><<<grid, 256, 0, c.stream>>>(a);
@@ -545,14 +551,15 @@ struct TileCfg {
       set_error("tile configuration built for the step only");
       return FCW_E_UNSUPPORTED;
     }
-    fcw_status st = launch_cut_products(c, nrhs, uin);
-    if (st) return st;
+    if (!c.skip_cut) {
+      fcw_status st = launch_cut_products(c, nrhs, uin);
+      if (st) return st;
+    }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     dim3 grid(8 * a.chunk, nrhs, 1);
-    if ((st = timing_begin(c, kTimeMain))) return st;
     tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
     FCW_HIP(hipGetLastError());
-    return timing_end(c, kTimeMain);
+    return FCW_OK;
   }
 };
 
@@ -849,16 +856,10 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
     // one problem: its record goes by value, items are implicit (tile-major, rhs fastest)
     const int nitems = ntx * nty * nrhs;
     for (int j = 0; j < nsteps; ++j) {
-      if (c.n_cut_cand > 0) {
-        if ((st = timing_begin(c, kTimeCut)) ||
-            (st = launch_cut(c, c.stream, nullptr, 1, crec, ncutblk, j)) ||
-            (st = timing_end(c, kTimeCut)))
-          return st;
-      }
-      if ((st = timing_begin(c, kTimeMain)) ||
-          (st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs)) ||
-          (st = timing_end(c, kTimeMain)))
+      if (c.n_cut_cand > 0 && !c.skip_cut &&
+          (st = launch_cut(c, c.stream, nullptr, 1, crec, ncutblk, j)))
         return st;
+      if ((st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs))) return st;
     }
     return FCW_OK;
   }

@@ -36,6 +36,13 @@ __device__ static inline void buffer_dword_to_lds(__amdgpu_buffer_rsrc_t rsrc, i
                                            4, voffset, 0, 0, 0);
 }
 
+// One wave's 64 consecutive dwords, global -> LDS (lane l lands at lds_wave_base + 4 l).
+__device__ static inline void lds_dword2d(const void* gsrc, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)gsrc,
+                                   (__attribute__((address_space(3))) void*)lds_wave_base, 4, 0,
+                                   0);
+}
+
 // Per-problem arguments of a launch (device array, one entry per problem).
 template <typename T>
 struct Prob2d {
@@ -234,6 +241,27 @@ __global__ __launch_bounds__(256) void step2d_kernel(
 #pragma unroll
       for (int kk = 0; kk < NKS; ++kk)
         if (!(mb * 16 + lc < NL && 4 * kk + lk < NL)) areg[mb][kk] = T(0);
+    // cut cells: their products (cut-cell kernel) go global -> LDS by DMA, one wave per
+    // cell, all copies in flight while the matrix cores work below
+    {
+      int seen = 0;
+      for (int c0 = 0; c0 < NRC; c0 += 64) {
+        const int cq = c0 + lane;
+        unsigned long long mask = __ballot(cq < NRC && info_s[min(cq, NRC - 1)] >= 0);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          if ((seen++ & 3) != wave) continue;
+          const int c = c0 + bit;
+          const uint32_t* src =
+              (const uint32_t*)(pr.ycut + ((int64_t)rhs * pr.ncand + info_s[c]) * NL);
+          uint32_t* dst = (uint32_t*)(y_s + c * NLP);
+#pragma unroll
+          for (int ch = 0; ch < (NL * DPE + 63) / 64; ++ch)
+            if (ch * 64 + lane < NL * DPE) lds_dword2d(src + ch * 64 + lane, dst + ch * 64);
+        }
+      }
+    }
     // two batches of 16 cells per iteration: four independent accumulator chains
     for (int b0 = wave; b0 < NB; b0 += 8) {
       typename Mma<T>::acc acc[2][NMB];
@@ -257,7 +285,7 @@ __global__ __launch_bounds__(256) void step2d_kernel(
             acc[h][mb] = Mma<T>::mma(areg[mb][kk], bv[kk], acc[h][mb]);
       }
       // uncut cells their product, outside cells zeros (a select: their operands may be
-      // anything); cut cells are filled below
+      // anything); cut cells were copied in above
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         if (cc[h] < NRC && inf[h] < 0) {
@@ -271,21 +299,8 @@ __global__ __launch_bounds__(256) void step2d_kernel(
         }
       }
     }
-    // cut cells: their products from the cut-cell kernel, one wave per cell
-    int seen = 0;
-    for (int c0 = 0; c0 < NRC; c0 += 64) {
-      const int cq = c0 + lane;
-      unsigned long long mask = __ballot(cq < NRC && info_s[min(cq, NRC - 1)] >= 0);
-      while (mask) {
-        const int bit = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        if ((seen++ & 3) != wave) continue;
-        const int c = c0 + bit;
-        const T* yq = pr.ycut + ((int64_t)rhs * pr.ncand + info_s[c]) * NL;
-        if (lane < NL) y_s[c * NLP + lane] = yq[lane];
-      }
-    }
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
   // ---- update, one owned row per wave instruction ----
@@ -358,6 +373,357 @@ __global__ __launch_bounds__(256) void step2d_kernel(
   }
 }
 
+// Streaming variant: a block owns a column of TXS = 16 NBR - 1 cells (plus one ring cell
+// on the left) and YR cell rows, and marches up the column one cell row at a time, so
+// no cell row is computed twice and the loads of the next cell row are in flight while
+// the current one is computed:
+//  * node rows live in a ring buffer of 3P rows in LDS (row g in slot g mod 3P), filled
+//    by buffer_load ... lds one cell row ahead; the cut-cell products of the next row go
+//    global -> LDS the same way; d and the stored inverse masses of the next row's nodes
+//    are loaded into registers one iteration ahead;
+//  * per cell row, the NBR x NMB (16-cell batch, 16-row block) MFMA units are spread
+//    over the waves; products land in one of three row buffers (previous, current,
+//    next), so the node row shared with the previous cell row sums the previous row's
+//    products first (the fixed order of the tile kernels);
+//  * every store of the update is a buffer store with an out-of-range offset for lanes
+//    that own no node, so each wave issues a fixed number of stores per row and the
+//    end-of-row wait leaves exactly those in flight (vmcnt counts in issue order).
+template <typename T, int P, int NBR, int YR, bool SINGLE>
+__global__ __launch_bounds__(256) void stream2d_kernel(
+    const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, const Prob2d<T> one,
+    int nrhs1, int nitems, int chunk, int j) {
+  constexpr int NP1 = P + 1;
+  constexpr int NL = NP1 * NP1;
+  constexpr int NMB = (NL + 15) / 16;
+  constexpr int NKS = (NL + 3) / 4;
+  constexpr int NLP = NMB * 16 + 3;    // product stride per cell (bank-spread)
+  constexpr int NCR = 16 * NBR;        // cells per row, ring cell included
+  constexpr int TXS = NCR - 1;         // owned cells per row
+  constexpr int RW = NCR * P + 1;      // node row width staged (from the ring cell)
+  constexpr int OWN = TXS * P + 1;     // owned nodes per row at most (last column)
+  constexpr int NH = (OWN + 63) / 64;  // wave-halves per node row
+  constexpr int RING = 3 * P;          // ring buffer rows
+  constexpr int DPE = sizeof(T) / 4;
+  constexpr int RWD = RW * DPE;        // dwords per staged row
+  constexpr int NCH = (RWD + 63) / 64;
+  constexpr int NIR = YR + 1;          // cell rows with infos: cy0 - 1 .. cy0 + YR - 1
+  constexpr int NNR = YR * P + 1;      // node rows of the block: cy0 P .. (cy0 + YR) P
+  constexpr int FW = (OWN + 30) / 32 + 1;  // flag words spanned by a node row (any start)
+  constexpr int NU = P * NH;           // update units (node row, half) per cell row
+  constexpr int KU = (NU + 3) / 4;     // units per wave
+  constexpr int NMU = NBR * NMB;       // MFMA units per cell row
+  static_assert(NMB * NKS <= 32, "K_ref fragments kept in registers");
+
+  __shared__ T u_r[RING * RW];
+  __shared__ T y_b[3][NCR * NLP];
+  __shared__ int info_s[NIR * NCR];
+  __shared__ uint32_t fl_s[NNR * FW];
+  __shared__ double iwy_s[NNR];
+  __shared__ double ft_s;
+  __shared__ int src_s[3];
+
+  const int item = (int)(blockIdx.x % 8) * chunk + (int)(blockIdx.x / 8);
+  if (item >= nitems) return;
+  const int4 wi = SINGLE ? make_int4(0, item % nrhs1, item / nrhs1, 0) : items[item];
+  const Prob2d<T>& pr = SINGLE ? one : probs[wi.x];
+  if (j >= pr.nsteps) return;
+  const int rhs = wi.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lc = lane & 15, lk = lane >> 4;
+  const int cx0 = (wi.z % pr.ntile[0]) * TXS, cy0 = (wi.z / pr.ntile[0]) * YR;
+  const int n0 = pr.n[0], n1 = pr.n[1];
+  const int cy1 = min(cy0 + YR, n1);
+  const int npx = pr.np[0], npy = pr.np[1];
+  const int ox0 = cx0 * P, rnx0 = ox0 - P;
+  const int onx = (cx0 + TXS >= n0) ? npx - ox0 : TXS * P;
+  const int par = (pr.nsteps - 1 - j) & 1;
+  const int64_t roff = (int64_t)rhs * pr.ndof;
+  const T* uin = (par ? pr.ua : pr.ub) + roff;
+  T* dst_u = (par ? pr.ub : pr.ua) + roff;
+  T* dst_d = pr.d + roff;
+  const uint32_t nbytes = (uint32_t)((int64_t)npx * npy * sizeof(T));
+  const __amdgpu_buffer_rsrc_t urs_in =
+      __builtin_amdgcn_make_buffer_rsrc((void*)uin, (short)0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t drs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dst_d, (short)0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t urs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)dst_u, (short)0, (int)nbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t mrs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)pr.invm, (short)0, (int)nbytes, 0x00020000);
+  constexpr uint32_t kOff = 0xFFFFFFF0u;  // out-of-range buffer offset: no access
+  const double t = pr.t0 + j * pr.dt;
+
+  // ring slot of node row g (g may be negative below the grid)
+  auto slot = [](int g) { return ((g % RING) + RING) % RING; };
+  // node rows [g0, g0 + nr) of u -> their ring slots (rows outside the grid read 0)
+  auto stage_rows = [&](int g0, int nr) {
+    for (int r = wave; r < nr; r += 4) {
+      const int g = g0 + r;
+      const uint32_t rowbyte = (uint32_t)(((int64_t)g * npx + rnx0) * (int)sizeof(T));
+      T* dst = u_r + slot(g) * RW;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int dw = ch * 64 + lane;
+        const uint32_t vo = (g >= 0 && g < npy) ? rowbyte + (uint32_t)dw * 4u : kOff;
+        if (ch < NCH - 1 || dw < RWD)
+          buffer_dword_to_lds<T>(urs_in, (int)vo, (uint32_t*)dst + ch * 64);
+      }
+    }
+  };
+  // cut-cell products of cell row cy into a row buffer, one wave per cell
+  auto stage_cut = [&](int cy, T* yb) {
+    const int* inf = info_s + (cy - (cy0 - 1)) * NCR;
+    int seen = 0;
+#pragma unroll
+    for (int c0 = 0; c0 < NCR; c0 += 64) {
+      const int cq = c0 + lane;
+      unsigned long long mask = __ballot(cq < NCR && inf[min(cq, NCR - 1)] >= 0);
+      while (mask) {
+        const int bit = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        if ((seen++ & 3) != wave) continue;
+        const int c = c0 + bit;
+        const uint32_t* src =
+            (const uint32_t*)(pr.ycut + ((int64_t)rhs * pr.ncand + inf[c]) * NL);
+        uint32_t* dst = (uint32_t*)(yb + c * NLP);
+#pragma unroll
+        for (int ch = 0; ch < (NL * DPE + 63) / 64; ++ch)
+          if (ch * 64 + lane < NL * DPE) lds_dword2d(src + ch * 64 + lane, dst + ch * 64);
+      }
+    }
+  };
+
+  // ---- prologue: infos, flags, 1-D inverse weights, source, the ring cell row ----
+  for (int i = tid; i < NIR * NCR; i += 256) {
+    const int cy = cy0 - 1 + i / NCR, cx = cx0 - 1 + i % NCR;
+    const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1;
+    const int v = pr.info[in ? cx + n0 * cy : 0];
+    info_s[i] = in ? v : kInfoOut;
+  }
+  for (int i = tid; i < NNR * FW; i += 256) {
+    const int g = min(cy0 * P + i / FW, npy - 1);
+    fl_s[i] = pr.mflag[(size_t)g * pr.wpr + (ox0 >> 5) + i % FW];
+  }
+  for (int i = tid; i < NNR; i += 256) iwy_s[i] = pr.invw[npx + min(cy0 * P + i, npy - 1)];
+  if (tid == 0) {
+    int sx = -(1 << 20), sy = -(1 << 20);
+    double f = 0.0;
+    if (pr.src != nullptr) {
+      sx = pr.src[rhs].cell[0];
+      sy = pr.src[rhs].cell[1];
+      f = ricker(t, pr.src[rhs].f0);
+    }
+    src_s[0] = sx;
+    src_s[1] = sy;
+    src_s[2] = (sx * P + P >= ox0 && sx * P < ox0 + onx) ? 1 : 0;
+    ft_s = f;
+  }
+  double iwx[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) iwx[h] = pr.invw[min(ox0 + h * 64 + lane, npx - 1)];
+  T areg[NMB][NKS];
+#pragma unroll
+  for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+    for (int kk = 0; kk < NKS; ++kk) {
+      const int r = mb * 16 + lc, cc = 4 * kk + lk;
+      const T v = pr.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
+      areg[mb][kk] = (r < NL && cc < NL) ? v : T(0);
+    }
+  stage_rows((cy0 - 1) * P, P + 1);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  stage_cut(cy0 - 1, y_b[0]);
+
+  // per-lane constants of the MFMA B operand: local node (ix, iy) of this lane's k rows
+  int kx[NKS], ky[NKS];
+#pragma unroll
+  for (int kk = 0; kk < NKS; ++kk) {
+    const int jj = 4 * kk + lk;
+    kx[kk] = (jj < NL) ? jj % NP1 : 0;  // padded k rows read a real node (K_ref column 0)
+    ky[kk] = (jj < NL) ? jj / NP1 : 0;
+  }
+  // update units of this wave: (node row in the cell row, half)
+  T d_c[KU], d_n[KU], m_c[KU], m_n[KU];
+  bool st_c[KU], st_n[KU];
+#pragma unroll
+  for (int k = 0; k < KU; ++k) {
+    d_n[k] = m_n[k] = T(0);
+    st_n[k] = false;
+  }
+  // loads of the update operands of cell row cy (d; stored inverse masses where flagged)
+  auto load_upd = [&](int cy, T* dr, T* mr, bool* sr) {
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      const int u = wave + 4 * k;
+      const int ly = u / NH, h = u % NH;
+      const int g = cy * P + ly, xl = h * 64 + lane;
+      const bool own = u < NU && xl < onx && g >= cy0 * P && g <= cy1 * P && g < npy;
+      const uint32_t vo = own ? (uint32_t)(((int64_t)g * npx + ox0 + xl) * sizeof(T)) : kOff;
+      const int fr = min(max(g - cy0 * P, 0), NNR - 1);
+      const int gx = ox0 + xl;
+      const uint32_t word = fl_s[fr * FW + min((gx >> 5) - (ox0 >> 5), FW - 1)];
+      sr[k] = own && ((word >> (gx & 31)) & 1u);
+      if constexpr (sizeof(T) == 4) {
+        dr[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(drs, vo, 0, 0));
+        mr[k] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(mrs, sr[k] ? vo : kOff, 0, 0));
+      } else {
+        typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+        dr[k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(drs, vo, 0, 0));
+        mr[k] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(mrs, sr[k] ? vo : kOff, 0, 0));
+      }
+    }
+  };
+
+  const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
+  int bp = 2, bc = 0, bn = 1;  // previous / current / next product buffers (distinct)
+  for (int cy = cy0 - 1; cy < cy1; ++cy) {
+    const bool ring = cy < cy0;
+    // ---- A: loads of the next cell row (all in flight during this row's work) ----
+    if (cy + 1 < cy1) {
+      stage_cut(cy + 1, y_b[bn]);
+    }
+    stage_rows((cy + 1) * P + 1, P);
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+      d_c[k] = d_n[k];
+      m_c[k] = m_n[k];
+      st_c[k] = st_n[k];
+    }
+    load_upd(cy + 1, d_n, m_n, st_n);
+
+    // ---- B: products of cell row cy into y_b[bc] (cut cells were staged already) ----
+    {
+      const int* inf = info_s + (cy - (cy0 - 1)) * NCR;
+      const int s0 = slot(cy * P);
+      int offk[NKS];
+#pragma unroll
+      for (int kk = 0; kk < NKS; ++kk) offk[kk] = ((s0 + ky[kk]) % RING) * RW + kx[kk];
+      T* yb = y_b[bc];
+      for (int un = wave; un < NMU; un += 4) {
+        const int b = un / NMB, mb = un % NMB;
+        const int c = b * 16 + lc;
+        const int in = inf[c];
+        T bv[NKS];
+#pragma unroll
+        for (int kk = 0; kk < NKS; ++kk) bv[kk] = u_r[offk[kk] + c * P];
+        typename Mma<T>::acc acc = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NKS; ++kk) acc = Mma<T>::mma(areg[mb][kk], bv[kk], acc);
+        if (in < 0) {
+          const bool on = in == kInfoUncut;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yb[c * NLP + mb * 16 + Mma<T>::row(lk, r)] = on ? acc[r] : T(0);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- C: update of node rows cy P .. cy P + P - 1 ----
+    if (!ring) {
+      const T* yp = y_b[bp];
+      const T* yc = y_b[bc];
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int u = wave + 4 * k;
+        const int ly = min(u / NH, P - 1), h = u % NH;
+        const int g = cy * P + ly, xl = h * 64 + lane;
+        const bool own = u < NU && xl < onx;
+        const int qx = min(xl / P + 1, NCR - 1), lx = xl % P;
+        const T xam = (lx == 0) ? T(1) : T(0);
+        T acc = T(0);
+        if (ly == 0) {
+          acc = acc + xam * yp[(qx - 1) * NLP + P * NP1 + P];
+          acc = acc + yp[qx * NLP + P * NP1 + lx];
+        }
+        acc = acc + xam * yc[(qx - 1) * NLP + ly * NP1 + P];
+        acc = acc + yc[qx * NLP + ly * NP1 + lx];
+        T F = T(0);
+        if (src_s[2]) {
+          const int sx = ox0 + xl - src_s[0] * P, sy = g - src_s[1] * P;
+          if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
+        }
+        const T im = st_c[k] ? m_c[k]
+                             : analytic_invm<T>(pr.cm, iwx[min(h, NH - 1)],
+                                                iwy_s[g - cy0 * P], 1.0);
+        const T dn = d_c[k] + dt2h * im * (F - acc);
+        const T un_ = u_r[slot(g) * RW + min(xl + P, RW - 1)] + dn;
+        const uint32_t vo = own ? (uint32_t)(((int64_t)g * npx + ox0 + xl) * sizeof(T)) : kOff;
+        if constexpr (sizeof(T) == 4) {
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dn), drs, vo, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, un_), urs, vo, 0, 0);
+        } else {
+          typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, dn), drs, vo, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, un_), urs, vo, 0, 0);
+        }
+      }
+      // the loads of the next row done; this row's 2 KU stores may still be in flight
+      if constexpr (KU == 1) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+      else if constexpr (KU == 2) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+      else if constexpr (KU == 3) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();
+    const int t3 = bp;
+    bp = bc;
+    bc = bn;
+    bn = t3;
+  }
+
+  // ---- the top node row of the grid (only the cell row below contributes) ----
+  if (cy1 == n1 && wave < NH) {
+    const int g = n1 * P, h = wave, xl = h * 64 + lane;
+    const bool own = xl < onx;
+    const int qx = min(xl / P + 1, NCR - 1), lx = xl % P;
+    const T xam = (lx == 0) ? T(1) : T(0);
+    const T* yp = y_b[bp];
+    T acc = T(0);
+    acc = acc + xam * yp[(qx - 1) * NLP + P * NP1 + P];
+    acc = acc + yp[qx * NLP + P * NP1 + lx];
+    T F = T(0);
+    if (src_s[2]) {
+      const int sx = ox0 + xl - src_s[0] * P, sy = g - src_s[1] * P;
+      if (sx >= 0 && sx <= P && sy >= 0 && sy <= P) F = (T)(ft_s * pr.src[rhs].b[sx + NP1 * sy]);
+    }
+    // unit (row 0, half h) of cell row n1 was loaded by wave h as its first unit
+    const T im = st_n[0] ? m_n[0]
+                         : analytic_invm<T>(pr.cm, iwx[min(h, NH - 1)], iwy_s[g - cy0 * P], 1.0);
+    const T dn = d_n[0] + dt2h * im * (F - acc);
+    const T un_ = u_r[slot(g) * RW + min(xl + P, RW - 1)] + dn;
+    const uint32_t vo = own ? (uint32_t)(((int64_t)g * npx + ox0 + xl) * sizeof(T)) : kOff;
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dn), drs, vo, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, un_), urs, vo, 0, 0);
+    } else {
+      typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, dn), drs, vo, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, un_), urs, vo, 0, 0);
+    }
+  }
+}
+
+template <typename T, int P, int NBR, int YR>
+static fcw_status runs2d(hipStream_t stream, const void* probs, const int4* items, int nitems,
+                         int j, const void* one, int nrhs1) {
+  const int chunk = (nitems + 7) / 8;
+  if (one) {
+    Prob2d<T> rec;
+    std::memcpy(&rec, one, sizeof rec);
+    stream2d_kernel<T, P, NBR, YR, true><<<8 * chunk, 256, 0, stream>>>(nullptr, nullptr, rec,
+                                                                        nrhs1, nitems, chunk, j);
+  } else {
+    stream2d_kernel<T, P, NBR, YR, false><<<8 * chunk, 256, 0, stream>>>(
+        (const Prob2d<T>*)probs, items, Prob2d<T>{}, 1, nitems, chunk, j);
+  }
+  FCW_HIP(hipGetLastError());
+  return FCW_OK;
+}
+
 // probs/items: device work list; when `one` is given (a host record of a single
 // problem with nrhs1 right-hand sides) it is passed by value instead.
 template <typename T, int P, int TY>
@@ -379,18 +745,25 @@ static fcw_status run2d(hipStream_t stream, const void* probs, const int4* items
 
 // 2-D step kernels offered to the autotuner: (P, TY) -> launcher; TX = 64 / P.
 int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
-  struct E { int p, ty; Run2d f32, f64; };
-#define FCW_E(PP, TY) E{PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
+  struct E { int p, tx, ty; Run2d f32, f64; };
+  // tile kernels (tile = cells), then streaming kernels (tile = owned cells per row x cell
+  // rows per block)
+#define FCW_S(PP, NBR, YR) \
+  E{PP, 16 * NBR - 1, YR, &runs2d<float, PP, NBR, YR>, &runs2d<double, PP, NBR, YR>}
+#define FCW_E(PP, TY) E{PP, 64 / PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
       FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
-      FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8)};
+      FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8),
+      FCW_S(2, 2, 8), FCW_S(2, 2, 16), FCW_S(3, 2, 8), FCW_S(3, 2, 16), FCW_S(4, 2, 4),
+      FCW_S(4, 2, 8), FCW_S(4, 2, 16)};
 #undef FCW_E
+#undef FCW_S
   int n = 0;
   for (const E& e : table) {
     if (e.p != p) continue;
     if (n == i) {
       if (fn) *fn = fp64 ? e.f64 : e.f32;
-      if (tile) { tile[0] = 64 / e.p; tile[1] = e.ty; tile[2] = 1; }
+      if (tile) { tile[0] = e.tx; tile[1] = e.ty; tile[2] = 1; }
     }
     ++n;
   }

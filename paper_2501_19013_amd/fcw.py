@@ -25,7 +25,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
-           "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_timing", "fcw_timing_read", "fcw_run",
+           "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
            "fcw_export", "fcw_destroy", "fcw_last_error")
 
 
@@ -93,8 +93,7 @@ def load(path=LIB_PATH):
     lib.fcw_select_tile.argtypes = [vp, i32]
     lib.fcw_tile_name.argtypes = [vp, i32, C.c_char_p, i32]
     lib.fcw_set_stream.argtypes = [vp, vp]
-    lib.fcw_timing.argtypes = [vp, i32]
-    lib.fcw_timing_read.argtypes = [vp, i32, C.POINTER(f64), C.POINTER(C.c_int64)]
+    lib.fcw_kernel_times.argtypes = [vp, i32, i32, C.POINTER(f64), C.POINTER(f64)]
     lib.fcw_run.argtypes = [C.POINTER(RunItem), i32, i32]
     lib.fcw_destroy.argtypes = [vp]
     lib.fcw_destroy.restype = None
@@ -243,17 +242,11 @@ def set_stream(ctx, stream):
     _check(load().fcw_set_stream(ctx, stream))
 
 
-def timing(ctx, enable):
-    """fcw_timing: bracket every later step-kernel launch with HIP events (or stop)."""
-    _check(load().fcw_timing(ctx, int(bool(enable))))
-
-
-def timing_read(ctx, which):
-    """fcw_timing_read: (milliseconds, launches) of kernel kind 0 (main) or 1 (cut cells)."""
-    ms = C.c_double()
-    n = C.c_int64()
-    _check(load().fcw_timing_read(ctx, int(which), C.byref(ms), C.byref(n)))
-    return ms.value, n.value
+def kernel_times(ctx, nrhs=1, nsteps=100):
+    """fcw_kernel_times: (main kernel, cut-cell kernel) microseconds per launch."""
+    m, c = C.c_double(), C.c_double()
+    _check(load().fcw_kernel_times(ctx, int(nrhs), int(nsteps), C.byref(m), C.byref(c)))
+    return m.value, c.value
 
 
 def query(ctx):

@@ -298,6 +298,23 @@ def test_bf16_elastic_3d_parity():
         s.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_every_tile_configuration(c2_small, precision, tol):
+    # every kernel the autotuner may choose (2-D tile kernels, streaming kernels, generic
+    # tile shapes) against the oracle on the same 64^2 p=4 problem
+    from paper_2501_19013_amd import fcw
+    cfg, disc, dt = c2_small
+    ref = timestep.cdm(disc, dt, 60, sources=cfg["sources"])["u"]
+    s = _solver(cfg, precision)
+    confs = s.tile_configs()
+    assert len(confs) >= 5
+    for i, conf in enumerate(confs):
+        s.select_tile(i)
+        got = _run_gpu(s, cfg, dt, 60, [25, 35])
+        assert rel_l2(got[60], ref) <= tol, (i, conf)
+    s.close()
+
+
 def test_error_paths():
     from paper_2501_19013_amd import fcw
     cfg = workloads.config("c1")
