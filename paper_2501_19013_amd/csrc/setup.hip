@@ -510,7 +510,78 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
     for (int g = 0; g < NG; ++g) accG[e][g] = 0.0;
   }
   const double jac = 2.0 / a.g.h;
-  const int npts_total = nout * NPB;
+
+  // ---- boxes of constant alpha (all material or all void): the integrands separate,
+  // so each box adds products of 1-D integrals over its intervals (GL (p+1) per
+  // direction: exact, as the pointwise rule is on such a box) ----
+  __shared__ double t1[DIM][3][NP1 * NP1];  // per direction: m1, d1, g1 of the box
+  __shared__ int s_nleaf;
+  for (int b = 0; b < nout; ++b) {
+    int lvl, kind, ix[3];
+    box_unpack(outl[b], lvl, kind, ix);
+    if (kind == kKindLeaf) continue;
+    double lo[3], hi[3];
+    tree_box_bounds(DIM, clo, chi, lvl, ix, lo, hi);
+    if (tid < DIM * NP1 * NP1) {
+      const int k = tid / (NP1 * NP1), i = (tid / NP1) % NP1, jj = tid % NP1;
+      const double half = 0.5 * (hi[k] - lo[k]);
+      double m = 0.0, dd = 0.0, g = 0.0;
+      for (int qp = 0; qp < NP1; ++qp) {
+        const double x = lo[k] + (a.tab->gl_x[qp] + 1.0) * half;
+        const double xi = 2.0 * (x - clo[k]) / a.g.h - 1.0;
+        double L[NP1], dL[NP1];
+        lagrange_1d<NP1>(gll, xi, L, dL);
+        const double w = a.tab->gl_w[qp] * half;
+        m += w * L[i] * L[jj];
+        dd += w * (jac * dL[i]) * (jac * dL[jj]);
+        g += w * (jac * dL[i]) * L[jj];
+      }
+      t1[k][0][i * NP1 + jj] = m;
+      t1[k][1][i * NP1 + jj] = dd;
+      t1[k][2][i * NP1 + jj] = g;
+    }
+    __syncthreads();
+    const double al = (kind == kKindAlpha) ? a.alpha : 1.0;
+    for (int e = 0; e < EPT; ++e) {
+      if (tid + e * kTreeThreads >= NENT) break;
+      int ia[3] = {0, 0, 0}, ja[3] = {0, 0, 0};
+      int ri = ei[e], rj = ej[e];
+      for (int k = 0; k < DIM; ++k) {
+        ia[k] = ri % NP1; ri /= NP1;
+        ja[k] = rj % NP1; rj /= NP1;
+      }
+      double mm = al;
+      for (int k = 0; k < DIM; ++k) mm *= t1[k][0][ia[k] * NP1 + ja[k]];
+      accM[e] += mm;
+      for (int bb = 0; bb < DIM; ++bb)
+        for (int c2 = 0; c2 < DIM; ++c2) {
+          if (NCOMP == 1 && bb != c2) continue;
+          // d/dx_bb of N_i times d/dx_c2 of N_j, direction by direction
+          double v = al;
+          for (int k = 0; k < DIM; ++k) {
+            if (k == bb && k == c2) v *= t1[k][1][ia[k] * NP1 + ja[k]];
+            else if (k == bb) v *= t1[k][2][ia[k] * NP1 + ja[k]];
+            else if (k == c2) v *= t1[k][2][ja[k] * NP1 + ia[k]];
+            else v *= t1[k][0][ia[k] * NP1 + ja[k]];
+          }
+          accG[e][NCOMP == 1 ? 0 : bb * DIM + c2] += v;
+        }
+    }
+    __syncthreads();
+  }
+  // the leaves (cut at the finest level) keep the pointwise rule with alpha per point
+  if (tid == 0) {
+    int nl = 0;
+    for (int b = 0; b < nout; ++b) {
+      int lvl, kind, ix[3];
+      box_unpack(outl[b], lvl, kind, ix);
+      if (kind == kKindLeaf) lst[0][nl++] = outl[b];
+    }
+    s_nleaf = nl;
+  }
+  __syncthreads();
+  const uint32_t* leafl = lst[0];
+  const int npts_total = s_nleaf * NPB;
   for (int pb = 0; pb < npts_total; pb += kTreeBatch) {
     if (tid < kTreeBatch) {
       int ip = pb + tid;
@@ -518,7 +589,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
       if (ip < npts_total) {
         int bi = ip / NPB, qi = ip % NPB;
         int lvl, kind, ix[3];
-        box_unpack(outl[bi], lvl, kind, ix);
+        box_unpack(leafl[bi], lvl, kind, ix);
         double lo[3], hi[3];
         tree_box_bounds(DIM, clo, chi, lvl, ix, lo, hi);
         double x[3], w = 1.0;

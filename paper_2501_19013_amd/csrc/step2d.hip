@@ -388,8 +388,8 @@ __global__ __launch_bounds__(256) void step2d_kernel(
 //  * every store of the update is a buffer store with an out-of-range offset for lanes
 //    that own no node, so each wave issues a fixed number of stores per row and the
 //    end-of-row wait leaves exactly those in flight (vmcnt counts in issue order).
-template <typename T, int P, int NBR, int YR, bool SINGLE>
-__global__ __launch_bounds__(256) void stream2d_kernel(
+template <typename T, int P, int NBR, int YR, int NW, bool SINGLE>
+__global__ __launch_bounds__(64 * NW) void stream2d_kernel(
     const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, const Prob2d<T> one,
     int nrhs1, int nitems, int chunk, int j) {
   constexpr int NP1 = P + 1;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   constexpr int NNR = YR * P + 1;      // node rows of the block: cy0 P .. (cy0 + YR) P
   constexpr int FW = (OWN + 30) / 32 + 1;  // flag words spanned by a node row (any start)
   constexpr int NU = P * NH;           // update units (node row, half) per cell row
-  constexpr int KU = (NU + 3) / 4;     // units per wave
+  constexpr int KU = (NU + NW - 1) / NW;  // units per wave
   constexpr int NMU = NBR * NMB;       // MFMA units per cell row
   static_assert(NMB * NKS <= 32, "K_ref fragments kept in registers");
 
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   auto slot = [](int g) { return ((g % RING) + RING) % RING; };
   // node rows [g0, g0 + nr) of u -> their ring slots (rows outside the grid read 0)
   auto stage_rows = [&](int g0, int nr) {
-    for (int r = wave; r < nr; r += 4) {
+    for (int r = wave; r < nr; r += NW) {
       const int g = g0 + r;
       const uint32_t rowbyte = (uint32_t)(((int64_t)g * npx + rnx0) * (int)sizeof(T));
       T* dst = u_r + slot(g) * RW;
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
       while (mask) {
         const int bit = __ffsll((long long)mask) - 1;
         mask &= mask - 1;
-        if ((seen++ & 3) != wave) continue;
+        if ((seen++ % NW) != wave) continue;
         const int c = c0 + bit;
         const uint32_t* src =
             (const uint32_t*)(pr.ycut + ((int64_t)rhs * pr.ncand + inf[c]) * NL);
@@ -494,17 +494,17 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   };
 
   // ---- prologue: infos, flags, 1-D inverse weights, source, the ring cell row ----
-  for (int i = tid; i < NIR * NCR; i += 256) {
+  for (int i = tid; i < NIR * NCR; i += 64 * NW) {
     const int cy = cy0 - 1 + i / NCR, cx = cx0 - 1 + i % NCR;
     const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1;
     const int v = pr.info[in ? cx + n0 * cy : 0];
     info_s[i] = in ? v : kInfoOut;
   }
-  for (int i = tid; i < NNR * FW; i += 256) {
+  for (int i = tid; i < NNR * FW; i += 64 * NW) {
     const int g = min(cy0 * P + i / FW, npy - 1);
     fl_s[i] = pr.mflag[(size_t)g * pr.wpr + (ox0 >> 5) + i % FW];
   }
-  for (int i = tid; i < NNR; i += 256) iwy_s[i] = pr.invw[npx + min(cy0 * P + i, npy - 1)];
+  for (int i = tid; i < NNR; i += 64 * NW) iwy_s[i] = pr.invw[npx + min(cy0 * P + i, npy - 1)];
   if (tid == 0) {
     int sx = -(1 << 20), sy = -(1 << 20);
     double f = 0.0;
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   auto load_upd = [&](int cy, T* dr, T* mr, bool* sr) {
 #pragma unroll
     for (int k = 0; k < KU; ++k) {
-      const int u = wave + 4 * k;
+      const int u = wave + NW * k;
       const int ly = u / NH, h = u % NH;
       const int g = cy * P + ly, xl = h * 64 + lane;
       const bool own = u < NU && xl < onx && g >= cy0 * P && g <= cy1 * P && g < npy;
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
 #pragma unroll
       for (int kk = 0; kk < NKS; ++kk) offk[kk] = ((s0 + ky[kk]) % RING) * RW + kx[kk];
       T* yb = y_b[bc];
-      for (int un = wave; un < NMU; un += 4) {
+      for (int un = wave; un < NMU; un += NW) {
         const int b = un / NMB, mb = un % NMB;
         const int c = b * 16 + lc;
         const int in = inf[c];
@@ -627,7 +627,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
       const T* yc = y_b[bc];
 #pragma unroll
       for (int k = 0; k < KU; ++k) {
-        const int u = wave + 4 * k;
+        const int u = wave + NW * k;
         const int ly = min(u / NH, P - 1), h = u % NH;
         const int g = cy * P + ly, xl = h * 64 + lane;
         const bool own = u < NU && xl < onx;
@@ -664,6 +664,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
       if constexpr (KU == 1) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
       else if constexpr (KU == 2) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
       else if constexpr (KU == 3) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+      else if constexpr (KU == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
       else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     } else {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -676,6 +677,7 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   }
 
   // ---- the top node row of the grid (only the cell row below contributes) ----
+  static_assert(NH <= NW, "the top row takes one wave per half");
   if (cy1 == n1 && wave < NH) {
     const int g = n1 * P, h = wave, xl = h * 64 + lane;
     const bool own = xl < onx;
@@ -707,17 +709,17 @@ __global__ __launch_bounds__(256) void stream2d_kernel(
   }
 }
 
-template <typename T, int P, int NBR, int YR>
+template <typename T, int P, int NBR, int YR, int NW>
 static fcw_status runs2d(hipStream_t stream, const void* probs, const int4* items, int nitems,
                          int j, const void* one, int nrhs1) {
   const int chunk = (nitems + 7) / 8;
   if (one) {
     Prob2d<T> rec;
     std::memcpy(&rec, one, sizeof rec);
-    stream2d_kernel<T, P, NBR, YR, true><<<8 * chunk, 256, 0, stream>>>(nullptr, nullptr, rec,
+    stream2d_kernel<T, P, NBR, YR, NW, true><<<8 * chunk, 64 * NW, 0, stream>>>(nullptr, nullptr, rec,
                                                                         nrhs1, nitems, chunk, j);
   } else {
-    stream2d_kernel<T, P, NBR, YR, false><<<8 * chunk, 256, 0, stream>>>(
+    stream2d_kernel<T, P, NBR, YR, NW, false><<<8 * chunk, 64 * NW, 0, stream>>>(
         (const Prob2d<T>*)probs, items, Prob2d<T>{}, 1, nitems, chunk, j);
   }
   FCW_HIP(hipGetLastError());
@@ -748,14 +750,14 @@ int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
   struct E { int p, tx, ty; Run2d f32, f64; };
   // tile kernels (tile = cells), then streaming kernels (tile = owned cells per row x cell
   // rows per block)
-#define FCW_S(PP, NBR, YR) \
-  E{PP, 16 * NBR - 1, YR, &runs2d<float, PP, NBR, YR>, &runs2d<double, PP, NBR, YR>}
+#define FCW_S(PP, NBR, YR, NW) \
+  E{PP, 16 * NBR - 1, YR, &runs2d<float, PP, NBR, YR, NW>, &runs2d<double, PP, NBR, YR, NW>}
 #define FCW_E(PP, TY) E{PP, 64 / PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
       FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
       FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8),
-      FCW_S(2, 2, 8), FCW_S(2, 2, 16), FCW_S(3, 2, 8), FCW_S(3, 2, 16), FCW_S(4, 2, 4),
-      FCW_S(4, 2, 8), FCW_S(4, 2, 16)};
+      FCW_S(2, 2, 8, 4), FCW_S(2, 2, 16, 4), FCW_S(3, 2, 8, 4), FCW_S(3, 2, 16, 4),
+      FCW_S(4, 2, 4, 4), FCW_S(4, 2, 8, 4), FCW_S(4, 2, 16, 4)};
 #undef FCW_E
 #undef FCW_S
   int n = 0;
