@@ -23,7 +23,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "step_common.h"
@@ -83,30 +85,12 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   __shared__ double ft_s;
   __shared__ int src_on;
 
-  const int tile = (int)(blockIdx.x % 8) * a.chunk + (int)(blockIdx.x / 8);
-  if (tile >= a.ntiles) return;
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int lc = lane & 15, lk = lane >> 4;
-  const int tx = tile % a.ntile[0];
-  const int ty = (DIM >= 2) ? (tile / a.ntile[0]) % a.ntile[1] : 0;
-  const int tz = (DIM == 3) ? tile / (a.ntile[0] * a.ntile[1]) : 0;
-  const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
-  const int rcx0 = cx0 - 1;
-  const int rcy0 = (DIM >= 2) ? cy0 - 1 : 0;
-  const int rcz0 = (DIM == 3) ? cz0 - 1 : 0;
-  const int rnx0 = rcx0 * P, rny0 = rcy0 * P, rnz0 = rcz0 * P;
-  const T* uin = a.u_in + (int64_t)rhs * a.ndof;
-  const int ox0 = cx0 * P;
-  const int ox1 = (cx0 + TX >= a.n[0]) ? a.np[0] : (cx0 + TX) * P;
-  const int oy0 = (DIM >= 2) ? cy0 * P : 0;
-  const int oy1 = (DIM >= 2) ? ((cy0 + TY >= a.n[1]) ? a.np[1] : (cy0 + TY) * P) : 1;
-  const int oz0 = (DIM == 3) ? cz0 * P : 0;
-  const int oz1 = (DIM == 3) ? ((cz0 + TZ >= a.n[2]) ? a.np[2] : (cz0 + TZ) * P) : 1;
-  const int onx = ox1 - ox0, ony = oy1 - oy0, onz = oz1 - oz0;
 
-  // ---- issue every global load of the tile at once (all stay in flight) ----
+  // ---- once per block: K_ref fragments (registers or LDS) and the local offsets ----
   T areg[AREG ? NMB : 1][AREG ? NKS : 1];
   if (AREG) {
 #pragma unroll
@@ -118,67 +102,6 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         const T v = kp[min(r, NL - 1) * NL + min(cc, NL - 1)];
         areg[AREG ? mb : 0][AREG ? kk : 0] = (r < NL && cc < NL) ? v : T(0);
       }
-  }
-  int inf_r[NCI];
-#pragma unroll
-  for (int it = 0; it < NCI; ++it) {
-    const int c = tid + it * 256;
-    const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
-    const int gx = rcx0 + lx, gy = rcy0 + ly, gz = rcz0 + lz;
-    const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
-                    gz < a.n[2];
-    const int64_t cell = in ? gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz) : 0;
-    const int v = a.info[cell];
-    inf_r[it] = in ? v : kInfoOut;
-  }
-  // node values of the region; entries outside the grid belong only to cells outside
-  // the grid (never read), so their address is clamped to node 0 of the component
-  T u_r[DIRECT ? 1 : NUL];
-#pragma unroll
-  for (int it = 0; it < NUL; ++it) {
-    const int i = tid + it * 256;
-    const int comp = min(i / NRN, NCOMP - 1), j = i % NRN;
-    const int lx = j % RNX, ly = (j / RNX) % RNY, lz = j / (RNX * RNY);
-    const int gx = rnx0 + lx, gy = rny0 + ly, gz = rnz0 + lz;
-    const bool in = i < NUV && gx >= 0 && gx < a.np[0] && gy >= 0 && gy < a.np[1] && gz >= 0 &&
-                    gz < a.np[2];
-    const int64_t node = in ? gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz) : 0;
-    const T* src = uin + (int64_t)comp * a.nnodes + node;
-    if (DIRECT) {
-      load_dword_to_lds(src, &u_s[it * 256 + wave * 64]);
-    } else {
-      T v = *src;
-      if (MODE == kModeLanczos) v = v * (T)sqrt(a.invm64[node]);
-      u_r[DIRECT ? 0 : it] = in ? v : T(0);
-    }
-  }
-  T d_r[MODE == kModeStep ? NO : 1][NCOMP];
-  T im_r[MODE == kModeStep ? NO : 1];
-  if (MODE == kModeStep) {
-#pragma unroll
-    for (int it = 0; it < NO; ++it) {
-      const int i = tid + it * 256;
-      const int ii = (MODE == kModeStep) ? it : 0;
-      const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
-      const bool own = i < OX * OY * OZ && lx < onx && ly < ony && lz < onz;
-      const int64_t node =
-          own ? (ox0 + lx) + (int64_t)a.np[0] * ((oy0 + ly) + (int64_t)a.np[1] * (oz0 + lz)) : 0;
-      im_r[ii] = a.invm[node];
-#pragma unroll
-      for (int comp = 0; comp < NCOMP; ++comp)
-        d_r[ii][comp] = a.d[(int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node];
-    }
-  }
-
-  // ---- stage cell info, node values, K_ref, local offsets in LDS ----
-#pragma unroll
-  for (int it = 0; it < NCI; ++it) {
-    const int c = tid + it * 256;
-    if (c < NRC) info_s[c] = inf_r[it];
-  }
-  if (!DIRECT) {
-#pragma unroll
-    for (int it = 0; it < NUL; ++it) u_s[tid + it * 256] = u_r[DIRECT ? 0 : it];
   }
   if (ALDS) {
     for (int i = tid; i < NMB * 16 * KW; i += 256) {
@@ -195,27 +118,6 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     }
     off_s[j] = off;
   }
-  if (tid == 0) {
-    src_on = 0;
-    ft_s = 0.0;
-    if (MODE == kModeStep && a.src != nullptr) {
-      const SourceDev& s = a.src[rhs];
-      // owned node box of this tile vs node box of the source cell
-      bool hit = true;
-      const int c0[3] = {cx0, cy0, cz0};
-      const int tt[3] = {TX, TY, TZ};
-      for (int k = 0; k < DIM; ++k) {
-        const int o0 = c0[k] * P;
-        const int o1 = (c0[k] + tt[k] >= a.n[k]) ? a.np[k] : (c0[k] + tt[k]) * P;
-        const int s0 = s.cell[k] * P, s1 = s.cell[k] * P + P;
-        if (s1 < o0 || s0 >= o1) hit = false;
-      }
-      if (hit) {
-        src_on = 1;
-        ft_s = ricker(a.t, s.f0);
-      }
-    }
-  }
   if constexpr (BF) {
     // contiguous copy of the lane-ordered fragments (NFRAG x 16 bytes), 64 dwords per
     // wave instruction
@@ -223,260 +125,389 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     for (int w = wave; w < NFRAG * 4 / 64; w += 4)
       load_dword_to_lds(src + w * 64 + lane, (uint32_t*)a_sb + w * 64);
   }
-  if (DIRECT || BF) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // ---- cut cells: their products (cut-cell kernel) go global -> LDS by DMA, one wave
-  // per cell, all copies in flight while the matrix cores work below ----
-  if (MODE != kModeLanczos) {
-    constexpr int DPE = (int)(sizeof(T) / 4);
-    constexpr int RDW = NL * DPE;  // dwords of one cell's products
-    int seen = 0;
-    for (int c0 = 0; c0 < NRC; c0 += 64) {
-      const int cc = c0 + lane;
-      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
-      unsigned long long mask = __ballot(isc);
-      while (mask) {
-        const int bit = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        if ((seen++ & 3) != wave) continue;
-        const int c = c0 + bit;
-        const uint32_t* src =
-            (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL);
-        uint32_t* dst = (uint32_t*)(y_s + c * NL);
-#pragma unroll
-        for (int ch = 0; ch < (RDW + 63) / 64; ++ch)
-          if (ch * 64 + lane < RDW) load_dword_to_lds(src + ch * 64 + lane, dst + ch * 64);
-      }
-    }
-  }
-  // ---- uncut cells: batched K_ref contraction on the matrix cores ----
-  // Every non-cut cell of the region gets its row of y_s here: uncut cells their
-  // product, cells outside the domain zeros (their B operand is masked to zero).
-  if constexpr (BF) {
-    // BF16 form: operands split into bf16 hi + lo parts (nearest even), the four products
-    // K_lo u_lo + K_lo u_hi + K_hi u_lo + K_hi u_hi accumulated in FP32, smallest first
-    for (int b = wave; b < NB; b += 4) {
-      const int c = b * 16 + lc;
-      const int cs = min(c, NRC - 1);
-      const int inf = info_s[cs];
-      const bool valid = (c < NRC) && (inf == kInfoUncut);
-      const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
-      const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
-      f32x4 acc[NMB];
-#pragma unroll
-      for (int mb = 0; mb < NMB; ++mb) acc[mb] = f32x4{0, 0, 0, 0};
-#pragma unroll
-      for (int kb = 0; kb < NKB; ++kb) {
-        bf16x8 bhi, blo;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int off = off_s[kb * 32 + 8 * lk + e];
-          const float v = (valid && off >= 0) ? (float)u_s[base + max(off, 0)] : 0.0f;
-          const __bf16 h = (__bf16)v;
-          bhi[e] = h;
-          blo[e] = (__bf16)(v - (float)h);  // exact in FP32
-        }
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-          const bf16x8 ahi = a_sb[((mb * NKB + kb) * 2 + 0) * 64 + lane];
-          const bf16x8 alo = a_sb[((mb * NKB + kb) * 2 + 1) * 64 + lane];
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo, acc[mb], 0, 0, 0);
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[mb], 0, 0, 0);
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[mb], 0, 0, 0);
-          acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[mb], 0, 0, 0);
-        }
-      }
-      if (c < NRC && inf < 0) {
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = mb * 16 + 4 * lk + r;
-            if (i < NL) y_s[c * NL + i] = (T)acc[mb][r];
-          }
-      }
-    }
-  } else {
-    int offk[NKS];
-#pragma unroll
-    for (int kk = 0; kk < NKS; ++kk) offk[kk] = off_s[4 * kk + lk];
-    for (int b = wave; b < NB; b += 4) {
-      const int c = b * 16 + lc;
-      const int cs = min(c, NRC - 1);
-      const int inf = info_s[cs];
-      const bool valid = (c < NRC) && (inf == kInfoUncut);
-      const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
-      const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
-      T bv[NKS];
-#pragma unroll
-      for (int kk = 0; kk < NKS; ++kk) {
-        const T v = u_s[base + max(offk[kk], 0)];
-        bv[kk] = (valid && offk[kk] >= 0) ? v : T(0);
-      }
-      typename Mma<T>::acc acc[NMB];
-#pragma unroll
-      for (int mb = 0; mb < NMB; ++mb) acc[mb] = typename Mma<T>::acc{0, 0, 0, 0};
-#pragma unroll
-      for (int kk = 0; kk < NKS; ++kk) {
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-          T av;
-          if (AREG) {
-            av = areg[AREG ? mb : 0][AREG ? kk : 0];
-          } else if (ALDS) {
-            av = a_s[ALDS ? (mb * 16 + lc) * KW + 4 * kk + lk : 0];
-          } else {
-            const int r = mb * 16 + lc, cc = 4 * kk + lk;
-            av = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
-          }
-          acc[mb] = Mma<T>::mma(av, bv[kk], acc[mb]);
-        }
-      }
-      if (c < NRC && inf < 0) {
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = mb * 16 + Mma<T>::row(lk, r);
-            if (i < NL) y_s[c * NL + i] = acc[mb][r];
-          }
-      }
-    }
-  }  // FP32 / FP64 operands
+  // ---- the block's tiles: a stretch of the tiles of its XCD (blocks b, b + 8, ... run
+  // on one XCD), so neighbouring tiles share halo rows in that XCD's L2 ----
+  const int nbx = (int)(gridDim.x / 8);
+  for (int tk = (int)(blockIdx.x / 8); tk < a.chunk; tk += nbx) {
+    const int tile = (int)(blockIdx.x % 8) * a.chunk + tk;
+    if (tile >= a.ntiles) break;
+    const int tx = tile % a.ntile[0];
+    const int ty = (DIM >= 2) ? (tile / a.ntile[0]) % a.ntile[1] : 0;
+    const int tz = (DIM == 3) ? tile / (a.ntile[0] * a.ntile[1]) : 0;
+    const int cx0 = tx * TX, cy0 = ty * TY, cz0 = tz * TZ;
+    const int rcx0 = cx0 - 1;
+    const int rcy0 = (DIM >= 2) ? cy0 - 1 : 0;
+    const int rcz0 = (DIM == 3) ? cz0 - 1 : 0;
+    const int rnx0 = rcx0 * P, rny0 = rcy0 * P, rnz0 = rcz0 * P;
+    const T* uin = a.u_in + (int64_t)rhs * a.ndof;
+    const int ox0 = cx0 * P;
+    const int ox1 = (cx0 + TX >= a.n[0]) ? a.np[0] : (cx0 + TX) * P;
+    const int oy0 = (DIM >= 2) ? cy0 * P : 0;
+    const int oy1 = (DIM >= 2) ? ((cy0 + TY >= a.n[1]) ? a.np[1] : (cy0 + TY) * P) : 1;
+    const int oz0 = (DIM == 3) ? cz0 * P : 0;
+    const int oz1 = (DIM == 3) ? ((cz0 + TZ >= a.n[2]) ? a.np[2] : (cz0 + TZ) * P) : 1;
+    const int onx = ox1 - ox0, ony = oy1 - oy0, onz = oz1 - oz0;
 
-  // ---- Lanczos operator: full FP64 setup matrices streamed per tile, one wave per cell ----
-  if (MODE == kModeLanczos) {
-    int seen = 0;
-    for (int c0 = 0; c0 < NRC; c0 += 64) {
-      const int cc = c0 + lane;
-      const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
-      unsigned long long mask = __ballot(isc);
-      while (mask) {
-        const int bit = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        if ((seen++ & 3) != wave) continue;
-        const int c = c0 + bit;
-        const int q = info_s[c];
-        const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
-        const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
-        const T* K = a.kcut + (int64_t)q * NL * NL;
-        constexpr int NR = (NL + 63) / 64;
-        // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
-        // small lumped masses of cut-cell nodes amplify any error in their sum
-        double y[NR];
-#pragma unroll
-        for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
-        // straight-line over the columns: every load of the cell is issued before use
-#pragma unroll
-        for (int j = 0; j < NL; ++j) {
-          const T uj = u_s[base + off_s[j]];
-#pragma unroll
-          for (int rr = 0; rr < NR; ++rr) {
-            const int i = min(lane + 64 * rr, NL - 1);
-            y[rr] += (double)K[i * NL + j] * (double)uj;
-          }
-        }
-#pragma unroll
-        for (int rr = 0; rr < NR; ++rr) {
-          const int i = lane + 64 * rr;
-          if (i < NL) y_s[c * NL + i] = (T)y[rr];
-        }
+    // ---- issue every global load of the tile at once (all stay in flight) ----
+    int inf_r[NCI];
+  #pragma unroll
+    for (int it = 0; it < NCI; ++it) {
+      const int c = tid + it * 256;
+      const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
+      const int gx = rcx0 + lx, gy = rcy0 + ly, gz = rcz0 + lz;
+      const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
+                      gz < a.n[2];
+      const int64_t cell = in ? gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz) : 0;
+      const int v = a.info[cell];
+      inf_r[it] = in ? v : kInfoOut;
+    }
+    // node values of the region; entries outside the grid belong only to cells outside
+    // the grid (never read), so their address is clamped to node 0 of the component
+    T u_r[DIRECT ? 1 : NUL];
+  #pragma unroll
+    for (int it = 0; it < NUL; ++it) {
+      const int i = tid + it * 256;
+      const int comp = min(i / NRN, NCOMP - 1), j = i % NRN;
+      const int lx = j % RNX, ly = (j / RNX) % RNY, lz = j / (RNX * RNY);
+      const int gx = rnx0 + lx, gy = rny0 + ly, gz = rnz0 + lz;
+      const bool in = i < NUV && gx >= 0 && gx < a.np[0] && gy >= 0 && gy < a.np[1] && gz >= 0 &&
+                      gz < a.np[2];
+      const int64_t node = in ? gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz) : 0;
+      const T* src = uin + (int64_t)comp * a.nnodes + node;
+      if (DIRECT) {
+        load_dword_to_lds(src, &u_s[it * 256 + wave * 64]);
+      } else {
+        T v = *src;
+        if (MODE == kModeLanczos) v = v * (T)sqrt(a.invm64[node]);
+        u_r[DIRECT ? 0 : it] = in ? v : T(0);
       }
     }
-  }
-  if (MODE != kModeLanczos) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-
-  // ---- owned nodes: fixed-order gather of element results + update ----
-  // The cells around node g along one axis are a = g/P - 1 (when g is a positive
-  // multiple of P) and b = g/P (when g < n P); cells outside the domain hold zeros.
-#pragma unroll
-  for (int it = 0; it < NO; ++it) {
-    const int i = tid + it * 256;
-    const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
-    if (i >= OX * OY * OZ || lx >= onx || ly >= ony || lz >= onz) continue;
-    const int g3[3] = {ox0 + lx, oy0 + ly, oz0 + lz};
-    const int64_t node = g3[0] + (int64_t)a.np[0] * (g3[1] + (int64_t)a.np[1] * g3[2]);
-    int ca[3], cb[3], la[3], lb[3];
-    bool ua[3], ub[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int rc0 = (k == 0) ? rcx0 : (k == 1 ? rcy0 : rcz0);
-      if (k >= DIM) {
-        ca[k] = cb[k] = 0; la[k] = lb[k] = 0; ua[k] = false; ub[k] = true;
-        continue;
-      }
-      const int g = g3[k];
-      const int q = g / P, rem = g - q * P;
-      ua[k] = (rem == 0) && (g > 0);
-      ub[k] = g < a.n[k] * P;
-      ca[k] = max(q - 1 - rc0, 0);                       // region-local cell index
-      cb[k] = min(q - rc0, (k == 0 ? RCX : (k == 1 ? RCY : RCZ)) - 1);
-      la[k] = P;                                          // local node in cell a
-      lb[k] = rem;                                        // local node in cell b
-    }
-    T r[NCOMP];
-#pragma unroll
-    for (int comp = 0; comp < NCOMP; ++comp) r[comp] = T(0);
-#pragma unroll
-    for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
-#pragma unroll
-      for (int sy = 0; sy < (DIM >= 2 ? 2 : 1); ++sy)
-#pragma unroll
-        for (int sx = 0; sx < 2; ++sx) {
-          const bool use = (sx ? ub[0] : ua[0]) && (DIM < 2 || (sy ? ub[1] : ua[1])) &&
-                           (DIM < 3 || (sz ? ub[2] : ua[2]));
-          const int lcell = (sx ? cb[0] : ca[0]) +
-                            RCX * ((sy ? cb[1] : ca[1]) + RCY * (sz ? cb[2] : ca[2]));
-          const int loc = (sx ? lb[0] : la[0]) +
-                          NP1 * ((sy ? lb[1] : la[1]) + NP1 * (sz ? lb[2] : la[2]));
-#pragma unroll
-          for (int comp = 0; comp < NCOMP; ++comp) {
-            const T v = y_s[lcell * NL + comp * NS + loc];
-            r[comp] += use ? v : T(0);
-          }
-        }
+    T d_r[MODE == kModeStep ? NO : 1][NCOMP];
+    T im_r[MODE == kModeStep ? NO : 1];
     if (MODE == kModeStep) {
-      const int ii = (MODE == kModeStep) ? it : 0;
-      const int rl = (g3[0] - rnx0) + RNX * ((g3[1] - rny0) + RNY * (g3[2] - rnz0));
-      const T im = im_r[ii];
-      int sloc = -1;
-      if (src_on) {
-        const SourceDev& s = a.src[rhs];
-        const int sx = g3[0] - s.cell[0] * P, sy = g3[1] - s.cell[1] * P,
-                  sz = g3[2] - s.cell[2] * P;
-        if (sx >= 0 && sx <= P && (DIM < 2 || (sy >= 0 && sy <= P)) &&
-            (DIM < 3 || (sz >= 0 && sz <= P)))
-          sloc = sx + NP1 * ((DIM >= 2 ? sy : 0) + NP1 * (DIM == 3 ? sz : 0));
+  #pragma unroll
+      for (int it = 0; it < NO; ++it) {
+        const int i = tid + it * 256;
+        const int ii = (MODE == kModeStep) ? it : 0;
+        const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
+        const bool own = i < OX * OY * OZ && lx < onx && ly < ony && lz < onz;
+        const int64_t node =
+            own ? (ox0 + lx) + (int64_t)a.np[0] * ((oy0 + ly) + (int64_t)a.np[1] * (oz0 + lz)) : 0;
+        im_r[ii] = a.invm[node];
+  #pragma unroll
+        for (int comp = 0; comp < NCOMP; ++comp)
+          d_r[ii][comp] = a.d[(int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node];
       }
-#pragma unroll
-      for (int comp = 0; comp < NCOMP; ++comp) {
-        const int64_t dof = (int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node;
-        T F = T(0);
-        if (sloc >= 0) F = (T)(ft_s * a.src[rhs].b[comp * NS + sloc]);
-        T acc = a.dt2 * im * (F - r[comp]);
-        if (a.start) acc = acc * T(0.5);
-        const T dn = d_r[ii][comp] + acc;
-        a.d[dof] = dn;
-        a.u_out[dof] = u_s[comp * NRN + rl] + dn;
-      }
-    } else if (MODE == kModeApply) {
-#pragma unroll
-      for (int comp = 0; comp < NCOMP; ++comp)
-        a.u_out[(int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node] = r[comp];
-    } else {
-      const T s = (T)sqrt(a.invm64[node]);
-#pragma unroll
-      for (int comp = 0; comp < NCOMP; ++comp)
-        a.u_out[(int64_t)comp * a.nnodes + node] = s * r[comp];
     }
+
+    // ---- stage cell info, node values, K_ref, local offsets in LDS ----
+  #pragma unroll
+    for (int it = 0; it < NCI; ++it) {
+      const int c = tid + it * 256;
+      if (c < NRC) info_s[c] = inf_r[it];
+    }
+    if (!DIRECT) {
+  #pragma unroll
+      for (int it = 0; it < NUL; ++it) u_s[tid + it * 256] = u_r[DIRECT ? 0 : it];
+    }
+    if (tid == 0) {
+      src_on = 0;
+      ft_s = 0.0;
+      if (MODE == kModeStep && a.src != nullptr) {
+        const SourceDev& s = a.src[rhs];
+        // owned node box of this tile vs node box of the source cell
+        bool hit = true;
+        const int c0[3] = {cx0, cy0, cz0};
+        const int tt[3] = {TX, TY, TZ};
+        for (int k = 0; k < DIM; ++k) {
+          const int o0 = c0[k] * P;
+          const int o1 = (c0[k] + tt[k] >= a.n[k]) ? a.np[k] : (c0[k] + tt[k]) * P;
+          const int s0 = s.cell[k] * P, s1 = s.cell[k] * P + P;
+          if (s1 < o0 || s0 >= o1) hit = false;
+        }
+        if (hit) {
+          src_on = 1;
+          ft_s = ricker(a.t, s.f0);
+        }
+      }
+    }
+    if (DIRECT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    // ---- cut cells: their products (cut-cell kernel) go global -> LDS by DMA, one wave
+    // per cell, all copies in flight while the matrix cores work below ----
+    if (MODE != kModeLanczos) {
+      constexpr int DPE = (int)(sizeof(T) / 4);
+      constexpr int RDW = NL * DPE;  // dwords of one cell's products
+      int seen = 0;
+      for (int c0 = 0; c0 < NRC; c0 += 64) {
+        const int cc = c0 + lane;
+        const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
+        unsigned long long mask = __ballot(isc);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          if ((seen++ & 3) != wave) continue;
+          const int c = c0 + bit;
+          const uint32_t* src =
+              (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL);
+          uint32_t* dst = (uint32_t*)(y_s + c * NL);
+  #pragma unroll
+          for (int ch = 0; ch < (RDW + 63) / 64; ++ch)
+            if (ch * 64 + lane < RDW) load_dword_to_lds(src + ch * 64 + lane, dst + ch * 64);
+        }
+      }
+    }
+    // ---- uncut cells: batched K_ref contraction on the matrix cores ----
+    // Every non-cut cell of the region gets its row of y_s here: uncut cells their
+    // product, cells outside the domain zeros (their B operand is masked to zero).
+    if constexpr (BF) {
+      // BF16 form: operands split into bf16 hi + lo parts (nearest even), the four products
+      // K_lo u_lo + K_lo u_hi + K_hi u_lo + K_hi u_hi accumulated in FP32, smallest first
+      for (int b = wave; b < NB; b += 4) {
+        const int c = b * 16 + lc;
+        const int cs = min(c, NRC - 1);
+        const int inf = info_s[cs];
+        const bool valid = (c < NRC) && (inf == kInfoUncut);
+        const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
+        const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
+        f32x4 acc[NMB];
+  #pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) acc[mb] = f32x4{0, 0, 0, 0};
+  #pragma unroll
+        for (int kb = 0; kb < NKB; ++kb) {
+          bf16x8 bhi, blo;
+  #pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int off = off_s[kb * 32 + 8 * lk + e];
+            const float v = (valid && off >= 0) ? (float)u_s[base + max(off, 0)] : 0.0f;
+            const __bf16 h = (__bf16)v;
+            bhi[e] = h;
+            blo[e] = (__bf16)(v - (float)h);  // exact in FP32
+          }
+  #pragma unroll
+          for (int mb = 0; mb < NMB; ++mb) {
+            const bf16x8 ahi = a_sb[((mb * NKB + kb) * 2 + 0) * 64 + lane];
+            const bf16x8 alo = a_sb[((mb * NKB + kb) * 2 + 1) * 64 + lane];
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, blo, acc[mb], 0, 0, 0);
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[mb], 0, 0, 0);
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[mb], 0, 0, 0);
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[mb], 0, 0, 0);
+          }
+        }
+        if (c < NRC && inf < 0) {
+  #pragma unroll
+          for (int mb = 0; mb < NMB; ++mb)
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = mb * 16 + 4 * lk + r;
+              if (i < NL) y_s[c * NL + i] = (T)acc[mb][r];
+            }
+        }
+      }
+    } else {
+      int offk[NKS];
+  #pragma unroll
+      for (int kk = 0; kk < NKS; ++kk) offk[kk] = off_s[4 * kk + lk];
+      for (int b = wave; b < NB; b += 4) {
+        const int c = b * 16 + lc;
+        const int cs = min(c, NRC - 1);
+        const int inf = info_s[cs];
+        const bool valid = (c < NRC) && (inf == kInfoUncut);
+        const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
+        const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
+        T bv[NKS];
+  #pragma unroll
+        for (int kk = 0; kk < NKS; ++kk) {
+          const T v = u_s[base + max(offk[kk], 0)];
+          bv[kk] = (valid && offk[kk] >= 0) ? v : T(0);
+        }
+        typename Mma<T>::acc acc[NMB];
+  #pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) acc[mb] = typename Mma<T>::acc{0, 0, 0, 0};
+  #pragma unroll
+        for (int kk = 0; kk < NKS; ++kk) {
+  #pragma unroll
+          for (int mb = 0; mb < NMB; ++mb) {
+            T av;
+            if (AREG) {
+              av = areg[AREG ? mb : 0][AREG ? kk : 0];
+            } else if (ALDS) {
+              av = a_s[ALDS ? (mb * 16 + lc) * KW + 4 * kk + lk : 0];
+            } else {
+              const int r = mb * 16 + lc, cc = 4 * kk + lk;
+              av = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
+            }
+            acc[mb] = Mma<T>::mma(av, bv[kk], acc[mb]);
+          }
+        }
+        if (c < NRC && inf < 0) {
+  #pragma unroll
+          for (int mb = 0; mb < NMB; ++mb)
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = mb * 16 + Mma<T>::row(lk, r);
+              if (i < NL) y_s[c * NL + i] = acc[mb][r];
+            }
+        }
+      }
+    }  // FP32 / FP64 operands
+
+    // ---- Lanczos operator: full FP64 setup matrices streamed per tile, one wave per cell ----
+    if (MODE == kModeLanczos) {
+      int seen = 0;
+      for (int c0 = 0; c0 < NRC; c0 += 64) {
+        const int cc = c0 + lane;
+        const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
+        unsigned long long mask = __ballot(isc);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          if ((seen++ & 3) != wave) continue;
+          const int c = c0 + bit;
+          const int q = info_s[c];
+          const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
+          const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
+          const T* K = a.kcut + (int64_t)q * NL * NL;
+          constexpr int NR = (NL + 63) / 64;
+          // FP64 accumulation: the rows of a cut-cell matrix cancel strongly and the
+          // small lumped masses of cut-cell nodes amplify any error in their sum
+          double y[NR];
+  #pragma unroll
+          for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
+          // straight-line over the columns: every load of the cell is issued before use
+  #pragma unroll
+          for (int j = 0; j < NL; ++j) {
+            const T uj = u_s[base + off_s[j]];
+  #pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+              const int i = min(lane + 64 * rr, NL - 1);
+              y[rr] += (double)K[i * NL + j] * (double)uj;
+            }
+          }
+  #pragma unroll
+          for (int rr = 0; rr < NR; ++rr) {
+            const int i = lane + 64 * rr;
+            if (i < NL) y_s[c * NL + i] = (T)y[rr];
+          }
+        }
+      }
+    }
+    if (MODE != kModeLanczos) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    // ---- owned nodes: fixed-order gather of element results + update ----
+    // The cells around node g along one axis are a = g/P - 1 (when g is a positive
+    // multiple of P) and b = g/P (when g < n P); cells outside the domain hold zeros.
+  #pragma unroll
+    for (int it = 0; it < NO; ++it) {
+      const int i = tid + it * 256;
+      const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
+      if (i >= OX * OY * OZ || lx >= onx || ly >= ony || lz >= onz) continue;
+      const int g3[3] = {ox0 + lx, oy0 + ly, oz0 + lz};
+      const int64_t node = g3[0] + (int64_t)a.np[0] * (g3[1] + (int64_t)a.np[1] * g3[2]);
+      int ca[3], cb[3], la[3], lb[3];
+      bool ua[3], ub[3];
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int rc0 = (k == 0) ? rcx0 : (k == 1 ? rcy0 : rcz0);
+        if (k >= DIM) {
+          ca[k] = cb[k] = 0; la[k] = lb[k] = 0; ua[k] = false; ub[k] = true;
+          continue;
+        }
+        const int g = g3[k];
+        const int q = g / P, rem = g - q * P;
+        ua[k] = (rem == 0) && (g > 0);
+        ub[k] = g < a.n[k] * P;
+        ca[k] = max(q - 1 - rc0, 0);                       // region-local cell index
+        cb[k] = min(q - rc0, (k == 0 ? RCX : (k == 1 ? RCY : RCZ)) - 1);
+        la[k] = P;                                          // local node in cell a
+        lb[k] = rem;                                        // local node in cell b
+      }
+      T r[NCOMP];
+  #pragma unroll
+      for (int comp = 0; comp < NCOMP; ++comp) r[comp] = T(0);
+  #pragma unroll
+      for (int sz = 0; sz < (DIM == 3 ? 2 : 1); ++sz)
+  #pragma unroll
+        for (int sy = 0; sy < (DIM >= 2 ? 2 : 1); ++sy)
+  #pragma unroll
+          for (int sx = 0; sx < 2; ++sx) {
+            const bool use = (sx ? ub[0] : ua[0]) && (DIM < 2 || (sy ? ub[1] : ua[1])) &&
+                             (DIM < 3 || (sz ? ub[2] : ua[2]));
+            const int lcell = (sx ? cb[0] : ca[0]) +
+                              RCX * ((sy ? cb[1] : ca[1]) + RCY * (sz ? cb[2] : ca[2]));
+            const int loc = (sx ? lb[0] : la[0]) +
+                            NP1 * ((sy ? lb[1] : la[1]) + NP1 * (sz ? lb[2] : la[2]));
+  #pragma unroll
+            for (int comp = 0; comp < NCOMP; ++comp) {
+              const T v = y_s[lcell * NL + comp * NS + loc];
+              r[comp] += use ? v : T(0);
+            }
+          }
+      if (MODE == kModeStep) {
+        const int ii = (MODE == kModeStep) ? it : 0;
+        const int rl = (g3[0] - rnx0) + RNX * ((g3[1] - rny0) + RNY * (g3[2] - rnz0));
+        const T im = im_r[ii];
+        int sloc = -1;
+        if (src_on) {
+          const SourceDev& s = a.src[rhs];
+          const int sx = g3[0] - s.cell[0] * P, sy = g3[1] - s.cell[1] * P,
+                    sz = g3[2] - s.cell[2] * P;
+          if (sx >= 0 && sx <= P && (DIM < 2 || (sy >= 0 && sy <= P)) &&
+              (DIM < 3 || (sz >= 0 && sz <= P)))
+            sloc = sx + NP1 * ((DIM >= 2 ? sy : 0) + NP1 * (DIM == 3 ? sz : 0));
+        }
+  #pragma unroll
+        for (int comp = 0; comp < NCOMP; ++comp) {
+          const int64_t dof = (int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node;
+          T F = T(0);
+          if (sloc >= 0) F = (T)(ft_s * a.src[rhs].b[comp * NS + sloc]);
+          T acc = a.dt2 * im * (F - r[comp]);
+          if (a.start) acc = acc * T(0.5);
+          const T dn = d_r[ii][comp] + acc;
+          a.d[dof] = dn;
+          a.u_out[dof] = u_s[comp * NRN + rl] + dn;
+        }
+      } else if (MODE == kModeApply) {
+  #pragma unroll
+        for (int comp = 0; comp < NCOMP; ++comp)
+          a.u_out[(int64_t)rhs * a.ndof + (int64_t)comp * a.nnodes + node] = r[comp];
+      } else {
+        const T s = (T)sqrt(a.invm64[node]);
+  #pragma unroll
+        for (int comp = 0; comp < NCOMP; ++comp)
+          a.u_out[(int64_t)comp * a.nnodes + node] = s * r[comp];
+      }
+    }
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 
 // --------------------------------------------------------------------------------
 // dispatch
 // --------------------------------------------------------------------------------
+
+// Blocks per XCD of a persistent launch: as many as the kernel's occupancy keeps resident
+// on the XCD's compute units (at most one per tile).
+static int resident_per_xcd(const void* kern) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(kern);
+  if (it != cache.end()) return it->second;
+  int dev = 0, ncu = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb < 1)
+    return 64;  // a safe guess; not cached
+  const int v = std::max(1, nb * ncu / 8);
+  cache[kern] = v;
+  return v;
+}
 
 template <typename T>
 static StepArgs<T> make_args(const Ctx& c, int tx, int ty, int tz) {
@@ -504,6 +535,15 @@ using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, 
 
 template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, bool BF = false>
 struct TileCfg {
+  // 3-D: persistent launch, 8 x (blocks per XCD) blocks each walking its XCD's tiles, so
+  // the large K_ref (LDS or bf16 fragments) is staged once per block; 2-D (K_ref in
+  // registers): one block per tile, which balances better
+  static fcw_status launch(void (*kern)(StepArgs<T>), Ctx& c, const StepArgs<T>& a, int nrhs) {
+    const int nbx = (DIM == 3) ? std::min(a.chunk, resident_per_xcd((const void*)kern)) : a.chunk;
+    kern<<<dim3(8 * nbx, nrhs, 1), 256, 0, c.stream>>>(a);
+    FCW_HIP(hipGetLastError());
+    return FCW_OK;
+  }
   static StepArgs<T> args(Ctx& c, const void* uin, void* uout, void* d, double t, double dt,
                           int start, int mode) {
     StepArgs<T> a = make_args<T>(c, TX, TY, TZ);
@@ -531,18 +571,10 @@ struct TileCfg {
       if (st) return st;
     }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
-    dim3 grid(8 * a.chunk, nrhs, 1);
-    if (mode == kModeStep) {
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
-      FCW_HIP(hipGetLastError());
-      return FCW_OK;
-    }
+    if (mode == kModeStep) return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF>, c, a, nrhs);
     if (mode == kModeApply)
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF><<<grid, 256, 0, c.stream>>>(a);
-    else
-      tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos, false><<<grid, 256, 0, c.stream>>>(a);
-    FCW_HIP(hipGetLastError());
-    return FCW_OK;
+      return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF>, c, a, nrhs);
+    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos, false>, c, a, nrhs);
   }
   // the step only (alternative tile shapes offered to the autotuner)
   static fcw_status run_step(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
@@ -556,10 +588,7 @@ struct TileCfg {
       if (st) return st;
     }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
-    dim3 grid(8 * a.chunk, nrhs, 1);
-    tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF><<<grid, 256, 0, c.stream>>>(a);
-    FCW_HIP(hipGetLastError());
-    return FCW_OK;
+    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF>, c, a, nrhs);
   }
 };
 
