@@ -174,9 +174,10 @@ fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
 
 /* Average duration in microseconds of one launch of the step's main kernel (*main_us:
  * the tile or 2-D kernel of the selected configuration) and of the cut-cell product
- * kernel (*cut_us; 0 without cut cells), each timed over nsteps launches back to back
- * with HIP events on the context's stream, on scratch state with nrhs right-hand sides.
- * For measurement; the caller's state is not touched.  Synchronises. */
+ * kernel (*cut_us; 0 without cut cells), each timed over nsteps launches back to back,
+ * captured into a HIP graph and replayed between HIP events on the context's stream (so
+ * host launch gaps between short kernels are not counted), on scratch state with nrhs
+ * right-hand sides.  For measurement; the caller's state is not touched.  Synchronises. */
 fcw_status fcw_kernel_times(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, double* main_us,
                             double* cut_us);
 

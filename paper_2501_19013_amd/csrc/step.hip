@@ -687,7 +687,7 @@ bool step_supported(const Ctx& c) {
 }
 
 using Run2d = fcw_status (*)(hipStream_t, const void*, const int4*, int, int, const void*, int);
-int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]);
+int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3], std::string* name);
 size_t prob2d_size(int fp64);
 void prob2d_fill(const Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
                  int nsteps, int start, int tx, int ty, const SourceDev* src);
@@ -703,13 +703,13 @@ struct StepCand {
 static int step_candidates(const Ctx& c, int i, StepCand* out) {
   const int fp64 = c.precision == FCW_FP64;
   const int n2 = (c.dim == 2 && c.ncomp == 1 && c.precision != FCW_BF16)
-                     ? step2d_candidates(c.p, fp64, -1, nullptr, nullptr)
+                     ? step2d_candidates(c.p, fp64, -1, nullptr, nullptr, nullptr)
                      : 0;
   Cand cs[kMaxCand];
   const int ng = cands_for(c, fp64, cs);
   if (out) {
     if (i >= 0 && i < n2) {
-      step2d_candidates(c.p, fp64, i, &out->f2d, out->tile);
+      step2d_candidates(c.p, fp64, i, &out->f2d, out->tile, nullptr);
     } else if (i >= n2 && i < n2 + ng) {
       out->fgen = cs[i - n2].fn;
       for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
@@ -724,16 +724,15 @@ int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name) {
   if (i < 0 || i >= n) return n;
   if (tile)
     for (int k = 0; k < 3; ++k) tile[k] = sc.tile[k];
-  if (name) {
+  if (name && sc.f2d) {
+    step2d_candidates(c.p, c.precision == FCW_FP64, i, nullptr, nullptr, name);
+  } else if (name) {
     // the kernel's name as a profiler prints it (single-problem launches)
-    const char* t = c.precision == FCW_FP64 ? "double" : "float";
     char b[128];
-    if (sc.f2d)
-      std::snprintf(b, sizeof b, "fcw::step2d_kernel<%s, %d, %d, true>", t, c.p, sc.tile[1]);
-    else
-      std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d, %s>", t, c.dim,
-                    c.p, c.ncomp, sc.tile[0], sc.tile[1], sc.tile[2], (int)kModeStep,
-                    c.precision == FCW_BF16 ? "true" : "false");
+    std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d, %s>",
+                  c.precision == FCW_FP64 ? "double" : "float", c.dim, c.p, c.ncomp, sc.tile[0],
+                  sc.tile[1], sc.tile[2], (int)kModeStep,
+                  c.precision == FCW_BF16 ? "true" : "false");
     *name = b;
   }
   return n;

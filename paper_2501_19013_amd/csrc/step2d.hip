@@ -20,7 +20,9 @@
 //    GLL weights; only nodes flagged in a per-node bitmap (next to cut or outside cells)
 //    read the stored inverse mass.  d and M^{-1} are loaded into registers during the
 //    matrix-core phase.
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <type_traits>
 
 #include "step_common.h"
@@ -745,14 +747,15 @@ static fcw_status run2d(hipStream_t stream, const void* probs, const int4* items
   return FCW_OK;
 }
 
-// 2-D step kernels offered to the autotuner: (P, TY) -> launcher; TX = 64 / P.
-int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
-  struct E { int p, tx, ty; Run2d f32, f64; };
+// 2-D step kernels offered to the autotuner: (P, TY) -> launcher; TX = 64 / P.  `name`
+// receives the kernel's name as a profiler prints it (single-problem launches).
+int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3], std::string* name) {
+  struct E { int p, tx, ty, nbr, nw; Run2d f32, f64; };
   // tile kernels (tile = cells), then streaming kernels (tile = owned cells per row x cell
   // rows per block)
 #define FCW_S(PP, NBR, YR, NW) \
-  E{PP, 16 * NBR - 1, YR, &runs2d<float, PP, NBR, YR, NW>, &runs2d<double, PP, NBR, YR, NW>}
-#define FCW_E(PP, TY) E{PP, 64 / PP, TY, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
+  E{PP, 16 * NBR - 1, YR, NBR, NW, &runs2d<float, PP, NBR, YR, NW>, &runs2d<double, PP, NBR, YR, NW>}
+#define FCW_E(PP, TY) E{PP, 64 / PP, TY, 0, 0, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
       FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
       FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8),
@@ -766,6 +769,16 @@ int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3]) {
     if (n == i) {
       if (fn) *fn = fp64 ? e.f64 : e.f32;
       if (tile) { tile[0] = e.tx; tile[1] = e.ty; tile[2] = 1; }
+      if (name) {
+        char b[128];
+        const char* t = fp64 ? "double" : "float";
+        if (e.nbr)
+          std::snprintf(b, sizeof b, "fcw::stream2d_kernel<%s, %d, %d, %d, %d, true>", t, e.p,
+                        e.nbr, e.ty, e.nw);
+        else
+          std::snprintf(b, sizeof b, "fcw::step2d_kernel<%s, %d, %d, true>", t, e.p, e.ty);
+        *name = b;
+      }
     }
     ++n;
   }
