@@ -40,12 +40,20 @@ struct CutProb {
 
 template <typename T, int NL>
 struct CutShape {
-  static constexpr int KD = NL * (NL + 1) / 2 * (int)(sizeof(T) / 4);  // dwords per matrix
+  static constexpr int DPE = (int)(sizeof(T) / 4);
+  static constexpr int KD = NL * (NL + 1) / 2 * DPE;  // dwords per packed matrix
   static constexpr int KDP = (KD + 63) / 64 * 64;
-  static constexpr int UEP = (NL * (int)(sizeof(T) / 4) + 63) / 64 * 64;
+  static constexpr int UEP = (NL * DPE + 63) / 64 * 64;
+  // Pipelined form, for matrices of 1024 to 4096 dwords: a wave walks CPW cells; the
+  // next cell's packed matrix travels global -> registers while the current one is
+  // reduced from LDS.  Other sizes: packed triangle global -> LDS directly, one cell
+  // per wave.
+  static constexpr bool PIPE = KDP / 64 <= 64 && KD >= 1024;
   static constexpr int STRIDE = KDP + UEP;  // LDS dwords per wave
+  static constexpr int CPW = PIPE ? 8 : 1;                        // cells per wave
   static constexpr int WPB_ = 64 * 1024 / (STRIDE * 4);
-  static constexpr int WPB = WPB_ < 1 ? 1 : (WPB_ > 4 ? 4 : WPB_);  // waves per block
+  static constexpr int WPB = PIPE ? 1 : (WPB_ < 1 ? 1 : (WPB_ > 4 ? 4 : WPB_));  // waves per block
+  static constexpr int CPB = WPB * CPW;  // cells per block
   static constexpr int LDS = WPB * STRIDE * 4;
 };
 
@@ -53,6 +61,43 @@ __device__ static inline void lds_dword(const void* gsrc, void* lds_wave_base) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)gsrc,
                                    (__attribute__((address_space(3))) void*)lds_wave_base, 4, 0,
                                    0);
+}
+
+// Global node indices (component-major dofs) of the local rows lane + 64 rr of a cell.
+template <int DIM, int P, int NCOMP, int NR, typename Pr>
+__device__ static inline void cell_dofs(const Pr& pr, int cell, int lane, int64_t nodes[NR]) {
+  constexpr int NP1 = P + 1;
+  constexpr int NS = ipow(NP1, DIM);
+  constexpr int NL = NCOMP * NS;
+  const int cx = cell % pr.n[0];
+  const int cy = (DIM >= 2) ? (cell / pr.n[0]) % pr.n[1] : 0;
+  const int cz = (DIM == 3) ? cell / (pr.n[0] * pr.n[1]) : 0;
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    const int i = min(lane + 64 * rr, NL - 1);
+    const int comp = i / NS, loc = i % NS;
+    const int i0 = loc % NP1, i1 = (loc / NP1) % NP1, i2 = loc / (NP1 * NP1);
+    nodes[rr] = (int64_t)comp * pr.nnodes + (cx * P + i0) +
+                (int64_t)pr.np[0] * ((cy * P + i1) + (int64_t)pr.np[1] * (cz * P + i2));
+  }
+}
+
+// y = K u for one cell from its packed upper triangle K and node values ue in LDS; lane
+// i accumulates rows i, i + 64, ... in FP64 over the columns in order.
+template <typename T, int NL, int NR>
+__device__ static inline void cell_rows(const T* K, const T* ue, int lane, double y[NR]) {
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
+#pragma unroll 9
+  for (int jj = 0; jj < NL; ++jj) {
+    const double uj = (double)ue[jj];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+      const int i = min(lane + 64 * rr, NL - 1);
+      const int idx = (i <= jj) ? jj * (jj + 1) / 2 + i : i * (i + 1) / 2 + jj;
+      y[rr] += (double)K[idx] * uj;
+    }
+  }
 }
 
 template <typename T, int DIM, int P, int NCOMP, bool SINGLE>
@@ -66,7 +111,8 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
   using S = CutShape<T, NL>;
   extern __shared__ unsigned int lds_u32[];
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   // neighbouring cut cells (neighbouring in space) on one XCD share node rows in its L2
   const int64_t blk = (int64_t)(blockIdx.x % 8) * chunk + (blockIdx.x / 8);
   int k = 0;
@@ -80,66 +126,129 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
   }
   const CutProb<T>& pr = SINGLE ? one : probs[k];
   if (j >= pr.nsteps) return;
-  const int64_t q = (blk - pr.blk0) * S::WPB + wave;
-  if (q < 0 || q >= pr.ncand) return;
-  const int cell = pr.cut_cells[q];
-  if (pr.info[cell] < 0) return;  // reclassified (every leaf void): not stepped
+  const int64_t q0 = ((blk - pr.blk0) * S::WPB + wave) * S::CPW;
+  if (q0 < 0 || q0 >= pr.ncand) return;
+  const int ncell = (int)min((int64_t)S::CPW, pr.ncand - q0);
 
   unsigned int* kw = lds_u32 + wave * S::STRIDE;
   const T* K = (const T*)kw;
   T* ue = (T*)(kw + S::KDP);
-  const unsigned int* src = (const unsigned int*)pr.kcut + q * S::KD;
-  const int64_t rem = (pr.ncand - q) * S::KD;  // dwords of the array from this matrix on
-#pragma unroll 4
-  for (int w = 0; w < S::KDP / 64; ++w) {
-    const int64_t o = min((int64_t)(w * 64 + lane), rem - 1);
-    lds_dword(src + o, kw + w * 64);
-  }
-  const int cx = cell % pr.n[0];
-  const int cy = (DIM >= 2) ? (cell / pr.n[0]) % pr.n[1] : 0;
-  const int cz = (DIM == 3) ? cell / (pr.n[0] * pr.n[1]) : 0;
-  int64_t nodes[NR];
-#pragma unroll
-  for (int rr = 0; rr < NR; ++rr) {
-    const int i = min(lane + 64 * rr, NL - 1);
-    const int comp = i / NS, loc = i % NS;
-    const int i0 = loc % NP1, i1 = (loc / NP1) % NP1, i2 = loc / (NP1 * NP1);
-    nodes[rr] = (int64_t)comp * pr.nnodes + (cx * P + i0) +
-                (int64_t)pr.np[0] * ((cy * P + i1) + (int64_t)pr.np[1] * (cz * P + i2));
-  }
   const T* uin = ((pr.nsteps - 1 - j) & 1) ? pr.ua : pr.ub;
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  const int64_t total = pr.ncand * S::KD;  // dwords of the packed array
+  const unsigned int* kall = (const unsigned int*)pr.kcut;
 
-  for (int r = 0; r < pr.nrhs; ++r) {
-    const T* u = uin + (int64_t)r * pr.ndof;
+  // the wave's cells (lane l holds cell q0 + l) and whether each is stepped (a cut cell
+  // whose every leaf is void is reclassified and not stepped)
+  int my_cell = 0, my_on = 0;
+  if (lane < ncell) {
+    my_cell = pr.cut_cells[q0 + lane];
+    my_on = pr.info[my_cell] >= 0;
+  }
+
+  if constexpr (S::PIPE) {
+    constexpr int KW = S::KDP / 64;
+    uint32_t kr[KW];
+    T u0[NR];
+    int64_t nodes[NR];
+    // the loads of cell q: its matrix in whole 64-dword rows through a buffer resource
+    // that ends at the array's end (reads past it return zero) and its node values of
+    // rhs 0
+    auto issue = [&](int64_t q, int cell) {
+      const int64_t left = (total - q * S::KD) * 4;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(kall + q * S::KD), (short)0, (int)min(left, (int64_t)S::KDP * 4), 0x00020000);
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-      const int i = lane + 64 * rr;
-      if (i < NL) ue[i] = u[nodes[rr]];
-    }
-    // LDS accesses of one wave complete in order; the barrier keeps the compiler's order
-    __builtin_amdgcn_wave_barrier();
-    double y[NR];
+      for (int w = 0; w < KW; ++w)
+        kr[w] = __builtin_amdgcn_raw_buffer_load_b32(rs, (w * 64 + lane) * 4, 0, 0);
+      cell_dofs<DIM, P, NCOMP, NR>(pr, cell, lane, nodes);
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
-#pragma unroll 9
-    for (int jj = 0; jj < NL; ++jj) {
-      const double uj = (double)ue[jj];
+      for (int rr = 0; rr < NR; ++rr) u0[rr] = uin[nodes[rr]];
+    };
+    issue(q0, __shfl(my_cell, 0));
+    double yprev[NR];
+    int64_t qprev = -1;
+    for (int c = 0; c < ncell; ++c) {
+      const int64_t q = q0 + c;
+      const int on = __shfl(my_on, c);
+      int64_t nd[NR];
 #pragma unroll
-      for (int rr = 0; rr < NR; ++rr) {
-        const int i = min(lane + 64 * rr, NL - 1);
-        const int idx = (i <= jj) ? jj * (jj + 1) / 2 + i : i * (i + 1) / 2 + jj;
-        y[rr] += (double)K[idx] * uj;
+      for (int rr = 0; rr < NR; ++rr) nd[rr] = nodes[rr];
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+      for (int w = 0; w < KW; ++w) kw[w * 64 + lane] = kr[w];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr)
+        if (lane + 64 * rr < NL) ue[lane + 64 * rr] = u0[rr];
+      // the previous cell's rhs-0 products leave before the next loads are issued, so
+      // the wait at the top of the next pass finds them done
+      if (qprev >= 0) {
+        T* yo = pr.y + qprev * NL;
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+          if (lane + 64 * rr < NL) yo[lane + 64 * rr] = (T)yprev[rr];
+        qprev = -1;
       }
-    }
-    T* yo = pr.y + ((int64_t)r * pr.ncand + q) * NL;
+      if (c + 1 < ncell) issue(q + 1, __shfl(my_cell, c + 1));
+      // LDS accesses of one wave complete in order; the barrier keeps the compiler's order
+      __builtin_amdgcn_wave_barrier();
+      if (on) {
+        cell_rows<T, NL, NR>(K, ue, lane, yprev);
+        qprev = q;
+        // further right-hand sides: gathered and written here (not overlapped)
+        for (int r = 1; r < pr.nrhs; ++r) {
+          __builtin_amdgcn_wave_barrier();
+          const T* u = uin + (int64_t)r * pr.ndof;
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-      const int i = lane + 64 * rr;
-      if (i < NL) yo[i] = (T)y[rr];
+          for (int rr = 0; rr < NR; ++rr)
+            if (lane + 64 * rr < NL) ue[lane + 64 * rr] = u[nd[rr]];
+          __builtin_amdgcn_wave_barrier();
+          double yr[NR];
+          cell_rows<T, NL, NR>(K, ue, lane, yr);
+          T* yo = pr.y + ((int64_t)r * pr.ncand + q) * NL;
+#pragma unroll
+          for (int rr = 0; rr < NR; ++rr)
+            if (lane + 64 * rr < NL) yo[lane + 64 * rr] = (T)yr[rr];
+        }
+      }
+      // every lane has read this cell's LDS before the next pass overwrites it
+      __builtin_amdgcn_wave_barrier();
     }
-    // every lane has read ue before the next right-hand side overwrites it
-    __builtin_amdgcn_wave_barrier();
+    if (qprev >= 0) {
+      T* yo = pr.y + qprev * NL;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr)
+        if (lane + 64 * rr < NL) yo[lane + 64 * rr] = (T)yprev[rr];
+    }
+  } else {
+    // one cell per wave: packed triangle global -> LDS by DMA (64 coalesced dwords per
+    // instruction, no registers), node values of rhs 0 in flight alongside
+    const int64_t q = q0;
+    if (!__shfl(my_on, 0)) return;
+    const int cell = __shfl(my_cell, 0);
+#pragma unroll 4
+    for (int w = 0; w < S::KDP / 64; ++w)
+      lds_dword(kall + min(q * S::KD + w * 64 + lane, total - 1), kw + w * 64);
+    int64_t nodes[NR];
+    cell_dofs<DIM, P, NCOMP, NR>(pr, cell, lane, nodes);
+    T u0[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) u0[rr] = uin[nodes[rr]];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    for (int r = 0; r < pr.nrhs; ++r) {
+      const T* u = uin + (int64_t)r * pr.ndof;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr)
+        if (lane + 64 * rr < NL) ue[lane + 64 * rr] = (r == 0) ? u0[rr] : u[nodes[rr]];
+      __builtin_amdgcn_wave_barrier();
+      double y[NR];
+      cell_rows<T, NL, NR>(K, ue, lane, y);
+      T* yo = pr.y + ((int64_t)r * pr.ncand + q) * NL;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr)
+        if (lane + 64 * rr < NL) yo[lane + 64 * rr] = (T)y[rr];
+      // every lane has read ue before the next right-hand side overwrites it
+      __builtin_amdgcn_wave_barrier();
+    }
   }
 }
 
@@ -175,13 +284,13 @@ struct CutKind {
 
 using CutLaunch = fcw_status (*)(hipStream_t, const void*, int, const void*, int64_t, int);
 
-// launcher and waves per block of the cut-cell kernel of a problem kind (null if not built)
-static CutLaunch cut_kind(const Ctx& c, int* wpb) {
+// launcher and cells per block of the cut-cell kernel of a problem kind (null if not built)
+static CutLaunch cut_kind(const Ctx& c, int* cpb) {
   const bool f64 = c.precision == FCW_FP64;
 #define FCW_CUT(D, PP, NC)                                                          \
   if (c.dim == D && c.p == PP && c.ncomp == NC) {                                   \
-    if (f64) { *wpb = CutKind<double, D, PP, NC>::S::WPB; return &CutKind<double, D, PP, NC>::launch; } \
-    *wpb = CutKind<float, D, PP, NC>::S::WPB;                                        \
+    if (f64) { *cpb = CutKind<double, D, PP, NC>::S::CPB; return &CutKind<double, D, PP, NC>::launch; } \
+    *cpb = CutKind<float, D, PP, NC>::S::CPB;                                        \
     return &CutKind<float, D, PP, NC>::launch;                                       \
   }
   FCW_CUT(2, 1, 1) FCW_CUT(2, 2, 1) FCW_CUT(2, 3, 1) FCW_CUT(2, 4, 1) FCW_CUT(2, 5, 1)
@@ -239,19 +348,19 @@ static void fill(const Ctx& c, void* out, const void* ua, const void* ub, int nr
 // returns the number of blocks the problem takes.
 int64_t cutprob_fill(const Ctx& c, void* out, const void* ua, const void* ub, int nrhs,
                      int nsteps, int64_t blk0) {
-  int wpb = 1;
-  if (!cut_kind(c, &wpb)) wpb = 1;
+  int cpb = 1;
+  if (!cut_kind(c, &cpb)) cpb = 1;
   if (c.precision == FCW_FP64) fill<double>(c, out, ua, ub, nrhs, nsteps, blk0);
   else fill<float>(c, out, ua, ub, nrhs, nsteps, blk0);
-  return (c.n_cut_cand + wpb - 1) / wpb;
+  return (c.n_cut_cand + cpb - 1) / cpb;
 }
 
 // One launch of the cut-cell kernel: a single record by value (`one`), or nprob device
 // records covering nblk blocks; step j of the call.
 fcw_status launch_cut(const Ctx& kind, hipStream_t s, const void* probs, int nprob,
                       const void* one, int64_t nblk, int j) {
-  int wpb = 1;
-  CutLaunch f = cut_kind(kind, &wpb);
+  int cpb = 1;
+  CutLaunch f = cut_kind(kind, &cpb);
   if (!f) {
     set_error("cut-cell kernel not built for dim=%d p=%d ncomp=%d", kind.dim, kind.p, kind.ncomp);
     return FCW_E_UNSUPPORTED;

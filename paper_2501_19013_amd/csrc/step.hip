@@ -1,7 +1,7 @@
 // The explicit step of the spectral cell method on gfx950: one fused tile kernel per
 // central-difference step (paper eq. cdm), organised for CDNA4:
 //
-//  * A workgroup (4 wave64) owns a tile of TX x TY (x TZ) cells and every node in the
+//  * A workgroup (4 or 8 wave64) owns a tile of TX x TY (x TZ) cells and every node in the
 //    half-open node box of those cells.  It stages the node values of the tile plus
 //    one ring of cells on the low side in LDS (coalesced row loads), so each owned
 //    node sees every cell around it without atomics or a second pass.
@@ -40,8 +40,9 @@ __device__ static inline void load_dword_to_lds(const void* gsrc, void* lds_wave
                                    0);
 }
 
-template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE, bool BF>
-__global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
+template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE, bool BF, int NW>
+__global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
+  constexpr int NT = 64 * NW;  // threads of the block (NW waves)
   constexpr int NP1 = P + 1;
   constexpr int NS = ipow(NP1, DIM);
   constexpr int NL = NCOMP * NS;
@@ -69,14 +70,17 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
   constexpr int OX = TX * P + 1;
   constexpr int OY = (DIM >= 2) ? TY * P + 1 : 1;
   constexpr int OZ = (DIM == 3) ? TZ * P + 1 : 1;
-  constexpr int NO = (OX * OY * OZ + 255) / 256;  // owned nodes per thread
+  constexpr int NO = (OX * OY * OZ + NT - 1) / NT;  // owned nodes per thread
   constexpr int NUV = NCOMP * NRN;                // staged node values
-  constexpr int NUL = (NUV + 255) / 256;          // ... per thread
-  constexpr int NCI = (NRC + 255) / 256;          // staged cell infos per thread
+  constexpr int NUL = (NUV + NT - 1) / NT;            // ... per thread
+  constexpr int NCI = (NRC + NT - 1) / NT;            // staged cell infos per thread
   // direct global->LDS staging of dword node values (the Lanczos operator scales them)
   constexpr bool DIRECT = (sizeof(T) == 4) && (MODE != kModeLanczos);
 
-  __shared__ T u_s[NUL * 256];
+  // staged node values, plus one slot that holds zero: masked operands (padding of k,
+  // cells other than uncut ones) read it, so every operand load is unconditional
+  __shared__ T u_s[NUL * NT + 1];
+  constexpr int ZSLOT = NUL * NT;
   __shared__ T y_s[NRC * NL];
   __shared__ T a_s[ALDS ? NMB * 16 * KW : 1];
   __shared__ int info_s[NRC];
@@ -104,12 +108,12 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       }
   }
   if (ALDS) {
-    for (int i = tid; i < NMB * 16 * KW; i += 256) {
+    for (int i = tid; i < NMB * 16 * KW; i += NT) {
       const int r = i / KW, cc = i % KW;
       a_s[i] = (r < NL && cc < NL) ? a.kref[r * NL + cc] : T(0);
     }
   }
-  for (int j = tid; j < KWB; j += 256) {
+  for (int j = tid; j < KWB; j += NT) {
     int off = -1;
     if (j < NL) {
       const int comp = j / NS, loc = j % NS;
@@ -122,9 +126,10 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     // contiguous copy of the lane-ordered fragments (NFRAG x 16 bytes), 64 dwords per
     // wave instruction
     const uint32_t* src = (const uint32_t*)a.kref_bf;
-    for (int w = wave; w < NFRAG * 4 / 64; w += 4)
+    for (int w = wave; w < NFRAG * 4 / 64; w += NW)
       load_dword_to_lds(src + w * 64 + lane, (uint32_t*)a_sb + w * 64);
   }
+  if (tid == 0) u_s[ZSLOT] = T(0);  // never written by the staging below
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     int inf_r[NCI];
   #pragma unroll
     for (int it = 0; it < NCI; ++it) {
-      const int c = tid + it * 256;
+      const int c = tid + it * NT;
       const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
       const int gx = rcx0 + lx, gy = rcy0 + ly, gz = rcz0 + lz;
       const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     T u_r[DIRECT ? 1 : NUL];
   #pragma unroll
     for (int it = 0; it < NUL; ++it) {
-      const int i = tid + it * 256;
+      const int i = tid + it * NT;
       const int comp = min(i / NRN, NCOMP - 1), j = i % NRN;
       const int lx = j % RNX, ly = (j / RNX) % RNY, lz = j / (RNX * RNY);
       const int gx = rnx0 + lx, gy = rny0 + ly, gz = rnz0 + lz;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       const int64_t node = in ? gx + (int64_t)a.np[0] * (gy + (int64_t)a.np[1] * gz) : 0;
       const T* src = uin + (int64_t)comp * a.nnodes + node;
       if (DIRECT) {
-        load_dword_to_lds(src, &u_s[it * 256 + wave * 64]);
+        load_dword_to_lds(src, &u_s[it * NT + wave * 64]);
       } else {
         T v = *src;
         if (MODE == kModeLanczos) v = v * (T)sqrt(a.invm64[node]);
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     if (MODE == kModeStep) {
   #pragma unroll
       for (int it = 0; it < NO; ++it) {
-        const int i = tid + it * 256;
+        const int i = tid + it * NT;
         const int ii = (MODE == kModeStep) ? it : 0;
         const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
         const bool own = i < OX * OY * OZ && lx < onx && ly < ony && lz < onz;
@@ -206,12 +211,12 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     // ---- stage cell info, node values, K_ref, local offsets in LDS ----
   #pragma unroll
     for (int it = 0; it < NCI; ++it) {
-      const int c = tid + it * 256;
+      const int c = tid + it * NT;
       if (c < NRC) info_s[c] = inf_r[it];
     }
     if (!DIRECT) {
   #pragma unroll
-      for (int it = 0; it < NUL; ++it) u_s[tid + it * 256] = u_r[DIRECT ? 0 : it];
+      for (int it = 0; it < NUL; ++it) u_s[tid + it * NT] = u_r[DIRECT ? 0 : it];
     }
     if (tid == 0) {
       src_on = 0;
@@ -250,7 +255,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         while (mask) {
           const int bit = __ffsll((long long)mask) - 1;
           mask &= mask - 1;
-          if ((seen++ & 3) != wave) continue;
+          if ((seen++ % NW) != wave) continue;
           const int c = c0 + bit;
           const uint32_t* src =
               (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL);
@@ -267,7 +272,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     if constexpr (BF) {
       // BF16 form: operands split into bf16 hi + lo parts (nearest even), the four products
       // K_lo u_lo + K_lo u_hi + K_hi u_lo + K_hi u_hi accumulated in FP32, smallest first
-      for (int b = wave; b < NB; b += 4) {
+      for (int b = wave; b < NB; b += NW) {
         const int c = b * 16 + lc;
         const int cs = min(c, NRC - 1);
         const int inf = info_s[cs];
@@ -277,16 +282,24 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         f32x4 acc[NMB];
   #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) acc[mb] = f32x4{0, 0, 0, 0};
+        // every operand load of the block is issued before the first product
+        float bv[NKB][8];
+  #pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+  #pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const int off = off_s[kb * 32 + 8 * lk + e];
+            bv[kb][e] = (float)u_s[(valid && off >= 0) ? base + off : ZSLOT];
+          }
+        __builtin_amdgcn_sched_barrier(0);
   #pragma unroll
         for (int kb = 0; kb < NKB; ++kb) {
           bf16x8 bhi, blo;
   #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const int off = off_s[kb * 32 + 8 * lk + e];
-            const float v = (valid && off >= 0) ? (float)u_s[base + max(off, 0)] : 0.0f;
-            const __bf16 h = (__bf16)v;
+            const __bf16 h = (__bf16)bv[kb][e];
             bhi[e] = h;
-            blo[e] = (__bf16)(v - (float)h);  // exact in FP32
+            blo[e] = (__bf16)(bv[kb][e] - (float)h);  // exact in FP32
           }
   #pragma unroll
           for (int mb = 0; mb < NMB; ++mb) {
@@ -312,7 +325,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
       int offk[NKS];
   #pragma unroll
       for (int kk = 0; kk < NKS; ++kk) offk[kk] = off_s[4 * kk + lk];
-      for (int b = wave; b < NB; b += 4) {
+      for (int b = wave; b < NB; b += NW) {
         const int c = b * 16 + lc;
         const int cs = min(c, NRC - 1);
         const int inf = info_s[cs];
@@ -322,9 +335,10 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         T bv[NKS];
   #pragma unroll
         for (int kk = 0; kk < NKS; ++kk) {
-          const T v = u_s[base + max(offk[kk], 0)];
-          bv[kk] = (valid && offk[kk] >= 0) ? v : T(0);
+          bv[kk] = u_s[(valid && offk[kk] >= 0) ? base + offk[kk] : ZSLOT];
         }
+        // every operand load of the block is issued before the first product
+        __builtin_amdgcn_sched_barrier(0);
         typename Mma<T>::acc acc[NMB];
   #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) acc[mb] = typename Mma<T>::acc{0, 0, 0, 0};
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
         while (mask) {
           const int bit = __ffsll((long long)mask) - 1;
           mask &= mask - 1;
-          if ((seen++ & 3) != wave) continue;
+          if ((seen++ % NW) != wave) continue;
           const int c = c0 + bit;
           const int q = info_s[c];
           const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
@@ -404,7 +418,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
     // multiple of P) and b = g/P (when g < n P); cells outside the domain hold zeros.
   #pragma unroll
     for (int it = 0; it < NO; ++it) {
-      const int i = tid + it * 256;
+      const int i = tid + it * NT;
       const int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
       if (i >= OX * OY * OZ || lx >= onx || ly >= ony || lz >= onz) continue;
       const int g3[3] = {ox0 + lx, oy0 + ly, oz0 + lz};
@@ -493,7 +507,7 @@ __global__ __launch_bounds__(256) void tile_kernel(StepArgs<T> a) {
 
 // Blocks per XCD of a persistent launch: as many as the kernel's occupancy keeps resident
 // on the XCD's compute units (at most one per tile).
-static int resident_per_xcd(const void* kern) {
+static int resident_per_xcd(const void* kern, int threads) {
   static std::mutex mu;
   static std::unordered_map<const void*, int> cache;
   std::lock_guard<std::mutex> lock(mu);
@@ -502,7 +516,7 @@ static int resident_per_xcd(const void* kern) {
   int dev = 0, ncu = 0, nb = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0) != hipSuccess || nb < 1)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, 0) != hipSuccess || nb < 1)
     return 64;  // a safe guess; not cached
   const int v = std::max(1, nb * ncu / 8);
   cache[kern] = v;
@@ -533,14 +547,15 @@ static StepArgs<T> make_args(const Ctx& c, int tx, int ty, int tz) {
 
 using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, double, int);
 
-template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, bool BF = false>
+template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, bool BF = false, int NW = 4>
 struct TileCfg {
   // 3-D: persistent launch, 8 x (blocks per XCD) blocks each walking its XCD's tiles, so
   // the large K_ref (LDS or bf16 fragments) is staged once per block; 2-D (K_ref in
   // registers): one block per tile, which balances better
   static fcw_status launch(void (*kern)(StepArgs<T>), Ctx& c, const StepArgs<T>& a, int nrhs) {
-    const int nbx = (DIM == 3) ? std::min(a.chunk, resident_per_xcd((const void*)kern)) : a.chunk;
-    kern<<<dim3(8 * nbx, nrhs, 1), 256, 0, c.stream>>>(a);
+    const int nbx =
+        (DIM == 3) ? std::min(a.chunk, resident_per_xcd((const void*)kern, 64 * NW)) : a.chunk;
+    kern<<<dim3(8 * nbx, nrhs, 1), 64 * NW, 0, c.stream>>>(a);
     FCW_HIP(hipGetLastError());
     return FCW_OK;
   }
@@ -571,10 +586,10 @@ struct TileCfg {
       if (st) return st;
     }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
-    if (mode == kModeStep) return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF>, c, a, nrhs);
+    if (mode == kModeStep) return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF, NW>, c, a, nrhs);
     if (mode == kModeApply)
-      return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF>, c, a, nrhs);
-    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos, false>, c, a, nrhs);
+      return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeApply, BF, NW>, c, a, nrhs);
+    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeLanczos, false, NW>, c, a, nrhs);
   }
   // the step only (alternative tile shapes offered to the autotuner)
   static fcw_status run_step(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
@@ -588,13 +603,14 @@ struct TileCfg {
       if (st) return st;
     }
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
-    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF>, c, a, nrhs);
+    return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF, NW>, c, a, nrhs);
   }
 };
 
 struct Cand {
   RunFn fn;
   int tile[3];
+  int nw;  // waves per block
 };
 
 // Candidate tile shapes per problem kind; entry 0 is the default and serves every mode.
@@ -604,10 +620,13 @@ static int candidates(const Ctx& c, Cand* out) {
   int n = 0;
 #define FCW_C0(D, PP, NC, TX, TY, TZ)                  \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run, {TX, TY, TZ}};
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run, {TX, TY, TZ}, 4};
 #define FCW_C(D, PP, NC, TX, TY, TZ)                   \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run_step, {TX, TY, TZ}};
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run_step, {TX, TY, TZ}, 4};
+#define FCW_CW(D, PP, NC, TX, TY, TZ, NW)              \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::run_step, {TX, TY, TZ}, NW};
   if constexpr (F64) {
     FCW_C0(2, 1, 1, 32, 16, 1) FCW_C(2, 1, 1, 16, 16, 1)
     FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1)
@@ -635,23 +654,28 @@ static int candidates(const Ctx& c, Cand* out) {
     FCW_C0(3, 4, 1, 4, 4, 2) FCW_C(3, 4, 1, 4, 2, 2)
     FCW_C0(3, 1, 3, 8, 4, 4)
     FCW_C0(3, 2, 3, 4, 4, 4) FCW_C(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
+    FCW_CW(3, 2, 3, 4, 4, 4, 8) FCW_CW(3, 2, 3, 8, 4, 4, 8)
   }
 #undef FCW_C0
 #undef FCW_C
+#undef FCW_CW
   return n;
 }
 
-constexpr int kMaxCand = 8;
+constexpr int kMaxCand = 10;
 
 // BF16 form: FP32 state, bf16 operands of the uncut contraction
 static int candidates_bf(const Ctx& c, Cand* out) {
   int n = 0;
 #define FCW_B0(D, PP, NC, TX, TY, TZ)                  \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run, {TX, TY, TZ}};
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run, {TX, TY, TZ}, 4};
 #define FCW_B(D, PP, NC, TX, TY, TZ)                   \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run_step, {TX, TY, TZ}};
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run_step, {TX, TY, TZ}, 4};
+#define FCW_BW(D, PP, NC, TX, TY, TZ, NW)              \
+  if (c.dim == D && c.p == PP && c.ncomp == NC)        \
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true, NW>::run_step, {TX, TY, TZ}, NW};
   FCW_B0(2, 1, 1, 32, 32, 1)
   FCW_B0(2, 2, 1, 16, 16, 1) FCW_B(2, 2, 1, 16, 8, 1)
   FCW_B0(2, 3, 1, 16, 16, 1) FCW_B(2, 3, 1, 16, 8, 1)
@@ -664,8 +688,10 @@ static int candidates_bf(const Ctx& c, Cand* out) {
   FCW_B0(3, 4, 1, 4, 4, 2) FCW_B(3, 4, 1, 4, 2, 2)
   FCW_B0(3, 1, 3, 8, 4, 4)
   FCW_B0(3, 2, 3, 4, 4, 2) FCW_B(3, 2, 3, 4, 4, 4) FCW_B(3, 2, 3, 4, 2, 2)
+  FCW_BW(3, 2, 3, 4, 4, 4, 8) FCW_BW(3, 2, 3, 8, 4, 4, 8)
 #undef FCW_B0
 #undef FCW_B
+#undef FCW_BW
   return n;
 }
 
@@ -698,6 +724,7 @@ struct StepCand {
   Run2d f2d = nullptr;
   RunFn fgen = nullptr;
   int tile[3] = {0, 0, 0};
+  int nw = 4;
 };
 
 static int step_candidates(const Ctx& c, int i, StepCand* out) {
@@ -713,6 +740,7 @@ static int step_candidates(const Ctx& c, int i, StepCand* out) {
     } else if (i >= n2 && i < n2 + ng) {
       out->fgen = cs[i - n2].fn;
       for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
+      out->nw = cs[i - n2].nw;
     }
   }
   return n2 + ng;
@@ -729,10 +757,10 @@ int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name) {
   } else if (name) {
     // the kernel's name as a profiler prints it (single-problem launches)
     char b[128];
-    std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d, %s>",
+    std::snprintf(b, sizeof b, "fcw::tile_kernel<%s, %d, %d, %d, %d, %d, %d, %d, %s, %d>",
                   c.precision == FCW_FP64 ? "double" : "float", c.dim, c.p, c.ncomp, sc.tile[0],
                   sc.tile[1], sc.tile[2], (int)kModeStep,
-                  c.precision == FCW_BF16 ? "true" : "false");
+                  c.precision == FCW_BF16 ? "true" : "false", sc.nw);
     *name = b;
   }
   return n;

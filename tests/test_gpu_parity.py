@@ -315,6 +315,26 @@ def test_every_tile_configuration(c2_small, precision, tol):
     s.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", BF16_TOL)])
+def test_elastic_3d_every_tile_configuration(precision, tol):
+    # every 3-D elastic tile shape and block size the autotuner may choose, on a 9x6x5 p=2
+    # grid with one ball (several tiles per axis, ragged edge tiles, cut cells)
+    cfg = workloads._base(3, (9, 6, 5), 2, [(0.45, 0.3, 0.25)], [0.15], ncomp=3, nsteps=60,
+                          hi=(0.9, 0.6, 0.5))
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    ref = timestep.cdm(disc, dt, 60, sources=cfg["sources"])["u"]
+    s = _solver(cfg, precision)
+    confs = s.tile_configs()
+    assert len(confs) >= 4
+    for i, conf in enumerate(confs):
+        s.select_tile(i)
+        got = _run_gpu(s, cfg, dt, 60, [60])
+        assert rel_l2(got[60], ref) <= tol, (i, conf)
+    s.close()
+
+
 def test_error_paths():
     from paper_2501_19013_amd import fcw
     cfg = workloads.config("c1")
