@@ -46,10 +46,10 @@ struct CutShape {
   static constexpr int UEP = (NL * DPE + 63) / 64 * 64;
   // Pipelined form, for matrices of 1024 to 4096 dwords: a wave walks CPW cells; the
   // next cell's packed matrix travels global -> registers while the current one is
-  // reduced from LDS.  Other sizes: packed triangle global -> LDS directly, one cell
-  // per wave.
+  // reduced from LDS (node values kept there in FP64).  Other sizes: packed triangle
+  // global -> LDS directly, one cell per wave.
   static constexpr bool PIPE = KDP / 64 <= 64 && KD >= 1024;
-  static constexpr int STRIDE = KDP + UEP;  // LDS dwords per wave
+  static constexpr int STRIDE = KDP + (PIPE ? (2 * NL + 63) / 64 * 64 : UEP);  // LDS dwords per wave
   static constexpr int CPW = PIPE ? 8 : 1;                        // cells per wave
   static constexpr int WPB_ = 64 * 1024 / (STRIDE * 4);
   static constexpr int WPB = PIPE ? 1 : (WPB_ < 1 ? 1 : (WPB_ > 4 ? 4 : WPB_));  // waves per block
@@ -83,20 +83,39 @@ __device__ static inline void cell_dofs(const Pr& pr, int cell, int lane, int64_
 }
 
 // y = K u for one cell from its packed upper triangle K and node values ue in LDS; lane
-// i accumulates rows i, i + 64, ... in FP64 over the columns in order.
-template <typename T, int NL, int NR>
-__device__ static inline void cell_rows(const T* K, const T* ue, int lane, double y[NR]) {
+// i accumulates rows i, i + 64, ... in FP64 over the columns in order.  The entry (i, jj)
+// sits at jj (jj + 1) / 2 + i when i <= jj and at i (i + 1) / 2 + jj otherwise; the column
+// loop is split at 63 so that every row group for which all lanes take the same form
+// skips the per-lane choice.
+template <typename T, typename U, int NL, int NR>
+__device__ static inline void cell_rows(const T* K, const U* ue, int lane, double y[NR]) {
+  int row[NR], tri[NR];
 #pragma unroll
-  for (int rr = 0; rr < NR; ++rr) y[rr] = 0.0;
+  for (int rr = 0; rr < NR; ++rr) {
+    y[rr] = 0.0;
+    row[rr] = min(lane + 64 * rr, NL - 1);
+    tri[rr] = row[rr] * (row[rr] + 1) / 2;
+  }
+  constexpr int JS = NL < 63 ? NL : 63;
+  // columns 0 .. 62: rows of group 0 take either form, rows of later groups (>= 64) the
+  // lower one
 #pragma unroll 9
-  for (int jj = 0; jj < NL; ++jj) {
+  for (int jj = 0; jj < JS; ++jj) {
     const double uj = (double)ue[jj];
+    const int tj = jj * (jj + 1) / 2;
+    y[0] += (double)K[(row[0] <= jj) ? tj + row[0] : tri[0] + jj] * uj;
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-      const int i = min(lane + 64 * rr, NL - 1);
-      const int idx = (i <= jj) ? jj * (jj + 1) / 2 + i : i * (i + 1) / 2 + jj;
-      y[rr] += (double)K[idx] * uj;
-    }
+    for (int rr = 1; rr < NR; ++rr) y[rr] += (double)K[tri[rr] + jj] * uj;
+  }
+  // columns 63 .. NL-1: rows of group 0 (<= 63) the upper form, later groups either
+#pragma unroll 9
+  for (int jj = JS; jj < NL; ++jj) {
+    const double uj = (double)ue[jj];
+    const int tj = jj * (jj + 1) / 2;
+    y[0] += (double)K[tj + row[0]] * uj;
+#pragma unroll
+    for (int rr = 1; rr < NR; ++rr)
+      y[rr] += (double)K[(row[rr] <= jj) ? tj + row[rr] : tri[rr] + jj] * uj;
   }
 }
 
@@ -147,6 +166,7 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
 
   if constexpr (S::PIPE) {
     constexpr int KW = S::KDP / 64;
+    double* ued = (double*)(kw + S::KDP);
     uint32_t kr[KW];
     T u0[NR];
     int64_t nodes[NR];
@@ -178,7 +198,7 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
       for (int w = 0; w < KW; ++w) kw[w * 64 + lane] = kr[w];
 #pragma unroll
       for (int rr = 0; rr < NR; ++rr)
-        if (lane + 64 * rr < NL) ue[lane + 64 * rr] = u0[rr];
+        if (lane + 64 * rr < NL) ued[lane + 64 * rr] = (double)u0[rr];
       // the previous cell's rhs-0 products leave before the next loads are issued, so
       // the wait at the top of the next pass finds them done
       if (qprev >= 0) {
@@ -192,7 +212,7 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
       // LDS accesses of one wave complete in order; the barrier keeps the compiler's order
       __builtin_amdgcn_wave_barrier();
       if (on) {
-        cell_rows<T, NL, NR>(K, ue, lane, yprev);
+        cell_rows<T, double, NL, NR>(K, ued, lane, yprev);
         qprev = q;
         // further right-hand sides: gathered and written here (not overlapped)
         for (int r = 1; r < pr.nrhs; ++r) {
@@ -200,10 +220,10 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
           const T* u = uin + (int64_t)r * pr.ndof;
 #pragma unroll
           for (int rr = 0; rr < NR; ++rr)
-            if (lane + 64 * rr < NL) ue[lane + 64 * rr] = u[nd[rr]];
+            if (lane + 64 * rr < NL) ued[lane + 64 * rr] = (double)u[nd[rr]];
           __builtin_amdgcn_wave_barrier();
           double yr[NR];
-          cell_rows<T, NL, NR>(K, ue, lane, yr);
+          cell_rows<T, double, NL, NR>(K, ued, lane, yr);
           T* yo = pr.y + ((int64_t)r * pr.ncand + q) * NL;
 #pragma unroll
           for (int rr = 0; rr < NR; ++rr)
@@ -241,7 +261,7 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
         if (lane + 64 * rr < NL) ue[lane + 64 * rr] = (r == 0) ? u0[rr] : u[nodes[rr]];
       __builtin_amdgcn_wave_barrier();
       double y[NR];
-      cell_rows<T, NL, NR>(K, ue, lane, y);
+      cell_rows<T, T, NL, NR>(K, ue, lane, y);
       T* yo = pr.y + ((int64_t)r * pr.ncand + q) * NL;
 #pragma unroll
       for (int rr = 0; rr < NR; ++rr)
