@@ -136,6 +136,29 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
   // ---- the block's tiles: a stretch of the tiles of its XCD (blocks b, b + 8, ... run
   // on one XCD), so neighbouring tiles share halo rows in that XCD's L2 ----
   const int nbx = (int)(gridDim.x / 8);
+  // cell infos of the region of a tile (class or cut-cell index), one per thread and it
+  auto load_info = [&](int tile, int out[NCI]) {
+    const int rx = (tile % a.ntile[0]) * TX - 1;
+    const int ry = (DIM >= 2) ? ((tile / a.ntile[0]) % a.ntile[1]) * TY - 1 : 0;
+    const int rz = (DIM == 3) ? (tile / (a.ntile[0] * a.ntile[1])) * TZ - 1 : 0;
+  #pragma unroll
+    for (int it = 0; it < NCI; ++it) {
+      const int c = tid + it * NT;
+      const int gx = rx + c % RCX, gy = ry + (c / RCX) % RCY, gz = rz + c / (RCX * RCY);
+      const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
+                      gz < a.n[2];
+      const int64_t cell = in ? gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz) : 0;
+      const int v = a.info[cell];
+      out[it] = in ? v : kInfoOut;
+    }
+  };
+  // the next tile's infos are loaded one tile ahead, so its cut-cell copies can start
+  // with its first loads
+  int inf_next[NCI];
+  {
+    const int t0 = (int)(blockIdx.x % 8) * a.chunk + (int)(blockIdx.x / 8);
+    if ((int)(blockIdx.x / 8) < a.chunk && t0 < a.ntiles) load_info(t0, inf_next);
+  }
   for (int tk = (int)(blockIdx.x / 8); tk < a.chunk; tk += nbx) {
     const int tile = (int)(blockIdx.x % 8) * a.chunk + tk;
     if (tile >= a.ntiles) break;
@@ -159,15 +182,27 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
     // ---- issue every global load of the tile at once (all stay in flight) ----
     int inf_r[NCI];
   #pragma unroll
-    for (int it = 0; it < NCI; ++it) {
-      const int c = tid + it * NT;
-      const int lx = c % RCX, ly = (c / RCX) % RCY, lz = c / (RCX * RCY);
-      const int gx = rcx0 + lx, gy = rcy0 + ly, gz = rcz0 + lz;
-      const bool in = c < NRC && gx >= 0 && gx < a.n[0] && gy >= 0 && gy < a.n[1] && gz >= 0 &&
-                      gz < a.n[2];
-      const int64_t cell = in ? gx + (int64_t)a.n[0] * (gy + (int64_t)a.n[1] * gz) : 0;
-      const int v = a.info[cell];
-      inf_r[it] = in ? v : kInfoOut;
+    for (int it = 0; it < NCI; ++it) inf_r[it] = inf_next[it];
+    // cut cells: their products (cut-cell kernel) go global -> LDS by DMA first, each wave
+    // copying the cut cells among its own lanes' cells
+    if (MODE != kModeLanczos) {
+      constexpr int DPE = (int)(sizeof(T) / 4);
+      constexpr int RDW = NL * DPE;  // dwords of one cell's products
+  #pragma unroll
+      for (int it = 0; it < NCI; ++it) {
+        unsigned long long mask = __ballot(inf_r[it] >= 0);
+        while (mask) {
+          const int bit = __ffsll((long long)mask) - 1;
+          mask &= mask - 1;
+          const int c = it * NT + wave * 64 + bit;
+          const int q = __builtin_amdgcn_readlane(inf_r[it], bit);  // cut-cell index
+          const uint32_t* src = (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + q) * NL);
+          uint32_t* dst = (uint32_t*)(y_s + c * NL);
+  #pragma unroll
+          for (int ch = 0; ch < (RDW + 63) / 64; ++ch)
+            if (ch * 64 + lane < RDW) load_dword_to_lds(src + ch * 64 + lane, dst + ch * 64);
+        }
+      }
     }
     // node values of the region; entries outside the grid belong only to cells outside
     // the grid (never read), so their address is clamped to node 0 of the component
@@ -208,6 +243,8 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
       }
     }
 
+    if (tk + nbx < a.chunk && tile + nbx < a.ntiles) load_info(tile + nbx, inf_next);
+
     // ---- stage cell info, node values, K_ref, local offsets in LDS ----
   #pragma unroll
     for (int it = 0; it < NCI; ++it) {
@@ -242,30 +279,6 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
     if (DIRECT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
-    // ---- cut cells: their products (cut-cell kernel) go global -> LDS by DMA, one wave
-    // per cell, all copies in flight while the matrix cores work below ----
-    if (MODE != kModeLanczos) {
-      constexpr int DPE = (int)(sizeof(T) / 4);
-      constexpr int RDW = NL * DPE;  // dwords of one cell's products
-      int seen = 0;
-      for (int c0 = 0; c0 < NRC; c0 += 64) {
-        const int cc = c0 + lane;
-        const bool isc = (cc < NRC) && (info_s[min(cc, NRC - 1)] >= 0);
-        unsigned long long mask = __ballot(isc);
-        while (mask) {
-          const int bit = __ffsll((long long)mask) - 1;
-          mask &= mask - 1;
-          if ((seen++ % NW) != wave) continue;
-          const int c = c0 + bit;
-          const uint32_t* src =
-              (const uint32_t*)(a.ycut + ((int64_t)rhs * a.ncand + info_s[c]) * NL);
-          uint32_t* dst = (uint32_t*)(y_s + c * NL);
-  #pragma unroll
-          for (int ch = 0; ch < (RDW + 63) / 64; ++ch)
-            if (ch * 64 + lane < RDW) load_dword_to_lds(src + ch * 64 + lane, dst + ch * 64);
-        }
-      }
-    }
     // ---- uncut cells: batched K_ref contraction on the matrix cores ----
     // Every non-cut cell of the region gets its row of y_s here: uncut cells their
     // product, cells outside the domain zeros (their B operand is masked to zero).
