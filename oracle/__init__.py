@@ -18,6 +18,8 @@ cites the passage of the paper it follows (section / equation / algorithm):
 * ``problem``    - assembly of the whole discrete problem and the point load.
 * ``timestep``   - critical time step, central differences with the Newmark start-up,
                    discrete energy (Sec. 2.3, eq. cdm, Alg. newmark).
+* ``imex``       - the Newmark IMEX scheme: explicit/implicit DOF split, consistent
+                   cut-DOF mass, trapezoidal Newmark on the cut DOFs (Sec. 2.5, Alg. imex).
 
 Readings of the paper where it is silent are stated in the functions that take them.
 Parity status: every function here is pinned by tests under ``tests/test_oracle_*``;

@@ -1,0 +1,119 @@
+"""Newmark IMEX time integration (paper Sec. 2.5, Alg. imex).
+
+The DOFs split by the support of their basis functions: a DOF whose node lies only in
+uncut cells is explicit ("d"); a DOF whose node lies in at least one cut cell is
+implicit ("c").  With GLL nodes and nodal quadrature the mass of an uncut cell is
+diagonal, so M = diag(M^dd, M^cc) with M^dd diagonal and M^cc the consistent mass of the
+cut DOFs: the original tree-integrated cut-cell masses M^o_e (no stabilisation) plus
+the GLL diagonals of the uncut cells that touch cut DOFs.  The explicit DOFs take the
+central difference step, the implicit ones the trapezoidal Newmark step (beta = 1/4,
+gamma = 1/2) with S = M^cc + beta dt^2 K^cc, whose right-hand side uses the explicit
+DOFs' new values as their predictors.
+
+Readings (where the algorithm as printed is silent):
+* the explicit part's first step uses the Newmark start-up with beta = 0 (as the
+  explicit solver does), since Alg. imex needs Psi_{-1};
+* the initial acceleration of the implicit DOFs solves M^cc a_0 = F_0^c - K^c Psi_0
+  (the printed line writes F_k for F_0);
+* F_{k+1} in the implicit step is the load at t_{k+1}.
+
+Test infrastructure only (see ``oracle/__init__``).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .problem import assembled_K, load_vector, ricker
+
+
+def partition(disc):
+    """(c, d): sorted global DOF indices of the implicit DOFs (nodes of cut cells, every
+    component) and of the remaining active DOFs."""
+    prob = disc.prob
+    nn = prob.nnodes
+    cut_nodes = np.zeros(nn, dtype=bool)
+    if len(disc.cut_cells):
+        cut_nodes[disc.cell_nodes[disc.cut_cells].ravel()] = True
+    active = disc.mass > 0
+    c_nodes = np.flatnonzero(cut_nodes & active)
+    d_nodes = np.flatnonzero(active & ~cut_nodes)
+    c = np.concatenate([c_nodes + k * nn for k in range(prob.ncomp)])
+    d = np.concatenate([d_nodes + k * nn for k in range(prob.ncomp)])
+    return c, d
+
+
+def mass_matrices(disc, c, d):
+    """(m_dd, M_cc): the diagonal of M^dd (GLL diagonals of the uncut cells) and the
+    consistent M^cc (cut-cell M^o_e blocks, one per component, plus the uncut-cell GLL
+    diagonals on cut DOFs), both in the order of c and d."""
+    prob = disc.prob
+    nn, ns = prob.nnodes, prob.n_s
+    diag = np.zeros(nn)
+    unc = disc.uncut_cells
+    if len(unc):
+        np.add.at(diag, disc.cell_nodes[unc], np.broadcast_to(disc.lumped_ref, (len(unc), ns)))
+    rows, cols, vals = [], [], []
+    for e, cell in enumerate(disc.cut_cells):
+        nodes = disc.cell_nodes[cell]
+        for k in range(prob.ncomp):
+            g = nodes + k * nn
+            rows.append(np.repeat(g, ns))
+            cols.append(np.tile(g, ns))
+            vals.append(disc.Mo_cut[e].ravel())
+    full_diag = np.tile(diag, prob.ncomp)
+    ndof = prob.ndof
+    M = sp.coo_matrix((np.concatenate(vals + [full_diag]),
+                       (np.concatenate(rows + [np.arange(ndof)]),
+                        np.concatenate(cols + [np.arange(ndof)]))), shape=(ndof, ndof)).tocsr()
+    return full_diag[d], M[c][:, c]
+
+
+def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None, u0=None):
+    """Run ``nsteps`` steps of Alg. imex from u0 (default 0) at rest.  ``split``
+    overrides the partition (c, d) (a test reduces the scheme to one of its two parts
+    with it).  Returns the final u (all DOFs), the implicit DOFs' velocity and
+    acceleration, and the split."""
+    prob = disc.prob
+    c, d = partition(disc) if split is None else split
+    m_dd, Mcc = mass_matrices(disc, c, d)
+    K = assembled_K(disc)
+    Kc = K[c]
+    loads = [(load_vector(disc, s), float(s.get("f0", 10.0))) for s in sources]
+
+    def force(k):
+        F = np.zeros(prob.ndof)
+        for b, f0 in loads:
+            F += ricker(t0 + k * dt, f0) * b
+        return F
+
+    u = np.zeros(prob.ndof) if u0 is None else np.array(u0, dtype=np.float64)
+    v_c = np.zeros(len(c))
+    a_c = np.zeros(len(c))
+    if len(c):
+        S = (Mcc + beta * dt * dt * K[c][:, c]).toarray()
+        S_f = sla.cho_factor(0.5 * (S + S.T), lower=True)
+        Mc = Mcc.toarray()
+        a_c = sla.cho_solve(sla.cho_factor(0.5 * (Mc + Mc.T), lower=True), force(0)[c] - Kc @ u)
+    inv_dd = np.where(m_dd > 0, 1.0 / np.where(m_dd > 0, m_dd, 1.0), 0.0)
+    u_prev_d = None
+    for k in range(nsteps):
+        # explicit step on d (central differences; Newmark beta = 0 start-up at k = 0)
+        acc_d = inv_dd * (force(k)[d] - (K[d] @ u))
+        if k == 0:
+            new_d = u[d] + 0.5 * dt * dt * acc_d
+        else:
+            new_d = 2.0 * u[d] - u_prev_d + dt * dt * acc_d
+        u_prev_d = u[d].copy()
+        # implicit step on c (trapezoidal Newmark), predictors of d = their new values
+        pred = u.copy()
+        pred[d] = new_d
+        if len(c):
+            pred[c] = u[c] + dt * v_c + (0.5 - beta) * dt * dt * a_c
+            v_pred = v_c + (1.0 - gamma) * dt * a_c
+            a_c = sla.cho_solve(S_f, force(k + 1)[c] - Kc @ pred)
+            v_c = v_pred + gamma * dt * a_c
+            pred[c] = pred[c] + beta * dt * dt * a_c
+        u = pred
+    return dict(u=u, v_c=v_c, a_c=a_c, c=c, d=d)

@@ -1,0 +1,83 @@
+"""Pins of the IMEX oracle (Sec. 2.5, Alg. imex) against what the mathematics fixes:
+
+* no cut cell: the scheme is central differences (eq. cdm with the Newmark start-up);
+* every active DOF implicit and no load: the trapezoidal rule conserves the energy
+  1/2 v^T M v + 1/2 u^T K u exactly;
+* mixed split: second-order convergence in dt;
+* stability set by the explicit part: without eigenvalue stabilisation the lumped
+  explicit step diverges at the step size of the uncut cells, IMEX does not.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import imex as ox
+from oracle import problem, timestep
+
+
+def _disc(centers, radii, n=6, p=2, eps=1e-4, alpha=1e-12):
+    cfg = workloads._base(2, (n, n), p, centers, radii, eps=eps, alpha=alpha)
+    return cfg, problem.build(problem.Problem.from_config(cfg))
+
+
+def test_no_cut_cell_is_central_differences():
+    cfg, disc = _disc(np.zeros((0, 2)), np.zeros(0))
+    assert len(disc.cut_cells) == 0
+    dt = 0.9 * timestep.critical_dt(disc)
+    src = [dict(x=(0.31, 0.42), f0=10.0, amp=1.0)]
+    got = ox.imex(disc, dt, 40, sources=src)
+    ref = timestep.cdm(disc, dt, 40, sources=src)["u"]
+    assert len(got["c"]) == 0
+    assert np.linalg.norm(got["u"] - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_all_implicit_conserves_energy():
+    cfg, disc = _disc([(0.5, 0.5)], [0.21])
+    c, d = ox.partition(disc)
+    allc = np.sort(np.concatenate([c, d]))
+    split = (allc, np.zeros(0, dtype=np.int64))
+    m_dd, M = ox.mass_matrices(disc, *split)
+    K = problem.assembled_K(disc)[allc][:, allc]
+    rng = np.random.default_rng(7)
+    u0 = np.zeros(disc.prob.ndof)
+    u0[allc] = rng.standard_normal(len(allc))
+    dt = 0.05  # far above any explicit limit: the trapezoidal rule is unconditionally stable
+    e0 = 0.5 * u0[allc] @ (K @ u0[allc])
+    for n in (10, 37):
+        r = ox.imex(disc, dt, n, split=split, u0=u0)
+        uc = r["u"][allc]
+        e = 0.5 * r["v_c"] @ (M @ r["v_c"]) + 0.5 * uc @ (K @ uc)
+        assert abs(e - e0) <= 1e-11 * e0, (n, e, e0)
+
+
+def test_mixed_split_second_order():
+    cfg, disc = _disc([(0.47, 0.52)], [0.23])
+    c, d = ox.partition(disc)
+    assert len(c) > 0 and len(d) > 0
+    src = [dict(x=(0.1, 0.1), f0=6.0, amp=1.0)]
+    dt0 = 0.5 * timestep.critical_dt(disc)
+    T = 64 * dt0
+    sol = {}
+    for m in (1, 2, 4, 16):
+        dt = dt0 / m
+        sol[m] = ox.imex(disc, dt, int(round(T / dt)), sources=src)["u"]
+    e1 = np.linalg.norm(sol[1] - sol[16])
+    e2 = np.linalg.norm(sol[2] - sol[16])
+    e4 = np.linalg.norm(sol[4] - sol[16])
+    assert e1 > 0 and 3.0 < e1 / e2 < 5.5 and 3.0 < e2 / e4 < 5.5, (e1, e2, e4)
+
+
+def test_stability_set_by_explicit_part():
+    # eps = 0: no eigenvalue stabilisation, so a tiny cut fragment makes the lumped
+    # explicit step unstable at the step size that the uncut cells allow
+    centers, radii = [(0.5, 0.5)], [0.4949]
+    cfg, disc = _disc(centers, radii, n=6, p=2, eps=0.0)
+    cfg_u, disc_u = _disc(np.zeros((0, 2)), np.zeros(0), n=6, p=2)
+    dt = 0.9 * timestep.critical_dt(disc_u)
+    assert dt > timestep.critical_dt(disc)
+    src = [dict(x=(0.05, 0.05), f0=10.0, amp=1.0)]
+    n = 400
+    r = ox.imex(disc, dt, n, sources=src)
+    e = timestep.cdm(disc, dt, n, sources=src)["u"]
+    assert np.all(np.isfinite(r["u"])) and np.abs(r["u"]).max() < 1e3
+    assert not np.all(np.isfinite(e)) or np.abs(e).max() > 1e6
