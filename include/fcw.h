@@ -181,9 +181,35 @@ fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
 fcw_status fcw_kernel_times(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, double* main_us,
                             double* cut_us);
 
-/* Semi-explicit (IMEX) step of Alg. imex.  Not built yet: FCW_E_UNSUPPORTED. */
-fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* v_c, void* a_c,
-                         const fcw_source* src, double t0, double dt, int32_t nsteps);
+/* Largest implicit set of the IMEX step (its matrices are held dense). */
+#define FCW_IMEX_MAX_NC 16384
+
+/* Set up the semi-explicit (IMEX) scheme of Sec. 2.5 (Alg. imex) for step size dt:
+ * the implicit DOFs are those of the nodes of the cut cells (every component), the
+ * rest of the active DOFs are explicit.  Assembles M^cc (the consistent cut-cell masses
+ * M^o_e without stabilisation plus the GLL diagonals of the uncut cells on implicit
+ * DOFs) and S = M^cc + dt^2/4 K^cc, dense, and factors both by Cholesky on the device
+ * (FP64).  *n_c receives the number of implicit DOFs, whose global indices
+ * FCW_ARR_IMEX_DOFS exports (ascending: component-major, then node).
+ * FP64 contexts only (FCW_E_UNSUPPORTED otherwise, and when n_c > FCW_IMEX_MAX_NC);
+ * FCW_E_NOCONV if a matrix is not positive definite.  Requires the stabilised state.
+ * fcw_step_imex calls it itself when dt changes. */
+fcw_status fcw_imex_prepare(fcw_ctx* ctx, double dt, int64_t* n_c);
+
+/* nsteps semi-explicit steps (Alg. imex, beta = 1/4, gamma = 1/2): central differences on
+ * the explicit DOFs (the step of fcw_step_explicit, in increment form), the trapezoidal
+ * Newmark rule on the implicit DOFs with S of fcw_imex_prepare.
+ *   u, d  device double [nrhs][ndof]: state and increment d = u_k - u_{k-1} (the
+ *         increment is used on the explicit DOFs);
+ *   v_c, a_c  device double [nrhs][n_c]: velocity and acceleration of the implicit DOFs
+ *         in the FCW_ARR_IMEX_DOFS order (may be NULL when n_c = 0);
+ *   src, t0: as for fcw_step_explicit; the load of the implicit step is taken at t_{k+1};
+ *   start = 1: the call starts from rest (d = 0, v_c = 0): the explicit DOFs take the
+ *         Newmark start-up (beta = 0) and a_c is computed from M^cc a_0 = F_0 - (K u_0).
+ * FP64 contexts only.  Arrays are caller-owned; the call queues on the context's stream. */
+fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* d, void* v_c, void* a_c,
+                         const fcw_source* src, double t0, double dt, int32_t nsteps,
+                         int32_t start);
 
 /* Stiffness action r = K u (eq. semi, element by element, same kernels as the step):
  * u, r device [nrhs][ndof] in the state precision. */
@@ -203,7 +229,8 @@ enum {
   FCW_ARR_M_CUT = 4,      /* double [n_cut*n_s*n_s] cut-cell scalar consistent mass */
   FCW_ARR_LUMPED_CUT = 5, /* double [n_cut*n_s] stabilised lumped diagonal */
   FCW_ARR_MASS = 6,       /* double [nnodes] assembled lumped mass */
-  FCW_ARR_EVS_MARGIN = 7  /* double [n_cut] */
+  FCW_ARR_EVS_MARGIN = 7, /* double [n_cut] */
+  FCW_ARR_IMEX_DOFS = 8   /* int64 [n_c] implicit DOFs of the prepared IMEX scheme */
 };
 fcw_status fcw_export(const fcw_ctx* ctx, int32_t which, void* dst, int64_t capacity,
                       int64_t* count);

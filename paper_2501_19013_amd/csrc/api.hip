@@ -51,6 +51,7 @@ static void free_all(Ctx& c) {
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
   dfree(c.d_invw); dfree(c.d_mflag); dfree(c.d_kref_bf);
   dfree(c.d_src);
+  imex_free(c);
   dfree(c.d_wl);
   if (c.h_wl) (void)hipHostFree(c.h_wl);
   c.h_wl = nullptr;
@@ -603,13 +604,46 @@ fcw_status fcw_kernel_times(fcw_ctx* c, int32_t nrhs, int32_t nsteps, double* ma
   return st;
 }
 
-fcw_status fcw_step_imex(fcw_ctx* c, int32_t, void*, void*, void*, const fcw_source*, double,
-                         double, int32_t) {
+fcw_status fcw_imex_prepare(fcw_ctx* c, double dt, int64_t* n_c) {
   g_err.clear();
   fcw_status st = check_ctx(c, 2);
   if (st) return st;
-  set_error("the IMEX step is not built in this library");
-  return FCW_E_UNSUPPORTED;
+  if (c->precision != FCW_FP64) {
+    set_error("the IMEX scheme runs on FP64 contexts only");
+    return FCW_E_UNSUPPORTED;
+  }
+  if (!(dt > 0.0) || !n_c) {
+    set_error("need dt > 0 and non-null n_c");
+    return FCW_E_ARG;
+  }
+  if ((st = imex_prepare(*c, dt))) return st;
+  *n_c = c->imex_nc;
+  return FCW_OK;
+}
+
+fcw_status fcw_step_imex(fcw_ctx* c, int32_t nrhs, void* u, void* d, void* v_c, void* a_c,
+                         const fcw_source* src, double t0, double dt, int32_t nsteps,
+                         int32_t start) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (c->precision != FCW_FP64) {
+    set_error("the IMEX scheme runs on FP64 contexts only");
+    return FCW_E_UNSUPPORTED;
+  }
+  if ((st = prepare_call(c, nrhs, u, d, src, dt, nsteps))) return st;
+  if ((st = imex_prepare(*c, dt))) return st;
+  if (c->imex_nc > 0 && (!v_c || !a_c)) {
+    set_error("v_c and a_c are needed (%lld implicit DOFs)", (long long)c->imex_nc);
+    return FCW_E_ARG;
+  }
+  if (nsteps == 0) return FCW_OK;
+  SourceDev* saved = c->d_src;
+  if (!src) c->d_src = nullptr;
+  st = imex_run(*c, nrhs, (double*)u, (double*)d, (double*)v_c, (double*)a_c, t0, dt, nsteps,
+                start);
+  c->d_src = saved;
+  return st;
 }
 
 fcw_status fcw_apply_stiffness(fcw_ctx* c, int32_t nrhs, const void* u, void* r) {
@@ -661,6 +695,7 @@ fcw_status fcw_export(const fcw_ctx* c, int32_t which, void* dst, int64_t capaci
     case FCW_ARR_LUMPED_CUT: srcp = c->d_lumped; n = ncand * c->n_s; break;
     case FCW_ARR_MASS: srcp = c->d_mass; n = c->state >= 2 ? c->nnodes : 0; break;
     case FCW_ARR_EVS_MARGIN: srcp = c->d_margin; n = ncand; break;
+    case FCW_ARR_IMEX_DOFS: srcp = c->d_imex_dofs; n = c->imex_nc > 0 ? c->imex_nc : 0; break;
     default: set_error("unknown array %d", which); return FCW_E_ARG;
   }
   if (count) *count = n;

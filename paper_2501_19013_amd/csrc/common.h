@@ -111,6 +111,17 @@ struct Ctx {
   void* graph_wl = nullptr;
   int64_t footprint = 0;
   bool skip_cut = false;  // step calls launch the main kernel only (kernel timing)
+  // IMEX (implicit DOFs = nodes of cut cells): Cholesky factors of S = M^cc + beta dt^2
+  // K^cc and of M^cc, each with its transpose, for the step size imex_dt
+  int64_t imex_nc = -1;            // implicit DOFs (-1: not prepared)
+  int64_t imex_ncn = 0;            // implicit nodes
+  double imex_dt = 0.0;
+  int64_t* d_imex_dofs = nullptr;  // [imex_nc] global DOF of each implicit DOF
+  double* d_imex_s = nullptr;      // [2][imex_nc^2] L of S (row-major, lower), L^T
+  double* d_imex_m = nullptr;      // [2][imex_nc^2] the same for M^cc
+  double* d_imex_work = nullptr;   // per-call work vectors
+  size_t imex_work_bytes = 0;
+  int32_t* d_imex_flag = nullptr;  // [1] non-positive pivot seen
 
   size_t state_bytes() const { return precision == FCW_FP64 ? 8 : 4; }
 };
@@ -142,6 +153,14 @@ fcw_status setup_reclassify(Ctx& c);
 fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda);
 fcw_status setup_mass_and_pack(Ctx& c);
 fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
+// exclusive scan of n int32 on the context's stream; the total goes to *total_host (syncs)
+fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
+                          int32_t* total_host);
+// imex.hip: semi-explicit scheme (implicit DOFs = nodes of cut cells)
+void imex_free(Ctx& c);
+fcw_status imex_prepare(Ctx& c, double dt);
+fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double* a_c, double t0,
+                    double dt, int nsteps, int start);
 // cutcell.hip: cut-cell products y = K_e u_e, once per cut cell and step
 fcw_status ensure_ycut(Ctx& c, int nrhs);
 size_t cutprob_size(int fp64);

@@ -261,8 +261,8 @@ __global__ void scan_add_kernel(int32_t* out, const int32_t* sums, int64_t n) {
 }
 
 // exclusive scan of n ints on the stream; writes the total to *total_host (syncs).
-static fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
-                                 int32_t* total_host) {
+fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
+                          int32_t* total_host) {
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   if (nb < 1) nb = 1;
   int32_t* sums = nullptr;

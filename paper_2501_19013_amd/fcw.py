@@ -19,12 +19,13 @@ FCW_OK, FCW_E_ARG, FCW_E_NOMEM, FCW_E_DEVICE, FCW_E_STATE, FCW_E_NOCONV, FCW_E_U
 FCW_FP64, FCW_FP32, FCW_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FCW_FP64, "fp32": FCW_FP32, "bf16": FCW_BF16}
 (ARR_CELL_CLASS, ARR_CUT_CELLS, ARR_K_REF, ARR_K_CUT, ARR_M_CUT, ARR_LUMPED_CUT, ARR_MASS,
- ARR_EVS_MARGIN) = range(8)
-_ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32}
+ ARR_EVS_MARGIN, ARR_IMEX_DOFS) = range(9)
+_ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32, ARR_IMEX_DOFS: np.int64}
 
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
-           "fcw_step_explicit", "fcw_step_imex", "fcw_apply_stiffness", "fcw_query",
+           "fcw_step_explicit", "fcw_imex_prepare", "fcw_step_imex", "fcw_apply_stiffness",
+           "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
            "fcw_export", "fcw_destroy", "fcw_last_error")
 
@@ -84,7 +85,8 @@ def load(path=LIB_PATH):
     lib.fcw_stabilize_cut_cells.argtypes = [vp, f64, f64]
     lib.fcw_critical_dt.argtypes = [vp, i32, f64, C.POINTER(f64)]
     lib.fcw_step_explicit.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
-    lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Source), f64, f64, i32]
+    lib.fcw_imex_prepare.argtypes = [vp, f64, C.POINTER(C.c_int64)]
+    lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_apply_stiffness.argtypes = [vp, i32, vp, vp]
     lib.fcw_query.argtypes = [vp, C.POINTER(Info)]
     lib.fcw_export.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(C.c_int64)]
@@ -181,10 +183,17 @@ def step_explicit(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):
                                     float(dt), int(nsteps), int(start)))
 
 
-def step_imex(ctx, nrhs, u, v_c, a_c, sources, t0, dt, nsteps):
+def imex_prepare(ctx, dt):
+    """Number of implicit DOFs of the IMEX scheme for step size dt (sets it up)."""
+    n = C.c_int64()
+    _check(load().fcw_imex_prepare(ctx, float(dt), C.byref(n)))
+    return n.value
+
+
+def step_imex(ctx, nrhs, u, d, v_c, a_c, sources, t0, dt, nsteps, start):
     srcs = _sources(sources)
-    _check(load().fcw_step_imex(ctx, int(nrhs), _ptr(u), _ptr(v_c), _ptr(a_c), srcs,
-                                float(t0), float(dt), int(nsteps)))
+    _check(load().fcw_step_imex(ctx, int(nrhs), _ptr(u), _ptr(d), _ptr(v_c), _ptr(a_c), srcs,
+                                float(t0), float(dt), int(nsteps), int(start)))
 
 
 def apply_stiffness(ctx, nrhs, u, r):

@@ -19,7 +19,7 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     names = declared_symbols()
     for required in ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
-                     "fcw_step_explicit", "fcw_step_imex"):
+                     "fcw_step_explicit", "fcw_imex_prepare", "fcw_step_imex"):
         assert required in names
 
 
@@ -44,4 +44,6 @@ def test_error_path_without_gpu():
     desc.dim = 4
     assert lib.fcw_assemble_cells(ctypes.byref(desc), ctypes.byref(ctx)) == fcw.FCW_E_ARG
     assert lib.fcw_stabilize_cut_cells(None, 1e-4, 1e-4) == fcw.FCW_E_ARG
-    assert lib.fcw_step_imex(None, 1, None, None, None, None, 0.0, 0.0, 1) == fcw.FCW_E_ARG
+    assert lib.fcw_step_imex(None, 1, None, None, None, None, None, 0.0, 0.0, 1, 0) == fcw.FCW_E_ARG
+    n = ctypes.c_int64()
+    assert lib.fcw_imex_prepare(None, 1e-3, ctypes.byref(n)) == fcw.FCW_E_ARG

@@ -1,0 +1,128 @@
+"""Parity of the semi-explicit (IMEX) step (Sec. 2.5, Alg. imex) with the FP64 oracle.
+
+The implicit DOF set must equal the oracle's exactly (an index set).  The states after
+the steps agree to a tolerance set by the conditioning of S = M^cc + dt^2/4 K^cc:
+
+* with alpha = 1e-4 in the voids, cond(S) is about 3e5 on the C1 geometry and the
+  oracle's own result moves by 1e-14 when its cut-cell matrices move by 1e-14, so the
+  device (dense Cholesky in another order, its own tree quadrature) must agree to 1e-10;
+* with the paper's alpha = 1e-12, cut-cell fragments of almost no material make
+  cond(S) about 6e12: a relative change of 1e-15 in the cut-cell matrices (rounding of
+  the quadrature sums) moves the oracle's result by 6e-7, so the bar there is 1e-5.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import imex as ox
+from oracle import problem, timestep
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10       # alpha = 1e-4
+TOL_ILL = 1e-5    # alpha = 1e-12
+
+
+def _run(cfg, dt, chunks, sources):
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    s = Solver(cfg, precision="fp64")
+    nc = fcw.imex_prepare(s.ctx, dt)
+    dofs = fcw.export(s.ctx, fcw.ARR_IMEX_DOFS)
+    nrhs = len(sources)
+    u, d = s.zeros(nrhs), s.zeros(nrhs)
+    v = torch.zeros(nrhs, max(nc, 1), dtype=torch.float64, device="cuda")
+    a = torch.zeros_like(v)
+    k = 0
+    for n in chunks:
+        fcw.step_imex(s.ctx, nrhs, u, d, v, a, sources, k * dt, dt, n, int(k == 0))
+        k += n
+    torch.cuda.synchronize()
+    out = dict(u=u.double().cpu().numpy(), v=v.cpu().numpy()[:, :nc], a=a.cpu().numpy()[:, :nc],
+               dofs=dofs, nc=nc)
+    s.close()
+    return out
+
+
+def _check(cfg, steps, chunks, sources, dt=None, tol=TOL):
+    disc = problem.build(problem.Problem.from_config(cfg))
+    if dt is None:
+        dt = 0.9 * timestep.critical_dt(disc)
+    got = _run(cfg, dt, chunks, sources)
+    c, _ = ox.partition(disc)
+    assert got["nc"] == len(c)
+    assert np.array_equal(got["dofs"], c)
+    for r, src in enumerate(sources):
+        ref = ox.imex(disc, dt, steps, sources=[src])
+        e = np.linalg.norm(got["u"][r] - ref["u"]) / np.linalg.norm(ref["u"])
+        ev = np.linalg.norm(got["v"][r] - ref["v_c"]) / max(np.linalg.norm(ref["v_c"]), 1e-300)
+        assert e <= tol and ev <= tol, (r, e, ev)
+    return got
+
+
+def _c1(alpha):
+    cfg = workloads.config("c1")
+    cfg["alpha"] = alpha
+    return cfg
+
+
+def test_imex_c1_parity():
+    # 2-D p=3, 16x16 cells, one circular hole; two calls (start, then continue)
+    cfg = _c1(1e-4)
+    _check(cfg, 200, [120, 80], cfg["sources"])
+
+
+def test_imex_c1_paper_alpha():
+    cfg = _c1(1e-12)
+    _check(cfg, 200, [200], cfg["sources"], tol=TOL_ILL)
+
+
+def test_imex_two_sources_batched():
+    cfg = _c1(1e-4)
+    srcs = [dict(x=(0.1, 0.1), f0=10.0, amp=1.0), dict(x=(0.83, 0.27), f0=7.0, amp=0.5)]
+    _check(cfg, 90, [90], srcs)
+
+
+def test_imex_3d_scalar_parity():
+    cfg = workloads._base(3, (5, 4, 4), 2, [(0.52, 0.4, 0.4)], [0.22], nsteps=60,
+                          hi=(1.0, 0.8, 0.8), alpha=1e-4)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), f0=8.0, amp=1.0)]
+    _check(cfg, 60, [60], cfg["sources"])
+
+
+def test_imex_3d_elastic_parity():
+    cfg = workloads._base(3, (4, 4, 4), 2, [(0.55, 0.5, 0.5)], [0.2], ncomp=3, nsteps=40,
+                          alpha=1e-4)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    _check(cfg, 40, [40], cfg["sources"])
+
+
+def test_imex_without_cut_cells_is_the_explicit_step():
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cfg = workloads._base(2, (12, 12), 3, np.zeros((0, 2)), np.zeros(0), nsteps=50)
+    src = [dict(x=(0.3, 0.4), f0=10.0, amp=1.0)]
+    s = Solver(cfg, precision="fp64")
+    dt = 0.9 * s.critical_dt(max_iter=600, rtol=1e-9)
+    assert fcw.imex_prepare(s.ctx, dt) == 0
+    u1, d1 = s.zeros(1), s.zeros(1)
+    fcw.step_imex(s.ctx, 1, u1, d1, None, None, src, 0.0, dt, 50, 1)
+    u2, d2 = s.zeros(1), s.zeros(1)
+    s.step(u2, d2, src, dt, 50, t0=0.0, start=True)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+    s.close()
+
+
+def test_imex_beyond_the_explicit_limit():
+    # eps = 0: the lumped explicit step is limited by a tiny cut fragment; IMEX runs at
+    # the step size of the uncut cells and matches the oracle there
+    cfg = workloads._base(2, (6, 6), 2, [(0.5, 0.5)], [0.4949], eps=0.0, nsteps=300)
+    cfg_u = workloads._base(2, (6, 6), 2, np.zeros((0, 2)), np.zeros(0))
+    disc_u = problem.build(problem.Problem.from_config(cfg_u))
+    dt = 0.9 * timestep.critical_dt(disc_u)
+    src = [dict(x=(0.05, 0.05), f0=10.0, amp=1.0)]
+    got = _check(cfg, 300, [300], src, dt=dt, tol=TOL_ILL)
+    assert np.all(np.isfinite(got["u"]))

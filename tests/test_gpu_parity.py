@@ -346,10 +346,16 @@ def test_error_paths():
     with pytest.raises(fcw.FcwError) as e:     # outside the box
         s.step(u, d, [dict(x=(1.5, 0.5), f0=10.0)], 1e-3, 3, start=True)
     assert e.value.status == fcw.FCW_E_ARG
-    with pytest.raises(fcw.FcwError) as e:
-        fcw.step_imex(s.ctx, 1, u, d, d, None, 0.0, 1e-3, 1)
-    assert e.value.status == fcw.FCW_E_UNSUPPORTED
+    with pytest.raises(fcw.FcwError) as e:     # implicit DOFs but no v_c, a_c
+        fcw.step_imex(s.ctx, 1, u, d, None, None, None, 0.0, 1e-3, 1, 1)
+    assert e.value.status == fcw.FCW_E_ARG
     s.step(u, d, None, 1e-3, 0)               # zero steps is a no-op
+    s.close()
+    s = _solver(cfg, "fp32")                   # the IMEX scheme is FP64 only
+    u, d = s.zeros(1), s.zeros(1)
+    with pytest.raises(fcw.FcwError) as e:
+        fcw.step_imex(s.ctx, 1, u, d, None, None, None, 0.0, 1e-3, 1, 1)
+    assert e.value.status == fcw.FCW_E_UNSUPPORTED
     s.close()
 
 
