@@ -229,6 +229,55 @@ def bench_c3(steps, warmup, with_fp64):
     return out
 
 
+def bench_imex(steps, warmup):
+    """Semi-explicit (IMEX) scheme, FP64: the C2 void field at 64 x 64 cells, p = 3.
+    The implicit set (nodes of cut cells) has about 5.8 k DOFs; S and M^cc are dense and
+    factored once on the device."""
+    import torch
+    import workloads
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cc, rr = workloads.random_circles(seed=2)
+    cfg = workloads._base(2, (64, 64), 3, cc, rr, nsteps=steps)
+    src = cfg["sources"]
+    s = Solver(cfg, precision="fp64", device="cuda:0")
+    dt = 0.9 * s.critical_dt(max_iter=600, rtol=1e-7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nc = fcw.imex_prepare(s.ctx, dt)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    u, d = s.zeros(1), s.zeros(1)
+    v = torch.zeros(1, max(nc, 1), dtype=torch.float64, device="cuda:0")
+    a = torch.zeros_like(v)
+    stream = s.stream
+    fcw.step_imex(s.ctx, 1, u, d, v, a, src, 0.0, dt, warmup, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fcw.step_imex(s.ctx, 1, u, d, v, a, src, warmup * dt, dt, steps, 0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    active = int((s.export(fcw.ARR_MASS) > 0).sum())
+    # the explicit step alone on the same problem, for scale
+    u2, d2 = s.zeros(1), s.zeros(1)
+    s.step(u2, d2, src, dt, warmup, t0=0.0, start=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    s.step(u2, d2, src, dt, steps, t0=warmup * dt, start=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_exp = e0.elapsed_time(e1)
+    s.close()
+    return dict(workload="2-D scalar, the c2 void field at 64x64 cells, p=3 GLL, FP64, IMEX "
+                         "(Alg. imex, beta=1/4, gamma=1/2), dense FP64 Cholesky of S and M^cc",
+                value=active * steps / (ms * 1e-3), unit="DOF-updates/s", ms_per_step=ms / steps,
+                steps=steps, n_implicit=nc, active_dof=active, prepare_s=t_prep, dt=dt,
+                explicit_ms_per_step=ms_exp / steps,
+                solve_bytes_per_step=8 * nc * nc)
+
+
 def bench_serve(count, scale, rate, quantum):
     """Serving loop over the first `count` requests of the request stream (seed 5),
     cell counts per side scaled by `scale`; Poisson arrivals at `rate` requests/s
@@ -271,6 +320,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--calib", action="store_true", help="also run a 1 GiB copy (counter scale)")
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
+    ap.add_argument("--imex-steps", type=int, default=200,
+                    help="steps of the IMEX leg (0 skips it)")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--c3-warmup", type=int, default=10)
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving leg (0: skip)")
@@ -318,6 +369,10 @@ def main():
         print(f"[bench] cpu baseline: {cb['sample']}", file=sys.stderr, flush=True)
     if not args.no_c3:
         res["c3"] = bench_c3(args.c3_steps, args.c3_warmup, not args.no_fp64)
+    if args.imex_steps > 0:
+        res["imex"] = bench_imex(args.imex_steps, 5)
+        print(f"[bench] imex: {res['imex']['ms_per_step']:.3f} ms/step, "
+              f"{res['imex']['n_implicit']} implicit DOFs", file=sys.stderr, flush=True)
     if args.serve_count > 0:
         res["serving"] = bench_serve(args.serve_count, args.serve_scale,
                                      None if args.serve_rate <= 0 else args.serve_rate,

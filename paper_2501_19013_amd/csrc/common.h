@@ -117,7 +117,7 @@ struct Ctx {
   int64_t imex_ncn = 0;            // implicit nodes
   double imex_dt = 0.0;
   int64_t* d_imex_dofs = nullptr;  // [imex_nc] global DOF of each implicit DOF
-  double* d_imex_s = nullptr;      // [2][imex_nc^2] L of S (row-major, lower), L^T
+  double* d_imex_s = nullptr;      // [3][imex_nc^2] L of S (row-major, lower), L^T, S^{-1}
   double* d_imex_m = nullptr;      // [2][imex_nc^2] the same for M^cc
   double* d_imex_work = nullptr;   // per-call work vectors
   size_t imex_work_bytes = 0;

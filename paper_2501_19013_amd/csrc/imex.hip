@@ -11,9 +11,9 @@
 //   2. implicit predictors u_p = u_k + dt v_k + (1/2 - beta) dt^2 a_k on the implicit
 //      DOFs, the explicit DOFs' new values serving as theirs;
 //   3. r = K u_p (the explicit solver's stiffness action);
-//   4. S a_{k+1} = F_{k+1} - r on the implicit DOFs, S = M^cc + beta dt^2 K^cc, by the
-//      dense Cholesky factor of S (forward and backward sweeps, one workgroup per
-//      right-hand side, the vector in LDS);
+//   4. S a_{k+1} = F_{k+1} - r on the implicit DOFs, S = M^cc + beta dt^2 K^cc: a dense
+//      product with S^{-1}, formed once from the Cholesky factor of S (forward and
+//      backward sweeps against the unit vectors, one workgroup per column);
 //   5. v_{k+1} = v_k + dt ((1 - gamma) a_k + gamma a_{k+1}),
 //      u_{k+1} = u_p + beta dt^2 a_{k+1}.
 //
@@ -303,6 +303,37 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const 
   for (int64_t i = t; i < n; i += 256) xr[i] = xs[i];
 }
 
+// x_r = A b_r for every right-hand side r, A dense symmetric n x n (row-major): one wave
+// per row, each row read once for up to 8 right-hand sides
+__global__ __launch_bounds__(256) void sym_gemv_kernel(const double* A, int64_t n, const double* b,
+                                                       double* x, int nrhs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double* row = A + i * n;
+  for (int r0 = 0; r0 < nrhs; r0 += 8) {
+    const int nr = min(8, nrhs - r0);
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t j = lane; j < n; j += 64) {
+      const double aij = row[j];
+  #pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nr) acc[q] += aij * b[(int64_t)(r0 + q) * n + j];
+    }
+  #pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double v = acc[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (q < nr && lane == 0) x[(int64_t)(r0 + q) * n + i] = v;
+    }
+  }
+}
+
+__global__ void identity_kernel(double* A, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * n) A[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
 // ---- per-step vector kernels over [nrhs][nc] ----
 
 __global__ void imex_gather_kernel(const double* u, const int64_t* dofs, int64_t nc, int64_t ndof,
@@ -377,6 +408,21 @@ void imex_free(Ctx& c) {
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// x = A^{-1} b for nrhs right-hand sides of length n, A = L L^T given as the pair (L, L^T)
+static fcw_status imex_solve(Ctx& c, const double* Lpair, int64_t n, int nrhs, const double* b,
+                             double* x) {
+  const size_t lds = (size_t)n * sizeof(double);
+  // set once (not a stream operation)
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void*)chol_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      FCW_IMEX_MAX_NC * (int)sizeof(double));
+  FCW_HIP(attr);
+  chol_solve_kernel<<<nrhs, 256, lds, c.stream>>>(Lpair, Lpair + (size_t)n * n, n, b, x);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "IMEX triangular solves");
+  return FCW_OK;
+}
+
 // Implicit set, dense S = M^cc + beta dt^2 K^cc and M^cc, their factors.
 fcw_status imex_prepare(Ctx& c, double dt) {
   if (c.imex_nc >= 0 && c.imex_dt == dt) return FCW_OK;
@@ -414,7 +460,7 @@ fcw_status imex_prepare(Ctx& c, double dt) {
   if (nc > 0) {
     const size_t mat = (size_t)nc * nc * sizeof(double);
     if (hipMalloc(&c.d_imex_dofs, nc * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc(&c.d_imex_s, 2 * mat) != hipSuccess ||
+        hipMalloc(&c.d_imex_s, 3 * mat) != hipSuccess ||
         hipMalloc(&c.d_imex_m, 2 * mat) != hipSuccess) {
       set_error("IMEX: allocation of the dense implicit matrices (%lld DOFs) failed",
                 (long long)nc);
@@ -445,27 +491,29 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     const unsigned gy = (unsigned)std::min<int64_t>(nc, 65535);
     const unsigned gz = (unsigned)((nc + gy - 1) / gy);
     imex_assemble_kernel<<<dim3(blocks_for(nc), gy, gz), 256, 0, c.stream>>>(a);
-    if (hipGetLastError() != hipSuccess) return fail(hip_fail(hipGetLastError(), "IMEX assembly"));
+    {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return fail(hip_fail(e, "IMEX assembly"));
+    }
     if ((st = cholesky(c, c.d_imex_s, c.d_imex_s + (size_t)nc * nc, nc))) return fail(st);
     if ((st = cholesky(c, c.d_imex_m, c.d_imex_m + (size_t)nc * nc, nc))) return fail(st);
+    // S^{-1}, column by column (symmetric: row r of the result is column r)
+    double* sinv = c.d_imex_s + 2 * (size_t)nc * nc;
+    identity_kernel<<<blocks_for(nc * nc), 256, 0, c.stream>>>(sinv, nc);
+    {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return fail(hip_fail(e, "IMEX identity"));
+    }
+    if ((st = imex_solve(c, c.d_imex_s, nc, (int)nc, sinv, sinv))) return fail(st);
+    {
+      const hipError_t e = hipStreamSynchronize(c.stream);
+      if (e != hipSuccess) return fail(hip_fail(e, "IMEX inverse"));
+    }
   }
   (void)hipFree(mark);
   (void)hipFree(pos);
   c.imex_nc = nc;
   c.imex_dt = dt;
-  return FCW_OK;
-}
-
-static fcw_status imex_solve(Ctx& c, const double* Lpair, int nrhs, const double* b, double* x) {
-  const int64_t n = c.imex_nc;
-  const size_t lds = (size_t)n * sizeof(double);
-  // set once (not a stream operation)
-  static const hipError_t attr = hipFuncSetAttribute(
-      (const void*)chol_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-      FCW_IMEX_MAX_NC * (int)sizeof(double));
-  FCW_HIP(attr);
-  chol_solve_kernel<<<nrhs, 256, lds, c.stream>>>(Lpair, Lpair + (size_t)n * n, n, b, x);
-  FCW_HIP(hipGetLastError());
   return FCW_OK;
 }
 
@@ -494,7 +542,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     if ((st = launch_apply(c, nrhs, u, rk))) return st;
     imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes, nrhs,
                                               c.dim, c.p, c.npts[0], c.npts[1], t0, bv);
-    if ((st = imex_solve(c, c.d_imex_m, nrhs, bv, a_c))) return st;
+    if ((st = imex_solve(c, c.d_imex_m, nc, nrhs, bv, a_c))) return st;
   }
   for (int k = 0; k < nsteps; ++k) {
     const double t = t0 + k * dt;
@@ -509,7 +557,8 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     if ((st = launch_apply(c, nrhs, u, rk))) return st;
     imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes, nrhs,
                                               c.dim, c.p, c.npts[0], c.npts[1], t + dt, bv);
-    if ((st = imex_solve(c, c.d_imex_s, nrhs, bv, an))) return st;
+    sym_gemv_kernel<<<(unsigned)((nc + 3) / 4), 256, 0, c.stream>>>(
+        c.d_imex_s + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
     imex_correct_kernel<<<gb, 256, 0, c.stream>>>(u, d, c.d_imex_dofs, uold, v_c, a_c, an, nc,
                                                   ndof, nrhs, dt);
     FCW_HIP(hipGetLastError());
