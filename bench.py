@@ -27,6 +27,10 @@ the matrix cores for the FP32 3-D elastic one), the other sits under `other`.
 
 cpu_baseline: the FP64 numpy oracle (single BLAS thread) stepping the same full-size
 problem for a bounded number of steps on the host.
+
+Further legs in the same JSON line: `c3` (3-D elastic 96^3 p=2: FP32, split BF16, FP64),
+`imex` (the semi-explicit scheme of Alg. imex, FP64, on the same void field at 64^2 p=3)
+and `serving` (p50/p99 latency of a seeded request stream).
 """
 from __future__ import annotations
 
