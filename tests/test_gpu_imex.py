@@ -84,6 +84,15 @@ def test_imex_two_sources_batched():
     _check(cfg, 90, [90], srcs)
 
 
+def test_imex_ten_sources():
+    # ten right-hand sides: the S^-1 product runs them in passes of eight
+    cfg = _c1(1e-4)
+    xs = [(0.1, 0.1), (0.9, 0.1), (0.1, 0.9), (0.9, 0.9), (0.5, 0.08), (0.08, 0.5),
+          (0.92, 0.5), (0.5, 0.92), (0.25, 0.75), (0.75, 0.25)]
+    srcs = [dict(x=x, f0=8.0 + i, amp=1.0) for i, x in enumerate(xs)]
+    _check(cfg, 50, [30, 20], srcs)
+
+
 def test_imex_3d_scalar_parity():
     cfg = workloads._base(3, (5, 4, 4), 2, [(0.52, 0.4, 0.4)], [0.22], nsteps=60,
                           hi=(1.0, 0.8, 0.8), alpha=1e-4)
