@@ -1,11 +1,14 @@
-"""Pins of the IMEX oracle (Sec. 2.5, Alg. imex) against what the mathematics fixes:
+"""Pins of the IMEX oracle (Sec. 2.5, Alg. imex) and of central differences with the
+consistent cut-DOF mass, against what the mathematics fixes:
 
 * no cut cell: the scheme is central differences (eq. cdm with the Newmark start-up);
 * every active DOF implicit and no load: the trapezoidal rule conserves the energy
   1/2 v^T M v + 1/2 u^T K u exactly;
 * mixed split: second-order convergence in dt;
 * stability set by the explicit part: without eigenvalue stabilisation the lumped
-  explicit step diverges at the step size of the uncut cells, IMEX does not.
+  explicit step diverges at the step size of the uncut cells, IMEX does not;
+* consistent-mass central differences: eq. cdm without cut cells; the discrete energy
+  with the block mass is conserved below 2 / sqrt(lambda_max(M^-1 K)) and grows above it.
 """
 import numpy as np
 import pytest
@@ -81,3 +84,44 @@ def test_stability_set_by_explicit_part():
     e = timestep.cdm(disc, dt, n, sources=src)["u"]
     assert np.all(np.isfinite(r["u"])) and np.abs(r["u"]).max() < 1e3
     assert not np.all(np.isfinite(e)) or np.abs(e).max() > 1e6
+
+
+def test_consistent_cdm_without_cut_cells_is_cdm():
+    cfg, disc = _disc(np.zeros((0, 2)), np.zeros(0))
+    dt = 0.9 * timestep.critical_dt(disc)
+    src = [dict(x=(0.31, 0.42), f0=10.0, amp=1.0)]
+    got = ox.cdm_consistent(disc, dt, 40, sources=src)["u"]
+    ref = timestep.cdm(disc, dt, 40, sources=src)["u"]
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def _block_mass(disc):
+    c, d = ox.partition(disc)
+    m_dd, Mcc = ox.mass_matrices(disc, c, d)
+    act = np.concatenate([d, c])
+    M = np.zeros((len(act), len(act)))
+    M[:len(d), :len(d)] = np.diag(m_dd)
+    M[len(d):, len(d):] = Mcc.toarray()
+    K = problem.assembled_K(disc)[act][:, act].toarray()
+    return act, M, K
+
+
+def test_consistent_cdm_energy_and_stability_limit():
+    # with the consistent cut-DOF mass the discrete CDM energy
+    # 1/2 v^T M v + 1/2 u_{k+1}^T K u_k (v = (u_{k+1} - u_k) / dt) is conserved without load
+    # below 2 / sqrt(lambda_max(M^-1 K)), and the step grows above it
+    cfg, disc = _disc([(0.5, 0.5)], [0.4949], eps=0.0)
+    act, M, K = _block_mass(disc)
+    lam = float(np.max(np.real(np.linalg.eigvals(np.linalg.solve(M, K)))))
+    dtc = 2.0 / np.sqrt(lam)
+    rng = np.random.default_rng(3)
+    u0 = np.zeros(disc.prob.ndof)
+    u0[act] = rng.standard_normal(len(act))
+    es = []
+    for n in (30, 31, 90, 91):
+        r = ox.cdm_consistent(disc, 0.9 * dtc, n, u0=u0)
+        v = (r["u"][act] - r["u_prev"][act]) / (0.9 * dtc)
+        es.append(0.5 * v @ M @ v + 0.5 * r["u"][act] @ K @ r["u_prev"][act])
+    assert max(es) - min(es) <= 1e-10 * abs(es[0]), es
+    grow = ox.cdm_consistent(disc, 1.05 * dtc, 600, u0=u0)["u"]
+    assert np.abs(grow).max() > 1e3 * np.abs(u0).max()
