@@ -211,6 +211,17 @@ fcw_status fcw_step_imex(fcw_ctx* ctx, int32_t nrhs, void* u, void* d, void* v_c
                          const fcw_source* src, double t0, double dt, int32_t nsteps,
                          int32_t start);
 
+/* nsteps central-difference steps (eq. cdm, Newmark beta = 0 start-up) with the block mass
+ * M = diag(M^dd, M^cc) of the IMEX split: the consistent cut-DOF mass M^cc of
+ * fcw_imex_prepare is inverted each step (a dense product with (M^cc)^{-1}), the other
+ * DOFs keep their GLL diagonal (the consistent-mass spectral cell method).  Stable below
+ * 2 / sqrt(lambda_max(M^{-1} K)) of that block mass, which the caller supplies through dt
+ * (fcw_critical_dt covers the lumped mass only).  u, d, src, t0, start as for
+ * fcw_step_explicit; FP64 contexts only; sets the scheme up for dt when needed. */
+fcw_status fcw_step_consistent(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
+                               const fcw_source* src, double t0, double dt, int32_t nsteps,
+                               int32_t start);
+
 /* Stiffness action r = K u (eq. semi, element by element, same kernels as the step):
  * u, r device [nrhs][ndof] in the state precision. */
 fcw_status fcw_apply_stiffness(fcw_ctx* ctx, int32_t nrhs, const void* u, void* r);

@@ -641,7 +641,26 @@ fcw_status fcw_step_imex(fcw_ctx* c, int32_t nrhs, void* u, void* d, void* v_c, 
   SourceDev* saved = c->d_src;
   if (!src) c->d_src = nullptr;
   st = imex_run(*c, nrhs, (double*)u, (double*)d, (double*)v_c, (double*)a_c, t0, dt, nsteps,
-                start);
+                start, false);
+  c->d_src = saved;
+  return st;
+}
+
+fcw_status fcw_step_consistent(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
+                               double t0, double dt, int32_t nsteps, int32_t start) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (c->precision != FCW_FP64) {
+    set_error("the consistent-mass step runs on FP64 contexts only");
+    return FCW_E_UNSUPPORTED;
+  }
+  if ((st = prepare_call(c, nrhs, u, d, src, dt, nsteps))) return st;
+  if ((st = imex_prepare(*c, dt))) return st;
+  if (nsteps == 0) return FCW_OK;
+  SourceDev* saved = c->d_src;
+  if (!src) c->d_src = nullptr;
+  st = imex_run(*c, nrhs, (double*)u, (double*)d, nullptr, nullptr, t0, dt, nsteps, start, true);
   c->d_src = saved;
   return st;
 }

@@ -118,7 +118,7 @@ struct Ctx {
   double imex_dt = 0.0;
   int64_t* d_imex_dofs = nullptr;  // [imex_nc] global DOF of each implicit DOF
   double* d_imex_s = nullptr;      // [3][imex_nc^2] L of S (row-major, lower), L^T, S^{-1}
-  double* d_imex_m = nullptr;      // [2][imex_nc^2] the same for M^cc
+  double* d_imex_m = nullptr;      // [3][imex_nc^2] the same for M^cc
   double* d_imex_work = nullptr;   // per-call work vectors
   size_t imex_work_bytes = 0;
   int32_t* d_imex_flag = nullptr;  // [1] non-positive pivot seen
@@ -159,8 +159,9 @@ fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
 // imex.hip: semi-explicit scheme (implicit DOFs = nodes of cut cells)
 void imex_free(Ctx& c);
 fcw_status imex_prepare(Ctx& c, double dt);
+// consistent: central differences with the consistent cut-DOF mass instead (v_c, a_c unused)
 fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double* a_c, double t0,
-                    double dt, int nsteps, int start);
+                    double dt, int nsteps, int start, bool consistent);
 // cutcell.hip: cut-cell products y = K_e u_e, once per cut cell and step
 fcw_status ensure_ycut(Ctx& c, int nrhs);
 size_t cutprob_size(int fp64);

@@ -17,6 +17,10 @@
 //   5. v_{k+1} = v_k + dt ((1 - gamma) a_k + gamma a_{k+1}),
 //      u_{k+1} = u_p + beta dt^2 a_{k+1}.
 //
+// The same set-up serves central differences with the consistent cut-DOF mass (the
+// consistent-mass spectral cell method, eq. cdm with M = diag(M^dd, M^cc)): per step
+// a = (M^cc)^{-1} (F_k - K u_k) on the implicit DOFs, the lumped step elsewhere.
+//
 // S and M^cc are assembled dense (entry by entry from the cells around the two nodes,
 // in a fixed order) and factored on the device by a blocked right-looking Cholesky.
 // The dense form bounds the implicit set (FCW_IMEX_MAX_NC); a sparse factorisation is
@@ -394,6 +398,19 @@ __global__ void imex_correct_kernel(double* u, double* d, const int64_t* dofs, c
   a[t] = an;
 }
 
+// consistent-mass central differences on the implicit DOFs: d = d_k + w a, u = u_k + d
+__global__ void cons_fix_kernel(double* u, double* d, const int64_t* dofs, const double* uold,
+                                const double* dold, const double* a, int64_t nc, int64_t ndof,
+                                int nrhs, double w) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * nrhs) return;
+  const int64_t r = t / nc, i = t % nc;
+  const int64_t g = r * ndof + dofs[i];
+  const double dn = dold[t] + w * a[t];
+  d[g] = dn;
+  u[g] = uold[t] + dn;
+}
+
 void imex_free(Ctx& c) {
   for (void* p : {(void*)c.d_imex_dofs, (void*)c.d_imex_s, (void*)c.d_imex_m,
                   (void*)c.d_imex_work, (void*)c.d_imex_flag})
@@ -461,7 +478,7 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     const size_t mat = (size_t)nc * nc * sizeof(double);
     if (hipMalloc(&c.d_imex_dofs, nc * sizeof(int64_t)) != hipSuccess ||
         hipMalloc(&c.d_imex_s, 3 * mat) != hipSuccess ||
-        hipMalloc(&c.d_imex_m, 2 * mat) != hipSuccess) {
+        hipMalloc(&c.d_imex_m, 3 * mat) != hipSuccess) {
       set_error("IMEX: allocation of the dense implicit matrices (%lld DOFs) failed",
                 (long long)nc);
       return fail(FCW_E_NOMEM);
@@ -497,14 +514,14 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     }
     if ((st = cholesky(c, c.d_imex_s, c.d_imex_s + (size_t)nc * nc, nc))) return fail(st);
     if ((st = cholesky(c, c.d_imex_m, c.d_imex_m + (size_t)nc * nc, nc))) return fail(st);
-    // S^{-1}, column by column (symmetric: row r of the result is column r)
-    double* sinv = c.d_imex_s + 2 * (size_t)nc * nc;
-    identity_kernel<<<blocks_for(nc * nc), 256, 0, c.stream>>>(sinv, nc);
-    {
+    // S^{-1} and (M^cc)^{-1}, column by column (symmetric: row r of the result is column r)
+    for (double* f : {c.d_imex_s, c.d_imex_m}) {
+      double* inv = f + 2 * (size_t)nc * nc;
+      identity_kernel<<<blocks_for(nc * nc), 256, 0, c.stream>>>(inv, nc);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return fail(hip_fail(e, "IMEX identity"));
+      if ((st = imex_solve(c, f, nc, (int)nc, inv, inv))) return fail(st);
     }
-    if ((st = imex_solve(c, c.d_imex_s, nc, (int)nc, sinv, sinv))) return fail(st);
     {
       const hipError_t e = hipStreamSynchronize(c.stream);
       if (e != hipSuccess) return fail(hip_fail(e, "IMEX inverse"));
@@ -519,11 +536,11 @@ fcw_status imex_prepare(Ctx& c, double dt) {
 
 // nsteps IMEX steps; u, d [nrhs][ndof], v_c, a_c [nrhs][nc] (FP64, device)
 fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double* a_c,
-                    double t0, double dt, int nsteps, int start) {
+                    double t0, double dt, int nsteps, int start, bool consistent) {
   const int64_t nc = c.imex_nc, ndof = c.ndof;
   const int64_t nv = nc * nrhs;
-  // work: r (nrhs x ndof), then b, anew, uold (nrhs x nc each)
-  const size_t need = ((size_t)nrhs * ndof + 3 * (size_t)nv) * sizeof(double);
+  // work: r (nrhs x ndof), then b, anew, uold, dold (nrhs x nc each)
+  const size_t need = ((size_t)nrhs * ndof + 4 * (size_t)nv) * sizeof(double);
   if (c.imex_work_bytes < need) {
     if (c.d_imex_work) FCW_HIP(hipFree(c.d_imex_work));
     c.d_imex_work = nullptr;
@@ -537,6 +554,30 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
   double* uold = an + nv;
   const unsigned gb = blocks_for(nv);
   fcw_status st;
+  if (consistent) {
+    // central differences with the consistent cut-DOF mass (a = (M^cc)^{-1} (F - K u) on
+    // the implicit DOFs, the diagonal elsewhere)
+    double* dold = uold + nv;
+    for (int k = 0; k < nsteps; ++k) {
+      const double t = t0 + k * dt;
+      const int first = start && k == 0;
+      if (nc > 0) {
+        imex_gather_kernel<<<gb, 256, 0, c.stream>>>(u, c.d_imex_dofs, nc, ndof, nrhs, uold);
+        imex_gather_kernel<<<gb, 256, 0, c.stream>>>(d, c.d_imex_dofs, nc, ndof, nrhs, dold);
+        if ((st = launch_apply(c, nrhs, u, rk))) return st;
+        imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes,
+                                                  nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, bv);
+        sym_gemv_kernel<<<(unsigned)((nc + 3) / 4), 256, 0, c.stream>>>(
+            c.d_imex_m + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
+      }
+      if ((st = run_steps(c, c.tile_choice, nrhs, u, d, c.d_ubuf, t, dt, 1, first))) return st;
+      if (nc > 0)
+        cons_fix_kernel<<<gb, 256, 0, c.stream>>>(u, d, c.d_imex_dofs, uold, dold, an, nc, ndof,
+                                                  nrhs, (first ? 0.5 : 1.0) * dt * dt);
+      FCW_HIP(hipGetLastError());
+    }
+    return FCW_OK;
+  }
   if (start && nc > 0) {
     // a_0 from M^cc a_0 = F_0 - (K u_0) on the implicit DOFs
     if ((st = launch_apply(c, nrhs, u, rk))) return st;

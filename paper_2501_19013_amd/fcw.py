@@ -24,7 +24,8 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32, ARR_IMEX_DOFS: n
 
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
-           "fcw_step_explicit", "fcw_imex_prepare", "fcw_step_imex", "fcw_apply_stiffness",
+           "fcw_step_explicit", "fcw_imex_prepare", "fcw_step_imex", "fcw_step_consistent",
+           "fcw_apply_stiffness",
            "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
            "fcw_export", "fcw_destroy", "fcw_last_error")
@@ -87,6 +88,7 @@ def load(path=LIB_PATH):
     lib.fcw_step_explicit.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_imex_prepare.argtypes = [vp, f64, C.POINTER(C.c_int64)]
     lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
+    lib.fcw_step_consistent.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_apply_stiffness.argtypes = [vp, i32, vp, vp]
     lib.fcw_query.argtypes = [vp, C.POINTER(Info)]
     lib.fcw_export.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(C.c_int64)]
@@ -188,6 +190,12 @@ def imex_prepare(ctx, dt):
     n = C.c_int64()
     _check(load().fcw_imex_prepare(ctx, float(dt), C.byref(n)))
     return n.value
+
+
+def step_consistent(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):
+    srcs = _sources(sources)
+    _check(load().fcw_step_consistent(ctx, int(nrhs), _ptr(u), _ptr(d), srcs, float(t0),
+                                      float(dt), int(nsteps), int(start)))
 
 
 def step_imex(ctx, nrhs, u, d, v_c, a_c, sources, t0, dt, nsteps, start):

@@ -135,3 +135,59 @@ def test_imex_beyond_the_explicit_limit():
     src = [dict(x=(0.05, 0.05), f0=10.0, amp=1.0)]
     got = _check(cfg, 300, [300], src, dt=dt, tol=TOL_ILL)
     assert np.all(np.isfinite(got["u"]))
+
+
+def _consistent_dt(disc):
+    """0.9 * 2 / sqrt(lambda_max(M^-1 K)) for the block mass diag(M^dd, M^cc) (dense)."""
+    c, d = ox.partition(disc)
+    m_dd, Mcc = ox.mass_matrices(disc, c, d)
+    act = np.concatenate([d, c])
+    n = len(act)
+    M = np.zeros((n, n))
+    M[:len(d), :len(d)] = np.diag(m_dd)
+    M[len(d):, len(d):] = Mcc.toarray()
+    K = problem.assembled_K(disc)[act][:, act].toarray()
+    Li = np.linalg.inv(np.linalg.cholesky(M))
+    lam = np.linalg.eigvalsh(Li @ K @ Li.T)[-1]
+    return 0.9 * 2.0 / np.sqrt(lam)
+
+
+@pytest.mark.parametrize("alpha,tol", [(1e-4, 1e-10), (1e-12, 1e-8)])
+def test_consistent_mass_cdm_parity(alpha, tol):
+    # central differences with the consistent cut-DOF mass, C1, two calls; the bar at
+    # alpha = 1e-12 follows from the oracle's own sensitivity (a 1e-15 relative change of
+    # the cut-cell matrices moves its result by 1e-11)
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cfg = _c1(alpha)
+    disc = problem.build(problem.Problem.from_config(cfg))
+    dt = _consistent_dt(disc)
+    ref = ox.cdm_consistent(disc, dt, 200, sources=cfg["sources"])["u"]
+    s = Solver(cfg, precision="fp64")
+    u, d = s.zeros(1), s.zeros(1)
+    fcw.step_consistent(s.ctx, 1, u, d, cfg["sources"], 0.0, dt, 120, 1)
+    fcw.step_consistent(s.ctx, 1, u, d, cfg["sources"], 120 * dt, dt, 80, 0)
+    torch.cuda.synchronize()
+    got = u[0].cpu().numpy()
+    s.close()
+    assert np.linalg.norm(got - ref) <= tol * np.linalg.norm(ref)
+
+
+def test_consistent_mass_cdm_3d_elastic():
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cfg = workloads._base(3, (4, 4, 4), 2, [(0.55, 0.5, 0.5)], [0.2], ncomp=3, nsteps=40,
+                          alpha=1e-4)
+    cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    disc = problem.build(problem.Problem.from_config(cfg))
+    dt = _consistent_dt(disc)
+    ref = ox.cdm_consistent(disc, dt, 40, sources=cfg["sources"])["u"]
+    s = Solver(cfg, precision="fp64")
+    u, d = s.zeros(1), s.zeros(1)
+    fcw.step_consistent(s.ctx, 1, u, d, cfg["sources"], 0.0, dt, 40, 1)
+    torch.cuda.synchronize()
+    got = u[0].cpu().numpy()
+    s.close()
+    assert np.linalg.norm(got - ref) <= TOL * np.linalg.norm(ref)
