@@ -333,6 +333,33 @@ __global__ __launch_bounds__(256) void sym_gemv_kernel(const double* A, int64_t 
   }
 }
 
+// the same for one right-hand side: 16-byte loads of the row and of b, two rows per wave
+// pass in flight (n even: rows start 16-byte aligned)
+__global__ __launch_bounds__(256) void sym_gemv1_kernel(const double* A, int64_t n,
+                                                        const double* b, double* x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double2* row = (const double2*)(A + i * n);
+  const double2* bv = (const double2*)b;
+  const int64_t n2 = n / 2;
+  double acc0 = 0.0, acc1 = 0.0;
+  int64_t j = lane;
+  for (; j + 64 < n2; j += 128) {
+    const double2 a0 = row[j], a1 = row[j + 64];
+    const double2 b0 = bv[j], b1 = bv[j + 64];
+    acc0 += a0.x * b0.x + a0.y * b0.y;
+    acc1 += a1.x * b1.x + a1.y * b1.y;
+  }
+  if (j < n2) {
+    const double2 a0 = row[j], b0 = bv[j];
+    acc0 += a0.x * b0.x + a0.y * b0.y;
+  }
+  double v = acc0 + acc1;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) x[i] = v;
+}
+
 __global__ void identity_kernel(double* A, int64_t n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n * n) A[t] = (t / n == t % n) ? 1.0 : 0.0;
@@ -409,6 +436,15 @@ __global__ void cons_fix_kernel(double* u, double* d, const int64_t* dofs, const
   const double dn = dold[t] + w * a[t];
   d[g] = dn;
   u[g] = uold[t] + dn;
+}
+
+// x = A b for nrhs right-hand sides (A the dense inverse of S or M^cc)
+static void solve_product(Ctx& c, const double* A, int64_t n, const double* b, double* x,
+                          int nrhs) {
+  if (nrhs == 1 && n % 2 == 0)
+    sym_gemv1_kernel<<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(A, n, b, x);
+  else
+    sym_gemv_kernel<<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(A, n, b, x, nrhs);
 }
 
 void imex_free(Ctx& c) {
@@ -539,8 +575,11 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
                     double t0, double dt, int nsteps, int start, bool consistent) {
   const int64_t nc = c.imex_nc, ndof = c.ndof;
   const int64_t nv = nc * nrhs;
-  // work: r (nrhs x ndof), then b, anew, uold, dold (nrhs x nc each)
-  const size_t need = ((size_t)nrhs * ndof + 4 * (size_t)nv) * sizeof(double);
+  // work: r (nrhs x ndof), then b, anew, uold, dold (nrhs x nc each), each part starting
+  // on a 256-byte boundary
+  auto up32 = [](size_t v) { return (v + 31) / 32 * 32; };
+  const size_t nr = up32((size_t)nrhs * ndof), nvp = up32((size_t)nv);
+  const size_t need = (nr + 4 * nvp) * sizeof(double);
   if (c.imex_work_bytes < need) {
     if (c.d_imex_work) FCW_HIP(hipFree(c.d_imex_work));
     c.d_imex_work = nullptr;
@@ -549,15 +588,15 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     c.imex_work_bytes = need;
   }
   double* rk = c.d_imex_work;
-  double* bv = rk + (size_t)nrhs * ndof;
-  double* an = bv + nv;
-  double* uold = an + nv;
+  double* bv = rk + nr;
+  double* an = bv + nvp;
+  double* uold = an + nvp;
   const unsigned gb = blocks_for(nv);
   fcw_status st;
   if (consistent) {
     // central differences with the consistent cut-DOF mass (a = (M^cc)^{-1} (F - K u) on
     // the implicit DOFs, the diagonal elsewhere)
-    double* dold = uold + nv;
+    double* dold = uold + nvp;
     for (int k = 0; k < nsteps; ++k) {
       const double t = t0 + k * dt;
       const int first = start && k == 0;
@@ -567,8 +606,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
         if ((st = launch_apply(c, nrhs, u, rk))) return st;
         imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes,
                                                   nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, bv);
-        sym_gemv_kernel<<<(unsigned)((nc + 3) / 4), 256, 0, c.stream>>>(
-            c.d_imex_m + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
+        solve_product(c, c.d_imex_m + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
       }
       if ((st = run_steps(c, c.tile_choice, nrhs, u, d, c.d_ubuf, t, dt, 1, first))) return st;
       if (nc > 0)
@@ -598,8 +636,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     if ((st = launch_apply(c, nrhs, u, rk))) return st;
     imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes, nrhs,
                                               c.dim, c.p, c.npts[0], c.npts[1], t + dt, bv);
-    sym_gemv_kernel<<<(unsigned)((nc + 3) / 4), 256, 0, c.stream>>>(
-        c.d_imex_s + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
+    solve_product(c, c.d_imex_s + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
     imex_correct_kernel<<<gb, 256, 0, c.stream>>>(u, d, c.d_imex_dofs, uold, v_c, a_c, an, nc,
                                                   ndof, nrhs, dt);
     FCW_HIP(hipGetLastError());
