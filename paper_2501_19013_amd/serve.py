@@ -6,8 +6,9 @@ counts) arrive over time.  The loop
 * admits a waiting request when a slot is free and its device footprint fits the
   memory budget; admission runs the FP64 setup of the problem (classification, space
   tree quadrature, eigenvalue stabilisation, lumping, Lanczos critical step) on a
-  second stream from a background thread, so it overlaps the stepping of the problems
-  already resident;
+  set-up stream from a background thread (``setup_workers`` of them, each with its own
+  stream), so set-ups overlap each other and the stepping of the problems already
+  resident;
 * keeps every admitted problem's fields resident on the device and advances all of
   them by one quantum of steps per round: problems of one kind (2-D scalar, same p
   and precision) share one fused launch per step through fcw_run, others follow on the
@@ -21,6 +22,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import math
+import threading
 import time
 from dataclasses import dataclass
 
@@ -74,28 +76,40 @@ def estimate_footprint(cfg, nrhs=1, precision="fp32"):
 
 class Server:
     def __init__(self, precision="fp32", device="cuda:0", memory_budget=None, max_slots=64,
-                 quantum=100, keep_results=False, graph=True):
+                 quantum=100, keep_results=False, graph=True, setup_workers=2):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.precision = precision
         self.stream = torch.cuda.Stream(self.device)
-        self.setup_stream = torch.cuda.Stream(self.device)
+        # one set-up stream per worker thread, handed out from a free list
+        self._setup_streams = [torch.cuda.Stream(self.device) for _ in range(setup_workers)]
+        self._free_streams = list(self._setup_streams)
+        self._streams_lock = threading.Lock()
         free, total = torch.cuda.mem_get_info(self.device)
         self.budget = int(memory_budget if memory_budget is not None else 0.8 * free)
         self.max_slots = max_slots
         self.quantum = quantum
         self.keep_results = keep_results
         self.graph = graph
-        self._pool = cf.ThreadPoolExecutor(max_workers=1)
+        self._pool = cf.ThreadPoolExecutor(max_workers=setup_workers)
 
     # -- setup on the side stream (background thread) --
     def _setup(self, req):
+        with self._streams_lock:
+            stream = self._free_streams.pop()
+        try:
+            return self._setup_on(req, stream)
+        finally:
+            with self._streams_lock:
+                self._free_streams.append(stream)
+
+    def _setup_on(self, req, setup_stream):
         torch = self.torch
         t_setup = time.perf_counter()
         with torch.cuda.device(self.device):
             ctx = fcw.assemble_cells(req.cfg, self.precision,
-                                     stream=self.setup_stream.cuda_stream)
+                                     stream=setup_stream.cuda_stream)
             try:
                 fcw.stabilize_cut_cells(ctx, req.cfg.get("eps", 1e-4),
                                         req.cfg.get("f_lambda", 1e-4))
@@ -103,10 +117,10 @@ class Server:
                 info = fcw.query(ctx)
                 nrhs = len(req.sources)
                 dtype = torch.float64 if self.precision == "fp64" else torch.float32
-                with torch.cuda.stream(self.setup_stream):
+                with torch.cuda.stream(setup_stream):
                     u = torch.zeros(nrhs, info["ndof"], dtype=dtype, device=self.device)
                     d = torch.zeros_like(u)
-                self.setup_stream.synchronize()
+                setup_stream.synchronize()
                 u.record_stream(self.stream)
                 d.record_stream(self.stream)
                 # stepping goes on the serving stream; set-up of later requests keeps the
