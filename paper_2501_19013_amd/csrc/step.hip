@@ -290,6 +290,19 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
         const int cs = min(c, NRC - 1);
         const int inf = info_s[cs];
         const bool valid = (c < NRC) && (inf == kInfoUncut);
+        if (__ballot(valid) == 0) {
+          // no uncut cell among the 16: outside cells get their zero rows, no products
+          if (c < NRC && inf == kInfoOut) {
+  #pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+  #pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = mb * 16 + 4 * lk + r;
+                if (i < NL) y_s[c * NL + i] = T(0);
+              }
+          }
+          continue;
+        }
         const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
         const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
         f32x4 acc[NMB];
@@ -343,6 +356,19 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
         const int cs = min(c, NRC - 1);
         const int inf = info_s[cs];
         const bool valid = (c < NRC) && (inf == kInfoUncut);
+        if (__ballot(valid) == 0) {
+          // no uncut cell among the 16: outside cells get their zero rows, no products
+          if (c < NRC && inf == kInfoOut) {
+  #pragma unroll
+            for (int mb = 0; mb < NMB; ++mb)
+  #pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int i = mb * 16 + Mma<T>::row(lk, r);
+                if (i < NL) y_s[c * NL + i] = T(0);
+              }
+          }
+          continue;
+        }
         const int lx = cs % RCX, ly = (cs / RCX) % RCY, lz = cs / (RCX * RCY);
         const int base = lx * P + RNX * (ly * P + RNY * (lz * P));
         T bv[NKS];
