@@ -71,15 +71,27 @@ def mass_matrices(disc, c, d):
 
 
 def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None, u0=None):
-    """Run ``nsteps`` steps of Alg. imex from u0 (default 0) at rest.  ``split``
-    overrides the partition (c, d) (a test reduces the scheme to one of its two parts
-    with it).  Returns the final u (all DOFs), the implicit DOFs' velocity and
-    acceleration, and the split."""
+    """Run ``nsteps`` steps of the IMEX scheme of Sec. 2.5 from u0 (default 0) at rest.
+    ``split`` overrides the partition (c, d) (a test reduces the scheme to one of its two
+    parts with it).  Returns the final u (all DOFs), the implicit DOFs' velocity and
+    acceleration, and the split.
+
+    The explicit DOFs take eq. cdm.  The implicit DOFs take the Newmark relations
+        u_{k+1} = u_k + dt v_k + dt^2 ((1/2 - beta) a_k + beta a_{k+1}),
+        v_{k+1} = v_k + dt ((1 - gamma) a_k + gamma a_{k+1}),
+        M^cc a_{k+1} = F^c_{k+1} - K^cc u^c_{k+1} - K^cd u^d_{k+1},
+    with u^d_{k+1} the explicit DOFs' new values.  Eliminating a_{k+1} with the first
+    relation gives the implicit displacements from one solve with S = M^cc + beta dt^2 K^cc:
+        S u^c_{k+1} = M^cc w + beta dt^2 (F^c_{k+1} - K^cd u^d_{k+1}),
+        w = u^c_k + dt v_k + (1/2 - beta) dt^2 a_k,
+    after which a_{k+1} = (u^c_{k+1} - w) / (beta dt^2) and the velocity follows."""
     prob = disc.prob
     c, d = partition(disc) if split is None else split
     m_dd, Mcc = mass_matrices(disc, c, d)
     K = assembled_K(disc)
-    Kc = K[c]
+    Kcc = K[c][:, c]
+    Kcd = K[c][:, d]
+    Kd = K[d]
     loads = [(load_vector(disc, s), float(s.get("f0", 10.0))) for s in sources]
 
     def force(k):
@@ -91,31 +103,36 @@ def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None,
     u = np.zeros(prob.ndof) if u0 is None else np.array(u0, dtype=np.float64)
     v_c = np.zeros(len(c))
     a_c = np.zeros(len(c))
+    bdt2 = beta * dt * dt
     if len(c):
-        S = (Mcc + beta * dt * dt * K[c][:, c]).toarray()
-        S_f = sla.cho_factor(0.5 * (S + S.T), lower=True)
         Mc = Mcc.toarray()
-        a_c = sla.cho_solve(sla.cho_factor(0.5 * (Mc + Mc.T), lower=True), force(0)[c] - Kc @ u)
+        Mc = 0.5 * (Mc + Mc.T)
+        S = Mc + bdt2 * Kcc.toarray()
+        S_f = sla.cho_factor(0.5 * (S + S.T), lower=True)
+        # initial acceleration from the equation of motion at t_0
+        a_c = sla.cho_solve(sla.cho_factor(Mc, lower=True), force(0)[c] - K[c] @ u)
     inv_dd = np.where(m_dd > 0, 1.0 / np.where(m_dd > 0, m_dd, 1.0), 0.0)
-    u_prev_d = None
+    ud_prev = None
     for k in range(nsteps):
-        # explicit step on d (central differences; Newmark beta = 0 start-up at k = 0)
-        acc_d = inv_dd * (force(k)[d] - (K[d] @ u))
+        Fk = force(k)
+        # explicit DOFs: eq. cdm, the first step by the Newmark rule with beta = 0
+        acc_d = inv_dd * (Fk[d] - Kd @ u)
         if k == 0:
-            new_d = u[d] + 0.5 * dt * dt * acc_d
+            ud_new = u[d] + 0.5 * dt * dt * acc_d
         else:
-            new_d = 2.0 * u[d] - u_prev_d + dt * dt * acc_d
-        u_prev_d = u[d].copy()
-        # implicit step on c (trapezoidal Newmark), predictors of d = their new values
-        pred = u.copy()
-        pred[d] = new_d
+            ud_new = 2.0 * u[d] - ud_prev + dt * dt * acc_d
+        ud_prev = u[d].copy()
+        u_new = u.copy()
+        u_new[d] = ud_new
         if len(c):
-            pred[c] = u[c] + dt * v_c + (0.5 - beta) * dt * dt * a_c
-            v_pred = v_c + (1.0 - gamma) * dt * a_c
-            a_c = sla.cho_solve(S_f, force(k + 1)[c] - Kc @ pred)
-            v_c = v_pred + gamma * dt * a_c
-            pred[c] = pred[c] + beta * dt * dt * a_c
-        u = pred
+            w = u[c] + dt * v_c + (0.5 - beta) * dt * dt * a_c
+            rhs = Mc @ w + bdt2 * (force(k + 1)[c] - Kcd @ ud_new)
+            uc_new = sla.cho_solve(S_f, rhs)
+            a_new = (uc_new - w) / bdt2
+            v_c = v_c + dt * ((1.0 - gamma) * a_c + gamma * a_new)
+            a_c = a_new
+            u_new[c] = uc_new
+        u = u_new
     return dict(u=u, v_c=v_c, a_c=a_c, c=c, d=d)
 
 

@@ -125,3 +125,57 @@ def test_consistent_cdm_energy_and_stability_limit():
     assert max(es) - min(es) <= 1e-10 * abs(es[0]), es
     grow = ox.cdm_consistent(disc, 1.05 * dtc, 600, u0=u0)["u"]
     assert np.abs(grow).max() > 1e3 * np.abs(u0).max()
+
+
+def _newmark_predictor_corrector(disc, split, dt, nsteps, src, beta=0.25, gamma=0.5):
+    """The implicit DOFs in the predictor-corrector (acceleration) form of the Newmark
+    relations, the explicit DOFs by central differences: an independent arrangement of
+    the same scheme as the oracle's displacement form."""
+    import scipy.linalg as sla
+    prob = disc.prob
+    c, d = split
+    m_dd, Mcc = ox.mass_matrices(disc, c, d)
+    K = problem.assembled_K(disc).toarray()
+    loads = [(problem.load_vector(disc, s), s["f0"]) for s in src]
+
+    def F(k):
+        out = np.zeros(prob.ndof)
+        for b, f0 in loads:
+            out += problem.ricker(k * dt, f0) * b
+        return out
+
+    M = Mcc.toarray()
+    u = np.zeros(prob.ndof)
+    v = np.zeros(len(c))
+    a = np.linalg.solve(M, F(0)[c] - K[c] @ u) if len(c) else np.zeros(0)
+    prev_d = None
+    for k in range(nsteps):
+        nd = u[d] + (0.5 if k == 0 else 1.0) * dt * dt * (F(k)[d] - K[d] @ u) / m_dd
+        if k > 0:
+            nd = nd + (u[d] - prev_d)
+        prev_d = u[d].copy()
+        pred = u.copy()
+        pred[d] = nd
+        if len(c):
+            pred[c] = u[c] + dt * v + (0.5 - beta) * dt * dt * a
+            vp = v + (1.0 - gamma) * dt * a
+            a = np.linalg.solve(M + beta * dt * dt * K[np.ix_(c, c)], F(k + 1)[c] - K[c] @ pred)
+            v = vp + gamma * dt * a
+            pred[c] += beta * dt * dt * a
+        u = pred
+    return u, v, a
+
+
+@pytest.mark.parametrize("mode", ["mixed", "all_implicit"])
+def test_displacement_form_equals_predictor_corrector(mode):
+    cfg, disc = _disc([(0.47, 0.52)], [0.23], alpha=1e-4)
+    c, d = ox.partition(disc)
+    if mode == "all_implicit":
+        c = np.sort(np.concatenate([c, d]))
+        d = np.zeros(0, dtype=np.int64)
+    src = [dict(x=(0.1, 0.1), f0=10.0, amp=1.0)]
+    dt = 0.5 * timestep.critical_dt(disc) if mode == "mixed" else 0.01
+    got = ox.imex(disc, dt, 60, sources=src, split=(c, d))
+    u, v, a = _newmark_predictor_corrector(disc, (c, d), dt, 60, src)
+    assert np.linalg.norm(got["u"] - u) <= 1e-9 * np.linalg.norm(u)
+    assert np.linalg.norm(got["v_c"] - v) <= 1e-8 * np.linalg.norm(v)
