@@ -88,7 +88,7 @@ def run_gpu(cfg, precision, steps, warmup, dt=None):
 
     s = Solver(cfg, precision=precision, device="cuda:0")
     if dt is None:
-        dt = 0.9 * s.critical_dt(max_iter=600, rtol=1e-7)
+        dt = 0.9 * s.critical_dt(max_iter=4000, rtol=1e-7)
     src = cfg["sources"]
     chosen, table = s.autotune(nrhs=1, nsteps=30)
     print(f"[bench] {precision} autotune: " + ", ".join(
@@ -245,7 +245,7 @@ def bench_imex(steps, warmup):
     cfg = workloads._base(2, (64, 64), 3, cc, rr, nsteps=steps)
     src = cfg["sources"]
     s = Solver(cfg, precision="fp64", device="cuda:0")
-    dt = 0.9 * s.critical_dt(max_iter=600, rtol=1e-7)
+    dt = 0.9 * s.critical_dt(max_iter=4000, rtol=1e-7)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nc = fcw.imex_prepare(s.ctx, dt)

@@ -104,8 +104,12 @@ fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out);
 fcw_status fcw_stabilize_cut_cells(fcw_ctx* ctx, double eps, double f_lambda);
 
 /* Critical step dt_crit = 2 / sqrt(lambda_max(K, M)) (Sec. 2.3) by FP64 Lanczos on
- * M^{-1/2} K M^{-1/2}, run until the largest Ritz value changes by less than rtol
- * between checks (or max_iter iterations).  Synchronises; writes *dt_crit. */
+ * M^{-1/2} K M^{-1/2} from a fixed pseudo-random start vector.  Every 20 iterations the
+ * largest Ritz value theta and the residual norm r = beta_k |s_k| of its Ritz pair are
+ * computed; the iteration stops once r <= rtol * theta, and lambda_max is taken as
+ * theta + r (Ritz values rise toward lambda_max from below, so the step errs on the safe
+ * side).  Returns FCW_E_NOCONV, leaving *dt_crit untouched, when max_iter iterations do
+ * not reach the tolerance.  Synchronises; writes *dt_crit. */
 fcw_status fcw_critical_dt(fcw_ctx* ctx, int32_t max_iter, double rtol, double* dt_crit);
 
 /* Advance nrhs independent right-hand sides by nsteps central-difference steps

@@ -106,7 +106,7 @@ struct Ctx {
   // cached graph of a batched run: valid for the same launch sequence
   hipGraphExec_t graph_exec = nullptr;
   const void* graph_fn = nullptr;
-  int graph_nitems = 0, graph_nsteps = 0;
+  int graph_nitems = 0, graph_nsteps = 0, graph_nprob = 0, graph_ncutprob = 0;
   int64_t graph_ncut = 0;
   void* graph_wl = nullptr;
   int64_t footprint = 0;

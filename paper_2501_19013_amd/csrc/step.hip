@@ -901,10 +901,13 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     return FCW_OK;
   }
   // graph replay: the records live in device memory, so a cached graph stays valid for
-  // the same kernels, item and cut-block counts, step count and work-list buffer
+  // the same kernels, work-list buffer and layout (member records, items and cut-cell
+  // records at the same offsets), cut-block count and step count
+  const int nprob = (int)m.size();
   if (!(owner.graph_exec && owner.graph_fn == (const void*)sc.f2d &&
         owner.graph_nitems == nitems && owner.graph_nsteps == nmax &&
-        owner.graph_ncut == ncutblk && owner.graph_wl == owner.d_wl)) {
+        owner.graph_ncut == ncutblk && owner.graph_wl == owner.d_wl &&
+        owner.graph_nprob == nprob && owner.graph_ncutprob == ncutprob)) {
     if (owner.graph_exec) FCW_HIP(hipGraphExecDestroy(owner.graph_exec));
     owner.graph_exec = nullptr;
     hipGraph_t g = nullptr;
@@ -922,6 +925,8 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
     owner.graph_nsteps = nmax;
     owner.graph_ncut = ncutblk;
     owner.graph_wl = owner.d_wl;
+    owner.graph_nprob = nprob;
+    owner.graph_ncutprob = ncutprob;
   }
   FCW_HIP(hipGraphLaunch(owner.graph_exec, owner.stream));
   return FCW_OK;

@@ -173,7 +173,7 @@ def stabilize_cut_cells(ctx, eps, f_lambda):
     _check(load().fcw_stabilize_cut_cells(ctx, float(eps), float(f_lambda)))
 
 
-def critical_dt(ctx, max_iter=400, rtol=1e-10):
+def critical_dt(ctx, max_iter=4000, rtol=1e-9):
     out = C.c_double()
     _check(load().fcw_critical_dt(ctx, int(max_iter), float(rtol), C.byref(out)))
     return out.value

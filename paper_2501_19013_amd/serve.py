@@ -113,7 +113,7 @@ class Server:
             try:
                 fcw.stabilize_cut_cells(ctx, req.cfg.get("eps", 1e-4),
                                         req.cfg.get("f_lambda", 1e-4))
-                dtc = fcw.critical_dt(ctx, 600, 1e-7)
+                dtc = fcw.critical_dt(ctx, 4000, 1e-7)
                 info = fcw.query(ctx)
                 nrhs = len(req.sources)
                 dtype = torch.float64 if self.precision == "fp64" else torch.float32

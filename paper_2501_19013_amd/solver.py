@@ -30,7 +30,7 @@ class Solver:
     def ndof(self):
         return self.info["ndof"]
 
-    def critical_dt(self, max_iter=600, rtol=1e-9):
+    def critical_dt(self, max_iter=4000, rtol=1e-9):
         dtc = fcw.critical_dt(self.ctx, max_iter, rtol)
         self.info = fcw.query(self.ctx)
         return dtc

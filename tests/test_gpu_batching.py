@@ -109,3 +109,45 @@ def test_finished_problem_drops_out(problems):
     torch.cuda.synchronize()
     assert np.array_equal(a[0].cpu().numpy(), ref0)
     assert np.array_equal(b[0].cpu().numpy(), ref1)
+
+
+def test_graph_cache_follows_member_layout():
+    # A graph captured for one work-list layout must not be replayed for another with
+    # the same item and step counts: five void-free members (one 64^2, four 32^2), then
+    # two 64^2 members, 64 items each with tile (21, 8); the second list fits the first's
+    # buffer, so only the member count tells the layouts apart.
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    stream = torch.cuda.Stream()
+    src = [dict(x=(0.13, 0.21), f0=10.0, amp=1.0)]
+
+    def solver(n):
+        cfg = workloads._base(2, (n, n), 3, np.zeros((0, 2)), np.zeros(0))
+        s = Solver(cfg, precision="fp32", stream=stream)
+        tiles = s.tile_configs()
+        i = next(k for k, t in enumerate(tiles) if tuple(t["tile"][:2]) == (21, 8))
+        s.select_tile(i)
+        return s
+
+    big = [solver(64), solver(64)]
+    small = [solver(32) for _ in range(4)]
+    dt = 1e-3
+    nsteps = 12
+
+    def run(members, use_graph):
+        st = [(s.zeros(1), s.zeros(1)) for s in members]
+        with torch.cuda.stream(stream):
+            fcw.run([dict(ctx=s.ctx, nrhs=1, u=u, d=d, sources=src, dt=dt, nsteps=nsteps,
+                          start=1) for s, (u, d) in zip(members, st)], graph=use_graph)
+        torch.cuda.synchronize()
+        return [u.cpu().numpy().copy() for u, _ in st]
+
+    first = [big[0]] + small
+    for a, b in zip(run(first, True), run(first, False)):
+        assert np.array_equal(a, b)
+    second = [big[0], big[1]]
+    for a, b in zip(run(second, True), run(second, False)):
+        assert np.array_equal(a, b)
+    for s in big + small:
+        s.close()

@@ -83,6 +83,31 @@ def test_c1_critical_dt(c1):
     s.close()
 
 
+def test_critical_dt_midsize():
+    # 128^2 cells p=4 (263k nodes) of the 2-D void field: the device Lanczos stops on the
+    # residual of its Ritz pair and reports theta + residual, which lies within rtol of
+    # the oracle's lambda_max and not below it
+    cfg = workloads.scaled_config(2, 128, 4, seed=2)
+    disc = problem.build(problem.Problem.from_config(cfg))
+    ref = timestep.critical_dt(disc)
+    s = _solver(cfg, "fp64")
+    dtc = s.critical_dt(max_iter=4000, rtol=1e-9)
+    s.close()
+    assert abs(dtc - ref) <= 1e-8 * ref
+    assert dtc <= ref * (1.0 + 1e-11)
+
+
+def test_critical_dt_reports_nonconvergence(c1):
+    # an iteration cap too small for the tolerance is an error, not a silent estimate
+    from paper_2501_19013_amd import fcw
+    cfg, _, _ = c1
+    s = _solver(cfg, "fp64")
+    with pytest.raises(fcw.FcwError) as e:
+        fcw.critical_dt(s.ctx, 20, 1e-15)
+    assert e.value.status == fcw.FCW_E_NOCONV
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_c1_stiffness_action(c1, precision):
     import torch
