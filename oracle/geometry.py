@@ -57,7 +57,7 @@ def box_status(lo, hi, centers, radii):
 
 
 def classify_cells(prob):
-    """Class of every cell of the grid (paper Sec. 2.2 and Sec. 3.3: cells that lie
+    """Class of every cell of the grid (paper Sec. 2.2 and Sec. 3.2.2: cells that lie
     entirely outside the physical domain are disregarded).  Vectorised over cells,
     same predicates as ``box_status``.  Returns int8 array in lexicographic cell
     order (x fastest)."""
