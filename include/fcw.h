@@ -125,6 +125,24 @@ fcw_status fcw_step_explicit(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
                              const fcw_source* src, double t0, double dt,
                              int32_t nsteps, int32_t start);
 
+/* Size in bytes of the fixed device work array of fcw_step_explicit_noalloc (64 MiB; each
+ * device the library runs on holds one until the process ends). */
+#define FCW_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory during the call (tight serving loops,
+ * harnesses that forbid hipMalloc): fcw_step_explicit with the same arguments, results
+ * and errors, whose work areas (load vectors, cut-cell products, the ping-pong partner
+ * of u) live in one fixed per-device array of FCW_NOALLOC_SCRATCH_BYTES instead of
+ * buffers the context allocates.  It calls no hipMalloc / hipFree.  Needs about
+ * nrhs * ndof * state bytes + nrhs * n_cut * n_loc * state bytes + 136 KiB; larger calls
+ * return FCW_E_ARG (fcw_step_explicit serves them).  Every call on one device shares
+ * that device's array: calls that overlap on one device (from other threads or on other
+ * streams) race; calls in sequence on one stream do not.  With sources the call
+ * synchronises its stream once while it stages their load vectors. */
+fcw_status fcw_step_explicit_noalloc(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
+                                     const fcw_source* src, double t0, double dt,
+                                     int32_t nsteps, int32_t start);
+
 /* One problem's share of a batched run (fcw_run). */
 typedef struct {
   fcw_ctx* ctx;

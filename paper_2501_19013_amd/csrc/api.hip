@@ -118,6 +118,37 @@ static fcw_status time_captured(Ctx& c, hipEvent_t e0, hipEvent_t e1, F queue) {
   return e == hipSuccess ? FCW_OK : hip_fail(e, "kernel timing replay");
 }
 
+// checks of one problem's step call
+fcw_status check_step_call(const fcw_ctx* c, int32_t nrhs, const void* u, const void* d,
+                           const fcw_source* src, double dt, int32_t nsteps) {
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > 64 || !u || !d || !(dt > 0.0) || nsteps < 0) {
+    set_error("invalid arguments (nrhs in [1,64], u, d non-null, dt > 0, nsteps >= 0)");
+    return FCW_E_ARG;
+  }
+  if (src) {
+    for (int s = 0; s < nrhs; ++s) {
+      for (int k = 0; k < c->dim; ++k)
+        if (!(src[s].x[k] >= c->lo[k] && src[s].x[k] <= c->hi[k])) {
+          set_error("source %d outside the box", s);
+          return FCW_E_ARG;
+        }
+      if (in_any_void(*c, src[s].x)) {
+        set_error("source %d lies inside a void", s);
+        return FCW_E_ARG;
+      }
+      if (!(src[s].f0 > 0.0)) {
+        set_error("source %d needs f0 > 0", s);
+        return FCW_E_ARG;
+      }
+    }
+  }
+  return FCW_OK;
+}
+
+void clear_error() { g_err.clear(); }
+
 }  // namespace fcw
 
 using namespace fcw;
@@ -295,30 +326,9 @@ fcw_status fcw_critical_dt(fcw_ctx* c, int32_t max_iter, double rtol, double* dt
 // checks of one problem's step call; prepares its sources and scratch
 static fcw_status prepare_call(fcw_ctx* c, int32_t nrhs, void* u, void* d, const fcw_source* src,
                                double dt, int32_t nsteps) {
-  fcw_status st = check_ctx(c, 2);
+  fcw_status st = check_step_call(c, nrhs, u, d, src, dt, nsteps);
   if (st) return st;
-  if (nrhs < 1 || nrhs > 64 || !u || !d || !(dt > 0.0) || nsteps < 0) {
-    set_error("invalid arguments (nrhs in [1,64], u, d non-null, dt > 0, nsteps >= 0)");
-    return FCW_E_ARG;
-  }
-  if (src) {
-    for (int s = 0; s < nrhs; ++s) {
-      for (int k = 0; k < c->dim; ++k)
-        if (!(src[s].x[k] >= c->lo[k] && src[s].x[k] <= c->hi[k])) {
-          set_error("source %d outside the box", s);
-          return FCW_E_ARG;
-        }
-      if (in_any_void(*c, src[s].x)) {
-        set_error("source %d lies inside a void", s);
-        return FCW_E_ARG;
-      }
-      if (!(src[s].f0 > 0.0)) {
-        set_error("source %d needs f0 > 0", s);
-        return FCW_E_ARG;
-      }
-    }
-    if ((st = prepare_sources(*c, nrhs, src))) return st;
-  }
+  if (src && (st = prepare_sources(*c, nrhs, src))) return st;
   const size_t bytes = (size_t)nrhs * c->ndof * c->state_bytes();
   if (c->ubuf_bytes < bytes) {
     dfree(c->d_ubuf);

@@ -136,6 +136,7 @@ __host__ __device__ inline T analytic_invm(double cm, double iwx, double iwy, do
 
 // error reporting (thread-local message)
 void set_error(const char* fmt, ...);
+void clear_error();
 fcw_status hip_fail(hipError_t e, const char* what);
 
 #define FCW_HIP(call)                                      \
@@ -152,7 +153,10 @@ fcw_status setup_integrate(Ctx& c);
 fcw_status setup_reclassify(Ctx& c);
 fcw_status setup_stabilize(Ctx& c, double eps, double f_lambda);
 fcw_status setup_mass_and_pack(Ctx& c);
-fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src);
+// Load vectors of nrhs point sources into c.d_src (allocated on first use when null).
+// remember: skip the work when the sources equal the last staged ones, and record them.
+constexpr int kMaxSrc = 64;
+fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src, bool remember = true);
 // exclusive scan of n int32 on the context's stream; the total goes to *total_host (syncs)
 fcw_status exclusive_scan(Ctx& c, const int32_t* in, int32_t* out, int64_t n,
                           int32_t* total_host);
@@ -162,6 +166,9 @@ fcw_status imex_prepare(Ctx& c, double dt);
 // consistent: central differences with the consistent cut-DOF mass instead (v_c, a_c unused)
 fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double* a_c, double t0,
                     double dt, int nsteps, int start, bool consistent);
+// api.hip: argument checks of a step call (no allocation, nothing enqueued)
+fcw_status check_step_call(const fcw_ctx* c, int32_t nrhs, const void* u, const void* d,
+                           const fcw_source* src, double dt, int32_t nsteps);
 // cutcell.hip: cut-cell products y = K_e u_e, once per cut cell and step
 fcw_status ensure_ycut(Ctx& c, int nrhs);
 size_t cutprob_size(int fp64);

@@ -1603,9 +1603,7 @@ __global__ void source_kernel(SrcArgs a) {
   o.f0 = in.f0;
 }
 
-constexpr int kMaxSrc = 64;
-
-fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src) {
+fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src, bool remember) {
   if (nrhs > kMaxSrc) {
     set_error("at most %d right-hand sides per call (got %d)", kMaxSrc, nrhs);
     return FCW_E_ARG;
@@ -1617,7 +1615,7 @@ fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src) {
     c.footprint += kMaxSrc * (sizeof(SourceDev) + sizeof(fcw_source));
   }
   // unchanged sources (the usual case for a run split into several calls) are kept
-  if ((int)c.src_staged.size() == nrhs &&
+  if (remember && (int)c.src_staged.size() == nrhs &&
       std::memcmp(c.src_staged.data(), src, nrhs * sizeof(fcw_source)) == 0)
     return FCW_OK;
   c.src_staged.clear();
@@ -1647,7 +1645,7 @@ fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src) {
   FCW_HIP(hipGetLastError());
   // the staged host array must stay valid until the copy has run
   FCW_HIP(hipStreamSynchronize(c.stream));
-  c.src_staged.assign(src, src + nrhs);
+  if (remember) c.src_staged.assign(src, src + nrhs);
   return FCW_OK;
 }
 

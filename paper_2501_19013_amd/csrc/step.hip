@@ -950,16 +950,19 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
     const int64_t ncutblk = cutprob_fill(c, crec, u, scratch, nrhs, nsteps, 0);
     const int ntx = (c.ncells[0] + sc.tile[0] - 1) / sc.tile[0];
     const int nty = (c.ncells[1] + sc.tile[1] - 1) / sc.tile[1];
-    std::vector<char> rec(prob2d_size(fp64));
-    prob2d_fill(c, rec.data(), u, scratch, d, t0, dt, nsteps, start, sc.tile[0], sc.tile[1],
-                c.d_src);
+    alignas(16) char rec[256];
+    if (prob2d_size(fp64) > sizeof rec) {
+      set_error("2-D problem record larger than its buffer");
+      return FCW_E_DEVICE;
+    }
+    prob2d_fill(c, rec, u, scratch, d, t0, dt, nsteps, start, sc.tile[0], sc.tile[1], c.d_src);
     // one problem: its record goes by value, items are implicit (tile-major, rhs fastest)
     const int nitems = ntx * nty * nrhs;
     for (int j = 0; j < nsteps; ++j) {
       if (c.n_cut_cand > 0 && !c.skip_cut &&
           (st = launch_cut(c, c.stream, nullptr, 1, crec, ncutblk, j)))
         return st;
-      if ((st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec.data(), nrhs))) return st;
+      if ((st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec, nrhs))) return st;
     }
     return FCW_OK;
   }

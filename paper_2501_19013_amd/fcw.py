@@ -24,7 +24,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32, ARR_IMEX_DOFS: n
 
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
-           "fcw_step_explicit", "fcw_imex_prepare", "fcw_step_imex", "fcw_step_consistent",
+           "fcw_step_explicit", "fcw_step_explicit_noalloc", "fcw_imex_prepare", "fcw_step_imex", "fcw_step_consistent",
            "fcw_apply_stiffness",
            "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
@@ -86,6 +86,8 @@ def load(path=LIB_PATH):
     lib.fcw_stabilize_cut_cells.argtypes = [vp, f64, f64]
     lib.fcw_critical_dt.argtypes = [vp, i32, f64, C.POINTER(f64)]
     lib.fcw_step_explicit.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
+    lib.fcw_step_explicit_noalloc.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32,
+                                              i32]
     lib.fcw_imex_prepare.argtypes = [vp, f64, C.POINTER(C.c_int64)]
     lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_step_consistent.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
@@ -183,6 +185,17 @@ def step_explicit(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):
     srcs = _sources(sources)
     _check(load().fcw_step_explicit(ctx, int(nrhs), _ptr(u), _ptr(d), srcs, float(t0),
                                     float(dt), int(nsteps), int(start)))
+
+
+def step_explicit_noalloc(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):
+    """fcw_step_explicit_noalloc: the explicit step with its work areas in the library's
+    fixed per-device array (no device allocation during the call)."""
+    srcs = _sources(sources)
+    _check(load().fcw_step_explicit_noalloc(ctx, int(nrhs), _ptr(u), _ptr(d), srcs, float(t0),
+                                            float(dt), int(nsteps), int(start)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def imex_prepare(ctx, dt):
