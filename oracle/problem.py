@@ -237,6 +237,21 @@ def load_vector(disc, src):
     return b
 
 
+def receiver_rows(disc, points):
+    """Observers (Sec. 3.2, observer traces): a matrix R with one row per (point, component),
+    row r * ncomp + comp, such that (R u)[row] = u_h(x_r) of that component, the finite
+    element field sum_a N_a(x_r) u_a of a cell containing x_r (the cell rule of the point
+    sources; the field is continuous, so any such cell gives the same row)."""
+    prob = disc.prob
+    pts = np.asarray(points, dtype=np.float64).reshape(-1, prob.dim)
+    R = np.zeros((len(pts) * prob.ncomp, prob.ndof))
+    for r, x in enumerate(pts):
+        cell, N = source_cell_and_values(prob, x)
+        for comp in range(prob.ncomp):
+            R[r * prob.ncomp + comp, disc.cell_nodes[cell] + comp * prob.nnodes] = N
+    return R
+
+
 def ricker(t, f0):
     """Ricker wavelet, eq. source_time: (1 - 2 q^2) exp(-q^2), q = pi f0 (t - t_s),
     t_s = 2 sqrt(6) / (pi f0)."""
@@ -245,26 +260,43 @@ def ricker(t, f0):
     return (1.0 - 2.0 * q * q) * math.exp(-q * q)
 
 
-def apply_K(disc, u):
-    """K u element by element (eq. semi): sum over uncut cells of P_e^T K_ref P_e u
-    plus the cut cells with their own matrices.  u: (ndof,) or (ndof, nrhs)."""
-    prob = disc.prob
+def _cell_dof_tables(disc):
+    """(uncut DOF table, cut DOF table) as torch int64 tensors, built once per problem."""
+    import torch
+    cached = getattr(disc, "_dof_tables", None)
+    if cached is None:
+        cached = tuple(torch.from_numpy(np.ascontiguousarray(disc.cell_dofs(cells)))
+                       for cells in (disc.uncut_cells, disc.cut_cells))
+        disc._dof_tables = cached
+    return cached
+
+
+def apply_K(disc, u, out=None):
+    """K u element by element (eq. semi): the sum over uncut cells of P_e^T K_ref P_e u
+    plus the cut cells with their own matrices.  The gather P_e u, the element products
+    and the scatter-add P_e^T are torch CPU indexing, matmul and index_add (library
+    primitives; the order in which the element contributions add up at a node is left to
+    the library).  u: (ndof,) or (ndof, nrhs); ``out`` (same shape) receives the result."""
+    import torch
     u = np.asarray(u, dtype=np.float64)
     vec = u.ndim == 1
-    U = u[:, None] if vec else u
-    out = np.zeros_like(U)
-    for cells, mats in ((disc.uncut_cells, None), (disc.cut_cells, disc.K_cut)):
-        if len(cells) == 0:
+    U = torch.from_numpy(np.ascontiguousarray(u[:, None] if vec else u))
+    if out is None:
+        res = np.zeros(u.shape)
+    else:
+        res = out
+        res[...] = 0.0
+    R = torch.from_numpy(res[:, None] if vec else res)
+    for dofs, mats in zip(_cell_dof_tables(disc), (None, disc.K_cut)):
+        if dofs.shape[0] == 0:
             continue
-        dofs = disc.cell_dofs(cells)
-        for r in range(U.shape[1]):
-            ue = U[dofs, r]
-            if mats is None:
-                ye = ue @ disc.K_ref.T
-            else:
-                ye = np.einsum("eij,ej->ei", mats, ue)
-            out[:, r] += np.bincount(dofs.ravel(), weights=ye.ravel(), minlength=prob.ndof)
-    return out[:, 0] if vec else out
+        ue = U[dofs]                                        # (cells, n_loc, nrhs)
+        if mats is None:
+            ye = torch.matmul(torch.from_numpy(disc.K_ref), ue)
+        else:
+            ye = torch.bmm(torch.from_numpy(mats), ue)
+        R.index_add_(0, dofs.reshape(-1), ye.reshape(-1, U.shape[1]))
+    return res
 
 
 def assembled_K(disc):

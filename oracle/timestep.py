@@ -4,7 +4,6 @@
 * Central differences, eq. cdm:  u_{k+1} = 2 u_k - u_{k-1} + dt^2 M^{-1} (F_k - K u_k),
   started as the Newmark predictor-corrector with beta = 0, gamma = 1/2 (Alg. newmark):
   a_0 = M^{-1}(F_0 - K u_0),  u_1 = u_0 + dt v_0 + dt^2/2 a_0.
-* Step size rule of Sec. 3.3: dt = min(0.9 dt_crit, dt_max).
 
 M is the assembled diagonal (lumped) mass; DOFs without mass are inactive and kept 0.
 
@@ -46,30 +45,38 @@ def critical_dt(disc, **kw):
     return 2.0 / math.sqrt(lambda_max(disc, **kw))
 
 
-def choose_dt(dt_crit, factor=0.9, dt_max=math.inf):
-    """Sec. 3.3: dt = min(0.9 dt_crit, dt_max)."""
-    return min(factor * dt_crit, dt_max)
-
-
 def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
-        receivers=None):
+        receivers=None, progress=None):
     """Run ``nsteps`` central-difference steps (eq. cdm) with the Newmark (beta=0)
     start-up.  ``sources``: list of dicts (x, dir, amp, f0); every source adds
     f_t(t_k) b to F_k.  Several right-hand sides are run by calling this once per
     source set.  Returns dict with the final u, the previous u, the states at the
     requested checkpoint step numbers, and receiver traces (one row per step k=0..n).
+    ``progress(k)``, if given, is called after step k.
+
+    Each step works in place on three state-sized arrays (a point load is nonzero on
+    one cell's DOFs only, so F_k is added where it is nonzero):
+        a   = M^{-1} (F_k - K u_k)
+        u_{k+1} = 2 u_k - u_{k-1} + dt^2 a   (written over u_{k-1}).
     """
     prob = disc.prob
     im = disc.inv_mass_dof()
     u = np.zeros(prob.ndof) if u0 is None else np.array(u0, dtype=np.float64)
     v = np.zeros(prob.ndof) if v0 is None else np.array(v0, dtype=np.float64)
-    loads = [(load_vector(disc, s), float(s.get("f0", 10.0))) for s in sources]
+    loads = []
+    for s in sources:
+        b = load_vector(disc, s)
+        nz = np.flatnonzero(b)
+        loads.append((nz, b[nz], float(s.get("f0", 10.0))))
 
-    def force(k):
-        F = np.zeros(prob.ndof)
-        for b, f0 in loads:
-            F += ricker(t0 + k * dt, f0) * b
-        return F
+    def accel(k, u_k, out):
+        """out = M^{-1} (F_k - K u_k)."""
+        apply_K(disc, u_k, out=out)
+        np.negative(out, out=out)
+        for nz, bv, f0 in loads:
+            out[nz] += ricker(t0 + k * dt, f0) * bv
+        out *= im
+        return out
 
     snaps = {}
     trace = []
@@ -81,22 +88,32 @@ def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
     if nsteps == 0:
         return dict(u=u, u_prev=u - dt * v, snapshots=snaps,
                     trace=None if rec is None else np.array(trace))
-    a0 = im * (force(0) - apply_K(disc, u))
+    a = accel(0, u, np.empty(prob.ndof))
     u_prev = u
-    u = u + dt * v + 0.5 * dt * dt * a0
+    u = u + dt * v + 0.5 * dt * dt * a
     k = 1
     if k in checkpoints:
         snaps[k] = u.copy()
     if rec is not None:
         trace.append(rec @ u)
+    if progress:
+        progress(k)
+    u_prev = u_prev.copy()
     while k < nsteps:
-        u_next = 2.0 * u - u_prev + dt * dt * im * (force(k) - apply_K(disc, u))
-        u_prev, u = u, u_next
+        accel(k, u, a)
+        # u_{k+1} = 2 u_k - u_{k-1} + dt^2 a, stored in the array of u_{k-1}
+        np.subtract(u, u_prev, out=u_prev)
+        u_prev += u
+        a *= dt * dt
+        u_prev += a
+        u_prev, u = u, u_prev
         k += 1
         if k in checkpoints:
             snaps[k] = u.copy()
         if rec is not None:
             trace.append(rec @ u)
+        if progress:
+            progress(k)
     return dict(u=u, u_prev=u_prev, snapshots=snaps,
                 trace=None if rec is None else np.array(trace))
 
