@@ -130,18 +130,30 @@ fcw_status fcw_step_explicit(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
 #define FCW_NOALLOC_SCRATCH_BYTES (64u << 20)
 
 /* For callers that cannot allocate device memory during the call (tight serving loops,
- * harnesses that forbid hipMalloc): fcw_step_explicit with the same arguments, results
- * and errors, whose work areas (load vectors, cut-cell products, the ping-pong partner
- * of u) live in one fixed per-device array of FCW_NOALLOC_SCRATCH_BYTES instead of
- * buffers the context allocates.  It calls no hipMalloc / hipFree.  Needs about
- * nrhs * ndof * state bytes + nrhs * n_cut * n_loc * state bytes + 136 KiB; larger calls
- * return FCW_E_ARG (fcw_step_explicit serves them).  Every call on one device shares
- * that device's array: calls that overlap on one device (from other threads or on other
- * streams) race; calls in sequence on one stream do not.  With sources the call
- * synchronises its stream once while it stages their load vectors. */
+ * harnesses that forbid hipMalloc): fcw_step_explicit with
+ * the same arguments, results and errors, whose work areas (load vectors, cut-cell
+ * products, the ping-pong partner of u) live in one fixed per-device array of
+ * FCW_NOALLOC_SCRATCH_BYTES instead of buffers the context allocates.  It calls no
+ * hipMalloc / hipFree.  Needs about nrhs * ndof * state bytes + nrhs * n_cut * n_loc *
+ * state bytes + 136 KiB; larger calls return FCW_E_ARG (fcw_step_explicit serves them).
+ * Every call on one device shares that device's array: calls that overlap on one device
+ * (from other threads or on other streams) race; calls in sequence on one stream do not.
+ * With sources the call synchronises its stream once while it stages their load vectors. */
 fcw_status fcw_step_explicit_noalloc(fcw_ctx* ctx, int32_t nrhs, void* u, void* d,
                                      const fcw_source* src, double t0, double dt,
                                      int32_t nsteps, int32_t start);
+
+/* Outcome of one problem of a batched run (fcw_run), written when the call returns. */
+typedef struct {
+  int32_t status;      /* FCW_OK, or FCW_E_UNSTABLE when growth was detected (see fcw_run) */
+  int32_t steps_done;  /* steps taken; below nsteps when the problem was stopped early */
+  double dt_used;      /* the step size of the run (after the dt <= 0 rule) */
+  double growth;       /* last ratio of the mass-free increment norms sum d_i^2 between two
+                          checks (0 before the second check or without checks) */
+} fcw_run_result;
+
+/* Largest number of receivers of one problem in a run. */
+#define FCW_MAX_RECEIVERS 64
 
 /* One problem's share of a batched run (fcw_run). */
 typedef struct {
@@ -151,9 +163,31 @@ typedef struct {
   void* d;                /* device [nrhs][ndof], in/out (dt * v_0 on a start call) */
   const fcw_source* src;  /* host [nrhs] or NULL */
   double t0;              /* time of the first step of this call */
-  double dt;              /* step; <= 0 means 0.9 * dt_crit (fcw_critical_dt must have run) */
+  double dt;              /* step; <= 0 selects the rule of Sec. 3.3,
+                             dt = min(0.9 dt_crit, dt_max) (fcw_critical_dt must have run) */
+  double dt_max;          /* cap of that rule; <= 0 means none */
   int32_t nsteps;         /* steps of this problem (problems may differ) */
   int32_t start;          /* nonzero on the first call of a run (Newmark beta = 0 start-up) */
+  /* Observers (Sec. 3.2, observer traces): nrec points (host [nrec][3], copied; 0 <= nrec
+   * <= FCW_MAX_RECEIVERS; each inside the box and in no void).  The finite element field
+   * u_h(x_r) = sum_a N_a(x_r) u_a of the cell holding x_r (the same cell rule as for
+   * sources) is written for the state before the first step and after every step:
+   * traces is device double [nrhs][nsteps + 1][nrec][ncomp]; row k holds u_k of this call
+   * (row 0 = the state passed in).  NULL / 0: no traces. */
+  int32_t nrec;
+  const double* rec_x;
+  double* traces;
+  /* Growth detection (Sec. 2.3 stability limit): every check_every steps the library
+   * computes s = sum_i d_i^2 per right-hand side (FP64) and synchronises.  The problem is
+   * stopped with FCW_E_UNSTABLE when s is not finite or when s grew by more than 1e6 over
+   * each of three consecutive check intervals (a Ricker onset from rest can do neither:
+   * its amplitude grows by at most e^24 in total, concentrated at the start; a step
+   * above dt_crit amplifies the highest mode by a factor above one per step).  0: no
+   * checks.  Items that check must share one check_every. */
+  int32_t check_every;
+  fcw_run_result* result; /* host, may be NULL */
+  double* energy;         /* host [nrhs] or NULL: discrete energy after the last step,
+                             E = 1/2 v^T M v + 1/2 u_{k+1}^T K u_k with v = d / dt */
 } fcw_run_item;
 
 enum { FCW_RUN_GRAPH = 1 };
@@ -164,8 +198,12 @@ enum { FCW_RUN_GRAPH = 1 };
  * finished their steps drop out of later launches.  Other problems run one after
  * another.  All work goes on the stream of the first problem's context.  With
  * FCW_RUN_GRAPH the launches of a group are captured once into a HIP graph and replayed
- * (the graph is cached and reused while the group's shape is unchanged).  Sources,
- * state layout and errors as in fcw_step_explicit. */
+ * (the graph is cached and reused while the group's shape is unchanged); a group with
+ * receivers or growth checks runs without a graph.  Sources, state layout and errors as
+ * in fcw_step_explicit.  The call synchronises when an item checks growth, asks for the
+ * energy or has a result to fill; an unstable problem stops at the check that found it
+ * (its state is that of the check) while the others go on, and the call then returns
+ * FCW_E_UNSTABLE (every result says which problems). */
 fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags);
 
 /* Autotuner of the step kernel: times every compiled tile configuration for this

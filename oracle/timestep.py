@@ -14,7 +14,6 @@ from __future__ import annotations
 import math
 
 import numpy as np
-import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .problem import apply_K, assembled_K, load_vector, ricker
@@ -28,12 +27,20 @@ def lambda_max(disc, dense_limit=6000, tol=1e-12):
     im = disc.inv_mass_dof()
     act = np.flatnonzero(im > 0)
     s = np.sqrt(im[act])
-    K = assembled_K(disc)[act][:, act]
     if len(act) <= dense_limit:
+        K = assembled_K(disc)[act][:, act]
         A = (K.toarray() * s[:, None]) * s[None, :]
         return float(np.linalg.eigvalsh(0.5 * (A + A.T))[-1])
-    S = sp.diags(s)
-    A = (S @ K @ S).tocsr()
+    # x -> M^{-1/2} K M^{-1/2} x on the active DOFs, K applied element by element
+    full = np.zeros(prob.ndof)
+    ku = np.zeros(prob.ndof)
+
+    def matvec(x):
+        full[act] = s * np.ravel(x)
+        apply_K(disc, full, out=ku)
+        return s * ku[act]
+
+    A = spla.LinearOperator((len(act), len(act)), matvec=matvec, dtype=np.float64)
     v0 = np.ones(len(act))
     vals = spla.eigsh(A, k=1, which="LA", tol=tol, v0=v0, return_eigenvectors=False,
                       ncv=64, maxiter=20000)
@@ -46,13 +53,15 @@ def critical_dt(disc, **kw):
 
 
 def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
-        receivers=None, progress=None):
+        receivers=None, progress=None, resume=None):
     """Run ``nsteps`` central-difference steps (eq. cdm) with the Newmark (beta=0)
     start-up.  ``sources``: list of dicts (x, dir, amp, f0); every source adds
     f_t(t_k) b to F_k.  Several right-hand sides are run by calling this once per
     source set.  Returns dict with the final u, the previous u, the states at the
     requested checkpoint step numbers, and receiver traces (one row per step k=0..n).
-    ``progress(k)``, if given, is called after step k.
+    ``progress(k)``, if given, is called after step k.  ``resume``: the dict returned by
+    an earlier call with the same disc, dt, sources and t0; the run then continues
+    from its last step (no start-up) up to step ``nsteps`` of the whole run.
 
     Each step works in place on three state-sized arrays (a point load is nonzero on
     one cell's DOFs only, so F_k is added where it is nonzero):
@@ -81,12 +90,17 @@ def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
     snaps = {}
     trace = []
     rec = None if receivers is None else np.asarray(receivers)
+    if resume is not None:
+        u_prev, u, k = resume["u_prev"], resume["u"], resume["k"]
+        a = np.empty(prob.ndof)
+        return _cdm_loop(k, nsteps, u_prev, u, a, accel, dt, checkpoints, snaps, rec, trace,
+                         progress)
     if 0 in checkpoints:
         snaps[0] = u.copy()
     if rec is not None:
         trace.append(rec @ u)
     if nsteps == 0:
-        return dict(u=u, u_prev=u - dt * v, snapshots=snaps,
+        return dict(u=u, u_prev=u - dt * v, k=0, snapshots=snaps,
                     trace=None if rec is None else np.array(trace))
     a = accel(0, u, np.empty(prob.ndof))
     u_prev = u
@@ -98,7 +112,12 @@ def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
         trace.append(rec @ u)
     if progress:
         progress(k)
-    u_prev = u_prev.copy()
+    return _cdm_loop(k, nsteps, u_prev.copy(), u, a, accel, dt, checkpoints, snaps, rec, trace,
+                     progress)
+
+
+def _cdm_loop(k, nsteps, u_prev, u, a, accel, dt, checkpoints, snaps, rec, trace, progress):
+    """Steps k -> nsteps of eq. cdm from (u_{k-1}, u_k)."""
     while k < nsteps:
         accel(k, u, a)
         # u_{k+1} = 2 u_k - u_{k-1} + dt^2 a, stored in the array of u_{k-1}
@@ -114,7 +133,7 @@ def cdm(disc, dt, nsteps, sources=(), u0=None, v0=None, t0=0.0, checkpoints=(),
             trace.append(rec @ u)
         if progress:
             progress(k)
-    return dict(u=u, u_prev=u_prev, snapshots=snaps,
+    return dict(u=u, u_prev=u_prev, k=k, snapshots=snaps,
                 trace=None if rec is None else np.array(trace))
 
 

@@ -6,6 +6,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
+#include <vector>
+#include <algorithm>
 
 #include "common.h"
 
@@ -51,6 +54,10 @@ static void free_all(Ctx& c) {
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
   dfree(c.d_invw); dfree(c.d_mflag); dfree(c.d_kref_bf);
   dfree(c.d_src);
+  dfree(c.d_rec);
+  dfree(c.d_red);
+  if (c.h_red) (void)hipHostFree(c.h_red);
+  c.h_red = nullptr;
   imex_free(c);
   dfree(c.d_wl);
   if (c.h_wl) (void)hipHostFree(c.h_wl);
@@ -349,54 +356,198 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
   fcw_ctx* owner = items[0].ctx;
   fcw_status st = check_ctx(owner, 2);
   if (st) return st;
-  // validate and prepare every member first (no work is enqueued on error)
-  std::vector<GroupMember> group;
-  std::vector<int> solo;
+  // validate and prepare every member first (no step is enqueued on error)
   std::vector<double> dts(n);
+  int check_every = 0;
+  bool any_rec = false, sync_end = false;
   for (int i = 0; i < n; ++i) {
     const fcw_run_item& r = items[i];
     if (!r.ctx) { set_error("run item %d has no context", i); return FCW_E_ARG; }
     double dt = r.dt;
     if (!(dt > 0.0)) {
+      // step size rule of Sec. 3.3: dt = min(0.9 dt_crit, dt_max)
       if (!(r.ctx->dt_crit > 0.0)) {
         set_error("run item %d: dt <= 0 needs fcw_critical_dt first", i);
         return FCW_E_STATE;
       }
       dt = 0.9 * r.ctx->dt_crit;
+      if (r.dt_max > 0.0 && r.dt_max < dt) dt = r.dt_max;
     }
     dts[i] = dt;
     for (int k = 0; k < i; ++k)
       if (items[k].ctx == r.ctx) { set_error("context listed twice in one run"); return FCW_E_ARG; }
-    if ((st = prepare_call(r.ctx, r.nrhs, r.u, r.d, r.src, dt, r.nsteps))) return st;
-    if (!r.src) r.ctx->d_src_active = false;
-    else r.ctx->d_src_active = true;
-    if (groupable_2d(*owner, *r.ctx))
-      group.push_back(GroupMember{r.ctx, r.nrhs, r.u, r.d, r.ctx->d_ubuf, r.t0, dt, r.nsteps,
-                                  r.start});
-    else
-      solo.push_back(i);
+    if (r.nrec < 0 || r.nrec > FCW_MAX_RECEIVERS || (r.nrec > 0 && (!r.rec_x || !r.traces))) {
+      set_error("run item %d: need 0 <= nrec <= %d, and points and a trace buffer with nrec > 0",
+                i, FCW_MAX_RECEIVERS);
+      return FCW_E_ARG;
+    }
+    for (int q = 0; q < r.nrec; ++q) {
+      const double* x = r.rec_x + 3 * q;
+      for (int k = 0; k < r.ctx->dim; ++k)
+        if (!(x[k] >= r.ctx->lo[k] && x[k] <= r.ctx->hi[k])) {
+          set_error("run item %d: receiver %d outside the box", i, q);
+          return FCW_E_ARG;
+        }
+      if (in_any_void(*r.ctx, x)) {
+        set_error("run item %d: receiver %d lies inside a void", i, q);
+        return FCW_E_ARG;
+      }
+    }
+    if (r.check_every < 0 || (r.check_every > 0 && check_every > 0 && r.check_every != check_every)) {
+      set_error("run item %d: check_every must be >= 0 and the same for every item that checks", i);
+      return FCW_E_ARG;
+    }
+    if (r.check_every > 0) check_every = r.check_every;
+    any_rec = any_rec || r.nrec > 0;
+    sync_end = sync_end || r.result || r.energy || r.check_every > 0;
+    if ((st = check_step_call(r.ctx, r.nrhs, r.u, r.d, r.src, dt, r.nsteps))) return st;
   }
-  // the group runs on the owner's stream; sources of members without any are hidden
-  std::vector<SourceDev*> saved;
-  for (auto& g : group) {
-    saved.push_back(g.ctx->d_src);
-    if (!g.ctx->d_src_active) g.ctx->d_src = nullptr;
-  }
-  if (!group.empty()) st = run_group(*owner, group, (flags & FCW_RUN_GRAPH) != 0);
-  for (size_t k = 0; k < group.size(); ++k) group[k].ctx->d_src = saved[k];
-  if (st) return st;
-  for (int i : solo) {
+  for (int i = 0; i < n; ++i) {
     const fcw_run_item& r = items[i];
+    if ((st = prepare_call(r.ctx, r.nrhs, r.u, r.d, r.src, dts[i], r.nsteps))) return st;
+    r.ctx->d_src_active = r.src != nullptr;
+    if (r.nrec > 0 && (st = prepare_receivers(*r.ctx, r.nrec, r.rec_x))) return st;
+  }
+  // per item: steps done, outcome, growth-check history per right-hand side
+  struct ItemRun {
+    int done = 0;
+    fcw_status status = FCW_OK;
+    double growth = 0.0;
+    std::vector<double> prev;
+    std::vector<int> streak;
+  };
+  std::vector<ItemRun> ir(n);
+  int maxsteps = 0;
+  for (int i = 0; i < n; ++i) {
+    ir[i].prev.assign(items[i].nrhs, 0.0);
+    ir[i].streak.assign(items[i].nrhs, 0);
+    maxsteps = std::max(maxsteps, items[i].nsteps);
+  }
+  const int chunk = check_every > 0 ? check_every : std::max(maxsteps, 1);
+  const bool graph = (flags & FCW_RUN_GRAPH) != 0 && !any_rec;
+  struct HookArg {
+    std::vector<TraceTarget> t;
+  };
+  auto hook_fn = [](void* arg, hipStream_t s, int j) -> fcw_status {
+    HookArg* h = static_cast<HookArg*>(arg);
+    return launch_traces(s, h->t.data(), (int)h->t.size(), j);
+  };
+  for (;;) {
+    // the next chunk of steps of every problem still running
+    std::vector<GroupMember> group;
+    std::vector<int> solo, cnt(n, 0);
+    HookArg ghook;
+    bool more = false;
+    for (int i = 0; i < n; ++i) {
+      const fcw_run_item& r = items[i];
+      if (ir[i].status != FCW_OK) continue;
+      const int k = std::min(chunk, r.nsteps - ir[i].done);
+      if (k <= 0) continue;
+      more = true;
+      cnt[i] = k;
+      const double t0 = r.t0 + ir[i].done * dts[i];
+      const int start = (r.start && ir[i].done == 0) ? 1 : 0;
+      if (groupable_2d(*owner, *r.ctx)) {
+        group.push_back(GroupMember{r.ctx, r.nrhs, r.u, r.d, r.ctx->d_ubuf, t0, dts[i], k, start});
+        if (r.nrec > 0)
+          ghook.t.push_back(TraceTarget{r.ctx, r.u, r.ctx->d_ubuf, r.nrhs, k, r.nrec, r.traces,
+                                        (int64_t)r.nsteps + 1, (int64_t)ir[i].done});
+      } else {
+        solo.push_back(i);
+      }
+    }
+    if (!more) break;
+    // the group runs on the owner's stream; sources of members without any are hidden
+    std::vector<SourceDev*> saved;
+    for (auto& g : group) {
+      saved.push_back(g.ctx->d_src);
+      if (!g.ctx->d_src_active) g.ctx->d_src = nullptr;
+    }
+    const StepHook gh{hook_fn, &ghook};
+    if (!group.empty()) st = run_group(*owner, group, graph, ghook.t.empty() ? nullptr : &gh);
+    for (size_t k = 0; k < group.size(); ++k) group[k].ctx->d_src = saved[k];
+    if (st) return st;
+    for (int i : solo) {
+      const fcw_run_item& r = items[i];
+      fcw_ctx* c = r.ctx;
+      HookArg sh;
+      if (r.nrec > 0)
+        sh.t.push_back(TraceTarget{c, r.u, c->d_ubuf, r.nrhs, cnt[i], r.nrec, r.traces,
+                                   (int64_t)r.nsteps + 1, (int64_t)ir[i].done});
+      const StepHook hk{hook_fn, &sh};
+      SourceDev* sv = c->d_src;
+      if (!r.src) c->d_src = nullptr;
+      hipStream_t s0 = c->stream;
+      c->stream = owner->stream;
+      st = run_steps(*c, c->tile_choice, r.nrhs, r.u, r.d, c->d_ubuf,
+                     r.t0 + ir[i].done * dts[i], dts[i], cnt[i],
+                     (r.start && ir[i].done == 0) ? 1 : 0, sh.t.empty() ? nullptr : &hk);
+      c->stream = s0;
+      c->d_src = sv;
+      if (st) return st;
+    }
+    for (int i = 0; i < n; ++i) ir[i].done += cnt[i];
+    if (check_every == 0) continue;
+    // growth checks (Sec. 2.3): sum d_i^2 per right-hand side after the chunk
+    for (int i = 0; i < n; ++i) {
+      const fcw_run_item& r = items[i];
+      if (r.check_every == 0 || cnt[i] == 0) continue;
+      if ((st = state_sums(*r.ctx, owner->stream, r.nrhs, nullptr, r.d, nullptr, false)))
+        return st;
+      ItemRun& x = ir[i];
+      double g = 0.0;
+      for (int q = 0; q < r.nrhs; ++q) {
+        const double sq = r.ctx->h_red[3 * q];
+        if (!std::isfinite(sq)) {
+          x.status = FCW_E_UNSTABLE;
+          g = sq;
+          break;
+        }
+        if (x.prev[q] > 0.0) {
+          const double ratio = sq / x.prev[q];
+          g = std::max(g, ratio);
+          x.streak[q] = ratio > 1e6 ? x.streak[q] + 1 : 0;
+          if (x.streak[q] >= 3) x.status = FCW_E_UNSTABLE;
+        }
+        x.prev[q] = sq;
+      }
+      x.growth = g;
+    }
+  }
+  // energies after the last step: r = K u in the partner buffer, then the three sums
+  for (int i = 0; i < n; ++i) {
+    const fcw_run_item& r = items[i];
+    if (!r.energy) continue;
     fcw_ctx* c = r.ctx;
-    SourceDev* sv = c->d_src;
-    if (!r.src) c->d_src = nullptr;
     hipStream_t s0 = c->stream;
     c->stream = owner->stream;
-    st = run_steps(*c, c->tile_choice, r.nrhs, r.u, r.d, c->d_ubuf, r.t0, dts[i], r.nsteps,
-                   r.start);
+    st = launch_apply(*c, r.nrhs, r.u, c->d_ubuf);
     c->stream = s0;
-    c->d_src = sv;
     if (st) return st;
+    if ((st = state_sums(*c, owner->stream, r.nrhs, r.u, r.d, c->d_ubuf, true))) return st;
+    const double dt = dts[i];
+    for (int q = 0; q < r.nrhs; ++q) {
+      const double* t = c->h_red + 3 * q;
+      r.energy[q] = 0.5 * (t[0] / (dt * dt) + t[1] - t[2]);
+    }
+  }
+  if (sync_end) FCW_HIP(hipStreamSynchronize(owner->stream));
+  bool unstable = false;
+  for (int i = 0; i < n; ++i) {
+    if (items[i].result) {
+      items[i].result->status = ir[i].status;
+      items[i].result->steps_done = ir[i].done;
+      items[i].result->dt_used = dts[i];
+      items[i].result->growth = ir[i].growth;
+    }
+    unstable = unstable || ir[i].status == FCW_E_UNSTABLE;
+  }
+  if (unstable) {
+    std::string which;
+    for (int i = 0; i < n; ++i)
+      if (ir[i].status == FCW_E_UNSTABLE) which += " " + std::to_string(i);
+    set_error("growth detected (dt above the critical step?) in run item(s)%s", which.c_str());
+    return FCW_E_UNSTABLE;
   }
   return FCW_OK;
 }

@@ -33,6 +33,14 @@ struct SourceDev {
   double b[kMaxNl];  // rho * amp * dir_c * N_a(x_s), local (comp-major) order
 };
 
+// An observer point prepared on the device: the cell holding it and the values N_a(x_r)
+// of that cell's shape functions (local node order, x fastest).
+struct RecDev {
+  int32_t cell[3];
+  int32_t pad;
+  double w[kMaxNl];
+};
+
 struct Ctx {
   // problem
   int dim = 2, ncomp = 1, p = 1, depth = 0, precision = FCW_FP64;
@@ -98,6 +106,11 @@ struct Ctx {
   bool d_src_active = false;  // the sources of the current batched call are set
   int src_cap = 0;
   std::vector<fcw_source> src_staged;  // host copy of the sources d_src was computed from
+  // receivers of the current run (FCW_MAX_RECEIVERS) and reduction buffers of the
+  // growth checks and energies: [64 rhs][3][kRedBlocks] partial sums and [64][3] totals
+  RecDev* d_rec = nullptr;
+  double* d_red = nullptr;
+  double* h_red = nullptr;  // pinned copy of the totals
   // work list of the persistent step kernel (device + pinned staging)
   void* d_wl = nullptr;
   void* h_wl = nullptr;
@@ -181,8 +194,14 @@ fcw_status launch_cut_products(Ctx& c, int nrhs, const void* u);
 bool step_supported(const Ctx& c);
 fcw_status launch_apply(Ctx& c, int nrhs, const void* u, void* r);
 int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name = nullptr);
+// Work queued after each step of a call (observer traces): fn(arg, stream, j) after step j
+// of the call has been queued, and once with j = -1 before the first step.
+struct StepHook {
+  fcw_status (*fn)(void* arg, hipStream_t s, int j);
+  void* arg;
+};
 fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scratch, double t0,
-                     double dt, int nsteps, int start);
+                     double dt, int nsteps, int start, const StepHook* hook = nullptr);
 // one batched group of 2-D problems (see fcw_run)
 struct GroupMember {
   Ctx* ctx;
@@ -191,7 +210,25 @@ struct GroupMember {
   double t0, dt;
   int nsteps, start;
 };
-fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph);
+fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph,
+                     const StepHook* hook = nullptr);
+// observe.hip: receivers, traces, growth checks and energies of fcw_run
+fcw_status prepare_receivers(Ctx& c, int nrec, const double* x);  // setup.hip; into c.d_rec
+struct TraceTarget {
+  Ctx* ctx;
+  const void* u;     // caller state of the call (the final state lands here)
+  const void* ub;    // its ping-pong partner
+  int nrhs, nsteps;  // of this call (fixes which buffer holds the state after step j)
+  int nrec;
+  double* traces;    // [nrhs][tlen][nrec][ncomp]
+  int64_t tlen, k0;  // rows per right-hand side; row of the call's initial state
+};
+fcw_status launch_traces(hipStream_t s, const TraceTarget* t, int n, int j);
+// per right-hand side sums over the DOFs into c.h_red[rhs * 3 + q] (synchronises):
+// energy = false: q = 0 sum d_i^2;  energy = true: q = 0 sum m_i d_i^2, q = 1 u.Ku,
+// q = 2 d.Ku, with Ku in `r` (m_i the lumped mass)
+fcw_status state_sums(Ctx& c, hipStream_t s, int nrhs, const void* u, const void* d,
+                      const void* r, bool energy);
 bool groupable_2d(const Ctx& a, const Ctx& b);
 fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
 // lanczos.hip

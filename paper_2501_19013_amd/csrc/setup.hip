@@ -1603,6 +1603,80 @@ __global__ void source_kernel(SrcArgs a) {
   o.f0 = in.f0;
 }
 
+// Receivers: the cell holding each point (the rule of the sources) and N_a(x_r).
+struct RecArgs {
+  Grid g;
+  const RefTables* tab;
+  int nrec;
+  const double* x;  // [nrec][3]
+  RecDev* out;
+};
+
+template <int NP1>
+__global__ void receiver_kernel(RecArgs a) {
+#pragma clang fp contract(off)
+  const int r = blockIdx.x;
+  if (r >= a.nrec || threadIdx.x != 0) return;
+  const double* x = a.x + 3 * r;
+  RecDev& o = a.out[r];
+  double L[3][NP1], dL[3][NP1];
+  for (int k = 0; k < 3; ++k) o.cell[k] = 0;
+  for (int k = 0; k < a.g.dim; ++k) {
+    int i = (int)floor((x[k] - a.g.lo[k]) / a.g.h);
+    i = max(0, min(i, a.g.n[k] - 1));
+    o.cell[k] = i;
+    const double clo = a.g.lo[k] + (double)i * a.g.h;
+    const double xi = 2.0 * (x[k] - clo) / a.g.h - 1.0;
+    lagrange_1d<NP1>(a.tab->gll_x, xi, L[k], dL[k]);
+  }
+  int ns = 1;
+  for (int k = 0; k < a.g.dim; ++k) ns *= NP1;
+  for (int loc = 0; loc < ns; ++loc) {
+    double N = 1.0;
+    int q = loc;
+    for (int k = 0; k < a.g.dim; ++k) { N *= L[k][q % NP1]; q /= NP1; }
+    o.w[loc] = N;
+  }
+}
+
+fcw_status prepare_receivers(Ctx& c, int nrec, const double* x) {
+  if (nrec <= 0) return FCW_OK;
+  if (nrec > FCW_MAX_RECEIVERS) {
+    set_error("at most %d receivers per problem (got %d)", FCW_MAX_RECEIVERS, nrec);
+    return FCW_E_ARG;
+  }
+  if (!c.d_rec) {
+    // RecDev[FCW_MAX_RECEIVERS] followed by a staging copy of the points
+    FCW_HIP(hipMalloc((void**)&c.d_rec,
+                      FCW_MAX_RECEIVERS * (sizeof(RecDev) + 3 * sizeof(double))));
+    c.footprint += FCW_MAX_RECEIVERS * (sizeof(RecDev) + 3 * sizeof(double));
+  }
+  double* staged = (double*)(c.d_rec + FCW_MAX_RECEIVERS);
+  FCW_HIP(hipMemcpyAsync(staged, x, (size_t)nrec * 3 * sizeof(double), hipMemcpyHostToDevice,
+                         c.stream));
+  RecArgs ra{};
+  ra.g = make_grid(c);
+  ra.tab = c.d_tab;
+  ra.nrec = nrec;
+  ra.x = staged;
+  ra.out = c.d_rec;
+  switch (c.p + 1) {
+    case 2: receiver_kernel<2><<<nrec, 64, 0, c.stream>>>(ra); break;
+    case 3: receiver_kernel<3><<<nrec, 64, 0, c.stream>>>(ra); break;
+    case 4: receiver_kernel<4><<<nrec, 64, 0, c.stream>>>(ra); break;
+    case 5: receiver_kernel<5><<<nrec, 64, 0, c.stream>>>(ra); break;
+    case 6: receiver_kernel<6><<<nrec, 64, 0, c.stream>>>(ra); break;
+    case 7: receiver_kernel<7><<<nrec, 64, 0, c.stream>>>(ra); break;
+    default:
+      set_error("receivers not built for p=%d", c.p);
+      return FCW_E_UNSUPPORTED;
+  }
+  FCW_HIP(hipGetLastError());
+  // the host points must stay valid until the copy has run
+  FCW_HIP(hipStreamSynchronize(c.stream));
+  return FCW_OK;
+}
+
 fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src, bool remember) {
   if (nrhs > kMaxSrc) {
     set_error("at most %d right-hand sides per call (got %d)", kMaxSrc, nrhs);

@@ -844,7 +844,8 @@ bool groupable_2d(const Ctx& a, const Ctx& b) {
 
 // A batched group: the first member's configuration choice gives the 2-D kernel (its tile
 // shape applies to every member); one launch per step over all members' items.
-fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) {
+fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph,
+                     const StepHook* hook) {
   const int fp64 = owner.precision == FCW_FP64;
   StepCand sc;
   step_candidates(owner, owner.tile_choice, &sc);
@@ -894,10 +895,13 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
   const int nitems = (int)items.size();
   const int4* ditems = (const int4*)((char*)owner.d_wl + rec.size());
   const void* dcut = (const char*)owner.d_wl + rec.size() + items.size() * sizeof(int4);
-  if (!graph) {
-    for (int j = 0; j < nmax; ++j)
+  if (!graph || hook) {
+    if (hook && (st = hook->fn(hook->arg, owner.stream, -1))) return st;
+    for (int j = 0; j < nmax; ++j) {
       if ((st = group_step(owner, sc.f2d, owner.d_wl, ditems, nitems, dcut, ncutprob, ncutblk, j)))
         return st;
+      if (hook && (st = hook->fn(hook->arg, owner.stream, j))) return st;
+    }
     return FCW_OK;
   }
   // graph replay: the records live in device memory, so a cached graph stays valid for
@@ -935,8 +939,12 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph) 
 // Advance nrhs right-hand sides by nsteps steps with configuration `choice`; the final
 // state is in u.  `scratch` holds nrhs*ndof state words.
 fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scratch, double t0,
-                     double dt, int nsteps, int start) {
+                     double dt, int nsteps, int start, const StepHook* hook) {
   if (nsteps <= 0) return FCW_OK;
+  if (hook) {
+    fcw_status st = hook->fn(hook->arg, c.stream, -1);
+    if (st) return st;
+  }
   const size_t bytes = (size_t)nrhs * c.ndof * c.state_bytes();
   StepCand sc;
   const int n = step_candidates(c, choice, &sc);
@@ -963,6 +971,7 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
           (st = launch_cut(c, c.stream, nullptr, 1, crec, ncutblk, j)))
         return st;
       if ((st = sc.f2d(c.stream, nullptr, nullptr, nitems, j, rec, nrhs))) return st;
+      if (hook && (st = hook->fn(hook->arg, c.stream, j))) return st;
     }
     return FCW_OK;
   }
@@ -971,6 +980,7 @@ fcw_status run_steps(Ctx& c, int choice, int nrhs, void* u, void* d, void* scrat
   for (int j = 0; j < nsteps; ++j) {
     fcw_status st = sc.fgen(c, kModeStep, nrhs, a, b, d, t0 + j * dt, dt, (start && j == 0) ? 1 : 0);
     if (st) return st;
+    if (hook && (st = hook->fn(hook->arg, c.stream, j))) return st;
     void* t = a;
     a = b;
     b = t;

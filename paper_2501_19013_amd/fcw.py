@@ -45,10 +45,24 @@ class Source(C.Structure):
                 ("amp", C.c_double)]
 
 
+class RunResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps_done", C.c_int32), ("dt_used", C.c_double),
+                ("growth", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class RunItem(C.Structure):
     _fields_ = [("ctx", C.c_void_p), ("nrhs", C.c_int32), ("u", C.c_void_p), ("d", C.c_void_p),
                 ("src", C.POINTER(Source)), ("t0", C.c_double), ("dt", C.c_double),
-                ("nsteps", C.c_int32), ("start", C.c_int32)]
+                ("dt_max", C.c_double), ("nsteps", C.c_int32), ("start", C.c_int32),
+                ("nrec", C.c_int32), ("rec_x", C.POINTER(C.c_double)),
+                ("traces", C.c_void_p), ("check_every", C.c_int32),
+                ("result", C.POINTER(RunResult)), ("energy", C.POINTER(C.c_double))]
+
+
+MAX_RECEIVERS = 64
 
 
 FCW_RUN_GRAPH = 1
@@ -244,10 +258,14 @@ def tile_configs(ctx):
     return out
 
 
-def run(entries, graph=False):
-    """fcw_run: entries are dicts with ctx, nrhs, u, d, sources, t0, dt, nsteps, start."""
+def run(entries, graph=False, raise_unstable=True):
+    """fcw_run.  Each entry is a dict with ctx, nrhs, u, d and optionally sources, t0, dt
+    (<= 0: the library's rule min(0.9 dt_crit, dt_max)), dt_max, nsteps, start,
+    receivers ([nrec][dim] points), traces (device double [nrhs][nsteps+1][nrec][ncomp]),
+    check_every, energy (True: return the discrete energy per right-hand side).
+    Returns one dict per entry: status, steps_done, dt_used, growth (and energy)."""
     arr = (RunItem * len(entries))()
-    keep = []
+    keep, results, energies = [], [], []
     for i, e in enumerate(entries):
         srcs = _sources(e.get("sources"))
         keep.append(srcs)
@@ -258,9 +276,38 @@ def run(entries, graph=False):
         arr[i].src = C.cast(srcs, C.POINTER(Source)) if srcs is not None else None
         arr[i].t0 = float(e.get("t0", 0.0))
         arr[i].dt = float(e.get("dt", 0.0))
+        arr[i].dt_max = float(e.get("dt_max", 0.0))
         arr[i].nsteps = int(e["nsteps"])
         arr[i].start = int(e.get("start", 0))
-    _check(load().fcw_run(arr, len(entries), FCW_RUN_GRAPH if graph else 0))
+        rec = e.get("receivers")
+        if rec is not None and len(rec):
+            pts = np.zeros((len(rec), 3))
+            for q, x in enumerate(rec):
+                pts[q, :len(x)] = x
+            pts = np.ascontiguousarray(pts)
+            keep.append(pts)
+            arr[i].nrec = len(rec)
+            arr[i].rec_x = pts.ctypes.data_as(C.POINTER(C.c_double))
+            arr[i].traces = _ptr(e["traces"])
+        arr[i].check_every = int(e.get("check_every", 0))
+        res = RunResult()
+        results.append(res)
+        arr[i].result = C.pointer(res)
+        en = None
+        if e.get("energy"):
+            en = (C.c_double * int(e["nrhs"]))()
+            arr[i].energy = C.cast(en, C.POINTER(C.c_double))
+        energies.append(en)
+    status = load().fcw_run(arr, len(entries), FCW_RUN_GRAPH if graph else 0)
+    if status != FCW_OK and not (status == FCW_E_UNSTABLE and not raise_unstable):
+        _check(status)
+    out = []
+    for res, en in zip(results, energies):
+        d = res.as_dict()
+        if en is not None:
+            d["energy"] = list(en)
+        out.append(d)
+    return out
 
 
 def select_tile(ctx, i):

@@ -129,12 +129,12 @@ class Server:
             except Exception:
                 fcw.destroy(ctx)
                 raise
-        dt = min(req.cfg.get("dt_factor", 0.9) * dtc, req.cfg.get("dt_max", math.inf))
         fp = info["footprint_bytes"] + 3 * u.numel() * u.element_size()
         req.dofs = int(info["ndof"]) * nrhs
-        req.dt = dt
         req.setup_s = time.perf_counter() - t_setup
-        return _Resident(req=req, ctx=ctx, u=u, d=d, dt=dt, footprint=fp)
+        # the step size comes from the library's rule (dt <= 0 in fcw_run) on the first
+        # quantum and is kept for the later ones
+        return _Resident(req=req, ctx=ctx, u=u, d=d, dt=None, footprint=fp)
 
     def run(self, requests, time_scale=1.0):
         """Serve ``requests`` (arrival times in seconds); returns a metrics dict."""
@@ -191,14 +191,19 @@ class Server:
                     entries = []
                     for r in members:
                         n = min(self.quantum, r.req.nsteps - r.steps_done)
+                        dt_max = r.req.cfg.get("dt_max", math.inf)
                         entries.append(dict(ctx=r.ctx, nrhs=len(r.req.sources), u=r.u, d=r.d,
-                                            sources=r.req.sources, t0=r.steps_done * r.dt,
-                                            dt=r.dt, nsteps=n, start=int(r.steps_done == 0)))
+                                            sources=r.req.sources,
+                                            t0=r.steps_done * r.dt if r.dt else 0.0,
+                                            dt=r.dt or 0.0,
+                                            dt_max=dt_max if math.isfinite(dt_max) else 0.0,
+                                            nsteps=n, start=int(r.steps_done == 0)))
                     if key[0] == 2 and key[1] == 1:
-                        fcw.run(entries, graph=self.graph)
+                        outs = fcw.run(entries, graph=self.graph)
                     else:
-                        for e in entries:
-                            fcw.run([e])
+                        outs = [fcw.run([e])[0] for e in entries]
+                    for r, o in zip(members, outs):
+                        r.dt = r.req.dt = o["dt_used"]
             self.stream.synchronize()
             step_s += time.perf_counter() - t_q
             t = now()

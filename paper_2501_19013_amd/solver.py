@@ -5,8 +5,6 @@ libfcw.so.  torch provides the device buffers (state vectors) and the stream.
 """
 from __future__ import annotations
 
-import math
-
 from . import fcw
 
 
@@ -82,7 +80,3 @@ class Solver:
         except Exception:
             pass
 
-
-def choose_dt(dt_crit, factor=0.9, dt_max=math.inf):
-    """dt = min(0.9 dt_crit, dt_max) (step-size rule of the paper's Sec. 3.3)."""
-    return min(factor * dt_crit, dt_max)
