@@ -46,6 +46,9 @@ class Problem:
     nu: float = 0.3
     eps: float = 1e-4
     f_lambda: float = 1e-4
+    # optional rotated cube (Sec. 3.1): (centre [d], half edge, T [d][d]); the physical
+    # domain is then the cube minus the voids
+    cube: object = None
     h: float = field(init=False)
 
     def __post_init__(self):
@@ -58,6 +61,10 @@ class Problem:
         self.h = hs[0]
         self.void_center = np.asarray(self.void_center, dtype=np.float64).reshape(-1, self.dim)
         self.void_radius = np.asarray(self.void_radius, dtype=np.float64).reshape(-1)
+        if self.cube is not None:
+            c, a, T = self.cube
+            self.cube = (np.asarray(c, dtype=np.float64).reshape(self.dim), float(a),
+                         np.asarray(T, dtype=np.float64).reshape(self.dim, self.dim))
 
     @property
     def nodes_per_dim(self):
@@ -83,7 +90,10 @@ class Problem:
     def from_config(cfg):
         keys = ("dim", "ncomp", "ncells", "lo", "hi", "p", "tree_depth", "void_center",
                 "void_radius", "alpha", "rho", "c", "E", "nu", "eps", "f_lambda")
-        return Problem(**{k: cfg[k] for k in keys})
+        cube = cfg.get("cube")
+        if cube is not None:
+            cube = (cube["center"], cube["half"], cube["rot"])
+        return Problem(**{k: cfg[k] for k in keys}, cube=cube)
 
     def cell_lo(self, cell):
         """Lower corner of a cell given by its lexicographic index."""
@@ -154,7 +164,7 @@ def cut_cell_matrices(prob, cell):
     lo = prob.cell_lo(cell)
     pts, wts, av, all_void = quadrature.tree_rule(prob.p, lo, lo + prob.h, prob.void_center,
                                                   prob.void_radius, prob.alpha,
-                                                  prob.tree_depth)
+                                                  prob.tree_depth, prob.cube)
     K, _ = element.element_integrals(prob, lo, pts, wts, av)
     _, Mo = element.scalar_integrals(prob.p, prob.dim, lo, prob.h, pts, wts, av,
                                      prob.rho, prob.c)

@@ -24,12 +24,12 @@ from .element import box_rule
 from .geometry import OUT, UNCUT, box_status, box_void_relation, indicator
 
 
-def tree_boxes(lo, hi, centers, radii, depth, level=0):
+def tree_boxes(lo, hi, centers, radii, depth, level=0, cube=None):
     """List of (lo, hi, kind) integration boxes of the space tree over [lo, hi].
 
     kind is 'alpha' (constant alpha), 'one' (constant 1) or 'leaf' (pointwise).
     """
-    st = box_status(lo, hi, centers, radii)
+    st = box_status(lo, hi, centers, radii, cube)
     if st == OUT:
         return [(lo, hi, "alpha")]
     if st == UNCUT:
@@ -42,11 +42,11 @@ def tree_boxes(lo, hi, centers, radii, depth, level=0):
         c = np.array(corner)
         clo = np.where(c == 0, lo, mid)
         chi = np.where(c == 0, mid, hi)
-        out.extend(tree_boxes(clo, chi, centers, radii, depth, level + 1))
+        out.extend(tree_boxes(clo, chi, centers, radii, depth, level + 1, cube))
     return out
 
 
-def tree_rule(p, lo, hi, centers, radii, alpha, depth):
+def tree_rule(p, lo, hi, centers, radii, alpha, depth, cube=None):
     """Quadrature points, weights and indicator values over one cut cell.
 
     Returns (pts, wts, alpha_vals, all_void) where all_void is True when every box of
@@ -58,9 +58,9 @@ def tree_rule(p, lo, hi, centers, radii, alpha, depth):
     # a void that does not meet the cell meets none of its sub-boxes and contains none
     # of its points: keep only the voids meeting the cell (same predicates, fewer tests)
     keep = [j for j in range(len(radii)) if box_void_relation(lo, hi, centers[j], radii[j])[0]]
-    centers = np.asarray(centers, float).reshape(len(radii), -1)[keep]
+    centers = np.asarray(centers, float).reshape(len(radii), len(lo))[keep]
     radii = np.asarray(radii, float)[keep]
-    boxes = tree_boxes(lo, hi, centers, radii, depth)
+    boxes = tree_boxes(lo, hi, centers, radii, depth, cube=cube)
     P, W, A = [], [], []
     for blo, bhi, kind in boxes:
         pts, wts = box_rule(p, blo, bhi)
@@ -69,7 +69,7 @@ def tree_rule(p, lo, hi, centers, radii, alpha, depth):
         elif kind == "one":
             av = np.ones(len(wts))
         else:
-            av = indicator(pts, centers, radii, alpha)
+            av = indicator(pts, centers, radii, alpha, cube)
         P.append(pts)
         W.append(wts)
         A.append(av)
@@ -77,7 +77,7 @@ def tree_rule(p, lo, hi, centers, radii, alpha, depth):
     return np.concatenate(P), np.concatenate(W), np.concatenate(A), all_void
 
 
-def physical_volume(p, lo, hi, centers, radii, depth):
+def physical_volume(p, lo, hi, centers, radii, depth, cube=None):
     """Volume of the physical part of [lo,hi] as seen by the tree rule (alpha = 0)."""
-    pts, wts, av, _ = tree_rule(p, lo, hi, centers, radii, 0.0, depth)
+    pts, wts, av, _ = tree_rule(p, lo, hi, centers, radii, 0.0, depth, cube)
     return float(np.sum(wts * av))

@@ -24,7 +24,8 @@ import numpy as np
 
 __all__ = [
     "circle_hole", "random_circles", "random_spheres", "config", "scaled_config",
-    "request_stream", "CONFIG_NAMES",
+    "request_stream", "CONFIG_NAMES", "cardan_rotation", "rotated_cube", "cube_point",
+    "cube_observers",
 ]
 
 CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
@@ -132,6 +133,50 @@ def scaled_config(dim, n, p, seed, nvoids=None, ncomp=1, porosity=None,
                                 rmax=0.06 if rmax is None else rmax, n_probe=50000)
     return _base(dim, (n,) * dim, p, cc, rr, ncomp=ncomp, nsteps=nsteps,
                  tree_depth=depth, **kw)
+
+
+def cardan_rotation(phi, theta, psi):
+    """Rotation matrix T = R_z(psi) R_y(theta) R_x(phi) of Cardan angles in degrees
+    (columns: the rotated frame's axes in global coordinates).  The paper names the
+    angles but not their order; this order reproduces most of its printed DOF counts."""
+    a, b, g = np.deg2rad([phi, theta, psi])
+    rx = np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]])
+    ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+    rz = np.array([[np.cos(g), -np.sin(g), 0], [np.sin(g), np.cos(g), 0], [0, 0, 1]])
+    return rz @ ry @ rx
+
+
+def rotated_cube(n, p, l_p=0.3, l_e=0.5, angles=(10.0, 10.0, 10.0), **kw):
+    """The paper's benchmark geometry (Sec. 3.1): a cube of edge l_p rotated by the Cardan
+    angles about the common centre of an embedding cube of edge l_e, here
+    [-l_e/2, l_e/2]^3 with n cells per direction, GLL degree p, scalar wave, no voids.
+    Sources and observers are given in the cube's local frame (origin at its centre)
+    and mapped to global coordinates with cube_point."""
+    T = cardan_rotation(*angles)
+    cfg = _base(3, (n, n, n), p, np.zeros((0, 3)), np.zeros(0),
+                lo=(-l_e / 2,) * 3, hi=(l_e / 2,) * 3, **kw)
+    cfg["cube"] = dict(center=np.zeros(3), half=l_p / 2, rot=T)
+    cfg["l_p"] = l_p
+    cfg["sources"] = [dict(x=tuple(cube_point(cfg, (-l_p / 2, 0.0, 0.0))), f0=10.0, amp=1.0)]
+    return cfg
+
+
+def cube_point(cfg, x_local):
+    """Global coordinates x = c + T x' of a point given in the cube's frame."""
+    c = cfg["cube"]
+    return np.asarray(c["center"]) + np.asarray(c["rot"]) @ np.asarray(x_local, dtype=np.float64)
+
+
+def cube_observers(cfg):
+    """The 11 observer points of Table observer_locations (source, centre, face centre, 4
+    edge centres, 4 corners), given there with the origin at a cube corner (x' in
+    [0, l]^3), in global coordinates."""
+    l = cfg["l_p"]
+    h = l / 2
+    pts = [(0.0, h, h), (h, h, h), (l, h, h)]
+    pts += [(h, h + sy * h, h + sz * h) for sy in (-1, 1) for sz in (-1, 1)]
+    pts += [(l, h + sy * h, h + sz * h) for sy in (-1, 1) for sz in (-1, 1)]
+    return np.array([cube_point(cfg, np.array(x) - h) for x in pts])
 
 
 def request_stream(seed=5, count=256, rate=None):
