@@ -760,7 +760,9 @@ int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3], std::strin
       FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
       FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8),
       FCW_S(2, 2, 8, 4), FCW_S(2, 2, 16, 4), FCW_S(3, 2, 8, 4), FCW_S(3, 2, 16, 4),
-      FCW_S(4, 2, 4, 4), FCW_S(4, 2, 8, 4), FCW_S(4, 2, 16, 4)};
+      FCW_S(4, 2, 3, 4), FCW_S(4, 2, 4, 4), FCW_S(4, 2, 5, 4), FCW_S(4, 2, 6, 4),
+      FCW_S(4, 2, 8, 4), FCW_S(4, 2, 16, 4), FCW_S(4, 1, 4, 2), FCW_S(4, 1, 6, 2),
+      FCW_S(4, 1, 8, 2)};
 #undef FCW_E
 #undef FCW_S
   int n = 0;

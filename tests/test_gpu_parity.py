@@ -340,7 +340,7 @@ def test_every_tile_configuration(c2_small, precision, tol):
     s.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("bf16", BF16_TOL)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4), ("bf16", BF16_TOL)])
 def test_elastic_3d_every_tile_configuration(precision, tol):
     # every 3-D elastic tile shape and block size the autotuner may choose, on a 9x6x5 p=2
     # grid with one ball (several tiles per axis, ragged edge tiles, cut cells)
@@ -352,11 +352,59 @@ def test_elastic_3d_every_tile_configuration(precision, tol):
     ref = timestep.cdm(disc, dt, 60, sources=cfg["sources"])["u"]
     s = _solver(cfg, precision)
     confs = s.tile_configs()
-    assert len(confs) >= 4
+    assert len(confs) >= 2
     for i, conf in enumerate(confs):
         s.select_tile(i)
         got = _run_gpu(s, cfg, dt, 60, [60])
         assert rel_l2(got[60], ref) <= tol, (i, conf)
+    s.close()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_scalar_3d_every_tile_configuration(p, precision, tol):
+    # every 3-D scalar tile shape the autotuner may choose, on a ragged 9x7x5 grid with one
+    # ball (several tiles per axis, edge tiles, cut cells)
+    cfg = workloads._base(3, (9, 7, 5), p, [(0.5, 0.35, 0.25)], [0.17], nsteps=50,
+                          hi=(0.9, 0.7, 0.5), tree_depth=2)
+    disc = _oracle(cfg)
+    assert len(disc.cut_cells) > 0
+    dt = 0.9 * timestep.critical_dt(disc)
+    ref = timestep.cdm(disc, dt, 50, sources=cfg["sources"])["u"]
+    s = _solver(cfg, precision)
+    confs = s.tile_configs()
+    assert len(confs) >= 2
+    for i, conf in enumerate(confs):
+        s.select_tile(i)
+        got = _run_gpu(s, cfg, dt, 50, [21, 29])
+        assert rel_l2(got[50], ref) <= tol, (i, conf)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_elastic_3d_multi_rhs(precision, tol):
+    # three right-hand sides (sources in other places and directions) in one call, each
+    # against its own oracle run
+    import torch
+    cfg = workloads.scaled_config(3, 5, 2, seed=4, ncomp=3, porosity=0.15)
+    srcs = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0),
+            dict(x=(0.72, 0.33, 0.61), dir=(0.0, 0.6, 0.8), f0=14.0, amp=-0.7),
+            dict(x=(0.45, 0.85, 0.2), dir=(0.0, 0.0, 1.0), f0=8.0, amp=0.4)]
+    srcs = [q for q in srcs if not np.any(np.linalg.norm(cfg["void_center"] - q["x"], axis=1)
+                                          < cfg["void_radius"])]
+    assert len(srcs) >= 2
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    nsteps = 70
+    s = _solver(cfg, precision)
+    u, d = s.zeros(len(srcs)), s.zeros(len(srcs))
+    s.step(u, d, srcs, dt, 33, start=True)
+    s.step(u, d, srcs, dt, nsteps - 33, t0=33 * dt)
+    torch.cuda.synchronize()
+    got = u.double().cpu().numpy()
+    for q, src in enumerate(srcs):
+        ref = timestep.cdm(disc, dt, nsteps, sources=[src])["u"]
+        assert rel_l2(got[q], ref) <= tol, (q, rel_l2(got[q], ref))
     s.close()
 
 
