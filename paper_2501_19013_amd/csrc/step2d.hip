@@ -38,6 +38,17 @@ __device__ static inline void buffer_dword_to_lds(__amdgpu_buffer_rsrc_t rsrc, i
                                            4, voffset, 0, 0, 0);
 }
 
+// s_waitcnt vmcnt(N) for a compile-time N (gfx9 encoding: vmcnt in bits 3:0 and 15:14;
+// expcnt and lgkmcnt at their maxima, i.e. not waited for); a compiler barrier on both sides
+template <int N>
+__device__ static inline void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+  constexpr int imm = (N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(imm);
+  asm volatile("" ::: "memory");
+}
+
 // One wave's 64 consecutive dwords, global -> LDS (lane l lands at lds_wave_base + 4 l).
 __device__ static inline void lds_dword2d(const void* gsrc, void* lds_wave_base) {
   __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)gsrc,
@@ -390,8 +401,12 @@ __global__ __launch_bounds__(256) void step2d_kernel(
 //  * every store of the update is a buffer store with an out-of-range offset for lanes
 //    that own no node, so each wave issues a fixed number of stores per row and the
 //    end-of-row wait leaves exactly those in flight (vmcnt counts in issue order).
-template <typename T, int P, int NBR, int YR, int NW, bool SINGLE>
-__global__ __launch_bounds__(64 * NW) void stream2d_kernel(
+//  * PD = 2 (prefetch distance): the node rows, d and stored inverse masses of a cell row
+//    are loaded two iterations ahead (ring of 4P rows), so their latency spans two
+//    iterations; the cut-cell products stay one row ahead and are issued first, so the
+//    end-of-row wait (a fixed count of later loads and stores per wave) covers them.
+template <typename T, int P, int NBR, int YR, int NW, bool SINGLE, int PD>
+__global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
     const Prob2d<T>* __restrict__ probs, const int4* __restrict__ items, const Prob2d<T> one,
     int nrhs1, int nitems, int chunk, int j) {
   constexpr int NP1 = P + 1;
@@ -404,7 +419,7 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
   constexpr int RW = NCR * P + 1;      // node row width staged (from the ring cell)
   constexpr int OWN = TXS * P + 1;     // owned nodes per row at most (last column)
   constexpr int NH = (OWN + 63) / 64;  // wave-halves per node row
-  constexpr int RING = 3 * P;          // ring buffer rows
+  constexpr int RING = (PD + 2) * P;   // ring buffer rows
   constexpr int DPE = sizeof(T) / 4;
   constexpr int RWD = RW * DPE;        // dwords per staged row
   constexpr int NCH = (RWD + 63) / 64;
@@ -415,6 +430,10 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
   constexpr int KU = (NU + NW - 1) / NW;  // units per wave
   constexpr int NMU = NBR * NMB;       // MFMA units per cell row
   static_assert(NMB * NKS <= 32, "K_ref fragments kept in registers");
+  static_assert(PD == 1 || (PD == 2 && P % NW == 0),
+                "prefetch distance 2 needs the same number of staged rows in every wave");
+  // loads per wave that follow the cut-cell copies of a row (node rows, d, 1/M)
+  constexpr int NFIX = NCH * (P / NW) + 2 * KU;
 
   __shared__ T u_r[RING * RW];
   __shared__ T y_b[3][NCR * NLP];
@@ -546,12 +565,12 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
     ky[kk] = (jj < NL) ? jj / NP1 : 0;
   }
   // update units of this wave: (node row in the cell row, half)
-  T d_c[KU], d_n[KU], m_c[KU], m_n[KU];
-  bool st_c[KU], st_n[KU];
+  T d_c[KU], d_n[KU], m_c[KU], m_n[KU], d_nn[KU], m_nn[KU];
+  bool st_c[KU], st_n[KU], st_nn[KU];
 #pragma unroll
   for (int k = 0; k < KU; ++k) {
-    d_n[k] = m_n[k] = T(0);
-    st_n[k] = false;
+    d_n[k] = m_n[k] = d_nn[k] = m_nn[k] = T(0);
+    st_n[k] = st_nn[k] = false;
   }
   // loads of the update operands of cell row cy (d; stored inverse masses where flagged)
   auto load_upd = [&](int cy, T* dr, T* mr, bool* sr) {
@@ -579,22 +598,35 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
     }
   };
 
+  if constexpr (PD == 2) {
+    // the first owned cell row goes ahead as well (waited for with the ring row's loads)
+    stage_rows(cy0 * P + 1, P);
+    load_upd(cy0, d_nn, m_nn, st_nn);
+  }
   const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
   int bp = 2, bc = 0, bn = 1;  // previous / current / next product buffers (distinct)
   for (int cy = cy0 - 1; cy < cy1; ++cy) {
     const bool ring = cy < cy0;
-    // ---- A: loads of the next cell row (all in flight during this row's work) ----
+    // ---- A: loads of the next cell row(s) (all in flight during this row's work) ----
     if (cy + 1 < cy1) {
       stage_cut(cy + 1, y_b[bn]);
     }
-    stage_rows((cy + 1) * P + 1, P);
+    // nothing below moves above the cut-cell copies (the end-of-row wait counts on it)
+    asm volatile("" ::: "memory");
+    stage_rows((cy + PD) * P + 1, P);
 #pragma unroll
     for (int k = 0; k < KU; ++k) {
       d_c[k] = d_n[k];
       m_c[k] = m_n[k];
       st_c[k] = st_n[k];
+      if constexpr (PD == 2) {
+        d_n[k] = d_nn[k];
+        m_n[k] = m_nn[k];
+        st_n[k] = st_nn[k];
+      }
     }
-    load_upd(cy + 1, d_n, m_n, st_n);
+    if constexpr (PD == 2) load_upd(cy + 2, d_nn, m_nn, st_nn);
+    else load_upd(cy + 1, d_n, m_n, st_n);
 
     // ---- B: products of cell row cy into y_b[bc] (cut cells were staged already) ----
     {
@@ -662,12 +694,17 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
           __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, un_), urs, vo, 0, 0);
         }
       }
-      // the loads of the next row done; this row's 2 KU stores may still be in flight
-      if constexpr (KU == 1) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
-      else if constexpr (KU == 2) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
-      else if constexpr (KU == 3) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
-      else if constexpr (KU == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
-      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // PD = 1: the loads of the next row done; this row's 2 KU stores may still be in
+      // flight.  PD = 2: besides, the NFIX loads of the row after next stay in flight.
+      if constexpr (PD == 2) {
+        wait_vmcnt<NFIX + 2 * KU>();
+      } else {
+        if constexpr (KU == 1) asm volatile("s_waitcnt vmcnt(2)" ::: "memory");
+        else if constexpr (KU == 2) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+        else if constexpr (KU == 3) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+        else if constexpr (KU == 4) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      }
     } else {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
@@ -711,17 +748,17 @@ __global__ __launch_bounds__(64 * NW) void stream2d_kernel(
   }
 }
 
-template <typename T, int P, int NBR, int YR, int NW>
+template <typename T, int P, int NBR, int YR, int NW, int PD>
 static fcw_status runs2d(hipStream_t stream, const void* probs, const int4* items, int nitems,
                          int j, const void* one, int nrhs1) {
   const int chunk = (nitems + 7) / 8;
   if (one) {
     Prob2d<T> rec;
     std::memcpy(&rec, one, sizeof rec);
-    stream2d_kernel<T, P, NBR, YR, NW, true><<<8 * chunk, 64 * NW, 0, stream>>>(nullptr, nullptr, rec,
-                                                                        nrhs1, nitems, chunk, j);
+    stream2d_kernel<T, P, NBR, YR, NW, true, PD><<<8 * chunk, 64 * NW, 0, stream>>>(
+        nullptr, nullptr, rec, nrhs1, nitems, chunk, j);
   } else {
-    stream2d_kernel<T, P, NBR, YR, NW, false><<<8 * chunk, 64 * NW, 0, stream>>>(
+    stream2d_kernel<T, P, NBR, YR, NW, false, PD><<<8 * chunk, 64 * NW, 0, stream>>>(
         (const Prob2d<T>*)probs, items, Prob2d<T>{}, 1, nitems, chunk, j);
   }
   FCW_HIP(hipGetLastError());
@@ -750,21 +787,25 @@ static fcw_status run2d(hipStream_t stream, const void* probs, const int4* items
 // 2-D step kernels offered to the autotuner: (P, TY) -> launcher; TX = 64 / P.  `name`
 // receives the kernel's name as a profiler prints it (single-problem launches).
 int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3], std::string* name) {
-  struct E { int p, tx, ty, nbr, nw; Run2d f32, f64; };
+  struct E { int p, tx, ty, nbr, nw, pd; Run2d f32, f64; };
   // tile kernels (tile = cells), then streaming kernels (tile = owned cells per row x cell
   // rows per block)
-#define FCW_S(PP, NBR, YR, NW) \
-  E{PP, 16 * NBR - 1, YR, NBR, NW, &runs2d<float, PP, NBR, YR, NW>, &runs2d<double, PP, NBR, YR, NW>}
-#define FCW_E(PP, TY) E{PP, 64 / PP, TY, 0, 0, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
+#define FCW_S(PP, NBR, YR, NW) FCW_SD(PP, NBR, YR, NW, 1)
+#define FCW_SD(PP, NBR, YR, NW, PD)                                  \
+  E{PP, 16 * NBR - 1, YR, NBR, NW, PD, &runs2d<float, PP, NBR, YR, NW, PD>, \
+    &runs2d<double, PP, NBR, YR, NW, PD>}
+#define FCW_E(PP, TY) E{PP, 64 / PP, TY, 0, 0, 0, &run2d<float, PP, TY>, &run2d<double, PP, TY>}
   static const E table[] = {
       FCW_E(1, 4), FCW_E(1, 8), FCW_E(2, 8), FCW_E(2, 16), FCW_E(3, 8), FCW_E(3, 16),
       FCW_E(4, 8), FCW_E(4, 4), FCW_E(4, 16), FCW_E(5, 4), FCW_E(5, 8),
       FCW_S(2, 2, 8, 4), FCW_S(2, 2, 16, 4), FCW_S(3, 2, 8, 4), FCW_S(3, 2, 16, 4),
       FCW_S(4, 2, 3, 4), FCW_S(4, 2, 4, 4), FCW_S(4, 2, 5, 4), FCW_S(4, 2, 6, 4),
       FCW_S(4, 2, 8, 4), FCW_S(4, 2, 16, 4), FCW_S(4, 1, 4, 2), FCW_S(4, 1, 6, 2),
-      FCW_S(4, 1, 8, 2)};
+      FCW_S(4, 1, 8, 2), FCW_SD(4, 2, 4, 4, 2), FCW_SD(4, 2, 6, 4, 2), FCW_SD(4, 2, 8, 4, 2),
+      FCW_SD(4, 2, 12, 4, 2), FCW_SD(4, 1, 6, 2, 2), FCW_SD(4, 1, 8, 2, 2)};
 #undef FCW_E
 #undef FCW_S
+#undef FCW_SD
   int n = 0;
   for (const E& e : table) {
     if (e.p != p) continue;
@@ -775,8 +816,8 @@ int step2d_candidates(int p, int fp64, int i, Run2d* fn, int tile[3], std::strin
         char b[128];
         const char* t = fp64 ? "double" : "float";
         if (e.nbr)
-          std::snprintf(b, sizeof b, "fcw::stream2d_kernel<%s, %d, %d, %d, %d, true>", t, e.p,
-                        e.nbr, e.ty, e.nw);
+          std::snprintf(b, sizeof b, "fcw::stream2d_kernel<%s, %d, %d, %d, %d, true, %d>", t,
+                        e.p, e.nbr, e.ty, e.nw, e.pd);
         else
           std::snprintf(b, sizeof b, "fcw::step2d_kernel<%s, %d, %d, true>", t, e.p, e.ty);
         *name = b;
