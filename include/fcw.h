@@ -60,7 +60,8 @@ enum { FCW_FP64 = 0, FCW_FP32 = 1, FCW_BF16 = 2 };
  * scalar_wave_equation: rho u'' - div(rho c^2 grad u) = rho f) or 3 (isotropic
  * linear elasticity with E, nu, rho; dim must be 3).  Cells are cubes of edge
  * (hi-lo)/ncells, equal in every direction.  Voids: nvoids balls (centre [dim],
- * radius); a point is fictitious iff |x-c|^2 < r^2 for some void.  alpha is the
+ * radius); a point is fictitious iff |x-c|^2 < r^2 for some void (or, with a cube,
+ * iff it lies outside the cube).  alpha is the
  * indicator value in the fictitious domain.  The outer box boundary and the void
  * surfaces carry homogeneous Neumann conditions (natural).  tree_depth: depth of the
  * space tree in cut cells (leaf edge h / 2^depth).  precision: FCW_FP64 / FCW_FP32 /
@@ -76,12 +77,30 @@ typedef struct {
   double alpha, rho, c, E, nu;
   int32_t precision;
   void* stream;              /* hipStream_t or NULL */
+  /* Optional rotated cube (Sec. 3.1): with cube_half > 0 the physical domain is the cube
+   * {x : |sum_k (x_k - cube_center_k) cube_rot[3k + j]| <= cube_half for every axis j}
+   * minus the voids; cube_rot is row-major [3][3] (the top-left dim x dim block is used),
+   * a rotation whose column j is the cube's axis j.  Cells entirely outside the cube are
+   * dropped like cells inside a void.  cube_half = 0: no cube. */
+  double cube_center[3];
+  double cube_half;
+  double cube_rot[9];
 } fcw_problem_desc;
 
-/* Point source with Ricker time function (eq. source_time, t_s = 2 sqrt(6)/(pi f0)):
- * F(t) = f_t(t) * amp * rho * N(x) * dir_c on component c (dir ignored for scalar). */
+/* Source with Ricker time function f_t (eq. source_time, t_s = 2 sqrt(6)/(pi f0)).
+ * sigma = 0: point source, F(t) = f_t(t) * amp * rho * N(x) * dir_c on component c (dir
+ * ignored for scalar problems).
+ * sigma > 0: volumetric Gaussian source of Sec. 3.1, f(y, t) = f_t(t) * amp *
+ * exp(-|y - x|^2 / (2 sigma^2)), so F_i(t) = f_t(t) * int alpha^FCM rho amp exp(...) N_i dy
+ * (times dir_c), integrated once per call that changes the sources: over the active cells
+ * within 8 sigma of x, each split into m^dim boxes (m = ceil(h / sigma), at most 64) with
+ * a Gauss-Legendre rule of p + 3 points per direction and the pointwise indicator.  Its
+ * load enters the increment before each step (one small launch per step).  Volumetric
+ * sources are taken by fcw_step_explicit and fcw_run; the other stepping calls return
+ * FCW_E_UNSUPPORTED for them. */
 typedef struct {
   double x[3], dir[3], f0, amp;
+  double sigma;
 } fcw_source;
 
 typedef struct {
@@ -169,7 +188,8 @@ typedef struct {
   int32_t nsteps;         /* steps of this problem (problems may differ) */
   int32_t start;          /* nonzero on the first call of a run (Newmark beta = 0 start-up) */
   /* Observers (Sec. 3.2, observer traces): nrec points (host [nrec][3], copied; 0 <= nrec
-   * <= FCW_MAX_RECEIVERS; each inside the box and in no void).  The finite element field
+   * <= FCW_MAX_RECEIVERS; each inside the box; points on or beyond an immersed boundary
+   * read the field that the fictitious-domain discretisation defines there).  The field
    * u_h(x_r) = sum_a N_a(x_r) u_a of the cell holding x_r (the same cell rule as for
    * sources) is written for the state before the first step and after every step:
    * traces is device double [nrhs][nsteps + 1][nrec][ncomp]; row k holds u_k of this call
@@ -305,6 +325,17 @@ enum {
 };
 fcw_status fcw_export(const fcw_ctx* ctx, int32_t which, void* dst, int64_t capacity,
                       int64_t* count);
+
+/* Accuracy measure of Sec. 3.2 (eq. error): the average over n_obs observers of the
+ * relative L2 error of a trace over n_s time samples,
+ *   e = 1/n_obs sum_i ||Psi_i - Psi_i,ref||_2 / ||Psi_i,ref||_2,
+ * with Psi_i = (Psi(x_i, t_1), ..., Psi(x_i, t_ns)).  Host arrays laid out as fcw_run
+ * writes traces of one right-hand side and component ([rows][n_obs], row 0 the initial
+ * state): sample s = 1..n_s is row s * sim_stride of sim and row s * ref_stride of ref
+ * (so a reference run with a finer step is sampled at the same times).  Host only; no
+ * context needed.  FCW_E_ARG when an observer's reference trace is zero. */
+fcw_status fcw_trace_error(const double* sim, int64_t sim_stride, const double* ref,
+                           int64_t ref_stride, int32_t n_samples, int32_t n_obs, double* e);
 
 /* Release every device allocation of the context. */
 void fcw_destroy(fcw_ctx* ctx);

@@ -54,6 +54,9 @@ static void free_all(Ctx& c) {
   dfree(c.d_invm); dfree(c.d_kref_s); dfree(c.d_kcut_s); dfree(c.d_invm64); dfree(c.d_ubuf); dfree(c.d_ycut);
   dfree(c.d_invw); dfree(c.d_mflag); dfree(c.d_kref_bf);
   dfree(c.d_src);
+  dfree(c.d_goff);
+  dfree(c.d_gdof);
+  dfree(c.d_gval);
   dfree(c.d_rec);
   dfree(c.d_red);
   if (c.h_red) (void)hipHostFree(c.h_red);
@@ -69,6 +72,7 @@ static void free_all(Ctx& c) {
 }
 
 static bool in_any_void(const Ctx& c, const double* x) {
+  if (c.cube.on && cube_point_outside(c.cube, x)) return true;
   for (int v = 0; v < c.nvoids; ++v) {
     double d2 = 0.0;
     for (int k = 0; k < c.dim; ++k) {
@@ -154,7 +158,31 @@ fcw_status check_step_call(const fcw_ctx* c, int32_t nrhs, const void* u, const 
   return FCW_OK;
 }
 
+// The work queued after each step of a call by fcw_run / fcw_step_explicit: volumetric
+// loads of the next step, then receiver samples of the state just written.
+struct StepObservers {
+  std::vector<LoadTarget> loads;
+  std::vector<TraceTarget> traces;
+  bool empty() const { return loads.empty() && traces.empty(); }
+  static fcw_status fn(void* arg, hipStream_t s, int j) {
+    StepObservers* o = static_cast<StepObservers*>(arg);
+    fcw_status st = launch_gauss_loads(s, o->loads.data(), (int)o->loads.size(), j);
+    if (st) return st;
+    return launch_traces(s, o->traces.data(), (int)o->traces.size(), j);
+  }
+};
+
 void clear_error() { g_err.clear(); }
+
+static fcw_status refuse_volumetric(const fcw_source* src, int nrhs) {
+  if (src)
+    for (int r = 0; r < nrhs && r < kMaxSrc; ++r)
+      if (src[r].sigma > 0.0) {
+        set_error("volumetric sources are taken by fcw_step_explicit and fcw_run only");
+        return FCW_E_UNSUPPORTED;
+      }
+  return FCW_OK;
+}
 
 }  // namespace fcw
 
@@ -187,6 +215,7 @@ fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out) {
     return FCW_E_ARG;
   }
   if (!(d.alpha >= 0.0) || !(d.rho > 0.0)) { set_error("need alpha >= 0, rho > 0"); return FCW_E_ARG; }
+  if (!(d.cube_half >= 0.0)) { set_error("need cube_half >= 0"); return FCW_E_ARG; }
   if (d.ncomp == 1 && !(d.c > 0.0)) { set_error("need c > 0"); return FCW_E_ARG; }
   if (d.ncomp == 3 && !(d.E > 0.0 && d.nu > -1.0 && d.nu < 0.5)) {
     set_error("need E > 0 and -1 < nu < 0.5");
@@ -233,6 +262,13 @@ fcw_status fcw_assemble_cells(const fcw_problem_desc* desc, fcw_ctx** out) {
   c->nvoids = d.nvoids;
   c->void_c.assign(d.void_center, d.void_center + (size_t)d.nvoids * d.dim);
   c->void_r.assign(d.void_radius, d.void_radius + d.nvoids);
+  if (d.cube_half > 0.0) {
+    c->cube.on = 1;
+    c->cube.dim = d.dim;
+    c->cube.a = d.cube_half;
+    for (int k = 0; k < 3; ++k) c->cube.c[k] = (k < d.dim) ? d.cube_center[k] : 0.0;
+    for (int k = 0; k < 9; ++k) c->cube.T[k] = d.cube_rot[k];
+  }
   if (!step_supported(*c)) {
     set_error("no step kernel built for dim=%d p=%d ncomp=%d", d.dim, d.p, d.ncomp);
     delete c;
@@ -388,10 +424,6 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
           set_error("run item %d: receiver %d outside the box", i, q);
           return FCW_E_ARG;
         }
-      if (in_any_void(*r.ctx, x)) {
-        set_error("run item %d: receiver %d lies inside a void", i, q);
-        return FCW_E_ARG;
-      }
     }
     if (r.check_every < 0 || (r.check_every > 0 && check_every > 0 && r.check_every != check_every)) {
       set_error("run item %d: check_every must be >= 0 and the same for every item that checks", i);
@@ -425,18 +457,14 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
   }
   const int chunk = check_every > 0 ? check_every : std::max(maxsteps, 1);
   const bool graph = (flags & FCW_RUN_GRAPH) != 0 && !any_rec;
-  struct HookArg {
-    std::vector<TraceTarget> t;
-  };
-  auto hook_fn = [](void* arg, hipStream_t s, int j) -> fcw_status {
-    HookArg* h = static_cast<HookArg*>(arg);
-    return launch_traces(s, h->t.data(), (int)h->t.size(), j);
-  };
+  bool any_load = false;
+  for (int i = 0; i < n; ++i) any_load = any_load || (items[i].src && items[i].ctx->g_active);
+  const bool graph2 = graph && !any_load;
   for (;;) {
     // the next chunk of steps of every problem still running
     std::vector<GroupMember> group;
     std::vector<int> solo, cnt(n, 0);
-    HookArg ghook;
+    StepObservers ghook;
     bool more = false;
     for (int i = 0; i < n; ++i) {
       const fcw_run_item& r = items[i];
@@ -450,8 +478,11 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
       if (groupable_2d(*owner, *r.ctx)) {
         group.push_back(GroupMember{r.ctx, r.nrhs, r.u, r.d, r.ctx->d_ubuf, t0, dts[i], k, start});
         if (r.nrec > 0)
-          ghook.t.push_back(TraceTarget{r.ctx, r.u, r.ctx->d_ubuf, r.nrhs, k, r.nrec, r.traces,
-                                        (int64_t)r.nsteps + 1, (int64_t)ir[i].done});
+          ghook.traces.push_back(TraceTarget{r.ctx, r.u, r.ctx->d_ubuf, r.nrhs, k, r.nrec,
+                                             r.traces, (int64_t)r.nsteps + 1,
+                                             (int64_t)ir[i].done});
+        if (r.src && r.ctx->g_active)
+          ghook.loads.push_back(LoadTarget{r.ctx, r.d, r.nrhs, k, start, t0, dts[i]});
       } else {
         solo.push_back(i);
       }
@@ -463,25 +494,29 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
       saved.push_back(g.ctx->d_src);
       if (!g.ctx->d_src_active) g.ctx->d_src = nullptr;
     }
-    const StepHook gh{hook_fn, &ghook};
-    if (!group.empty()) st = run_group(*owner, group, graph, ghook.t.empty() ? nullptr : &gh);
+    const StepHook gh{StepObservers::fn, &ghook};
+    if (!group.empty()) st = run_group(*owner, group, graph2, ghook.empty() ? nullptr : &gh);
     for (size_t k = 0; k < group.size(); ++k) group[k].ctx->d_src = saved[k];
     if (st) return st;
     for (int i : solo) {
       const fcw_run_item& r = items[i];
       fcw_ctx* c = r.ctx;
-      HookArg sh;
+      StepObservers sh;
+      const int sstart = (r.start && ir[i].done == 0) ? 1 : 0;
       if (r.nrec > 0)
-        sh.t.push_back(TraceTarget{c, r.u, c->d_ubuf, r.nrhs, cnt[i], r.nrec, r.traces,
-                                   (int64_t)r.nsteps + 1, (int64_t)ir[i].done});
-      const StepHook hk{hook_fn, &sh};
+        sh.traces.push_back(TraceTarget{c, r.u, c->d_ubuf, r.nrhs, cnt[i], r.nrec, r.traces,
+                                        (int64_t)r.nsteps + 1, (int64_t)ir[i].done});
+      if (r.src && c->g_active)
+        sh.loads.push_back(
+            LoadTarget{c, r.d, r.nrhs, cnt[i], sstart, r.t0 + ir[i].done * dts[i], dts[i]});
+      const StepHook hk{StepObservers::fn, &sh};
       SourceDev* sv = c->d_src;
       if (!r.src) c->d_src = nullptr;
       hipStream_t s0 = c->stream;
       c->stream = owner->stream;
       st = run_steps(*c, c->tile_choice, r.nrhs, r.u, r.d, c->d_ubuf,
-                     r.t0 + ir[i].done * dts[i], dts[i], cnt[i],
-                     (r.start && ir[i].done == 0) ? 1 : 0, sh.t.empty() ? nullptr : &hk);
+                     r.t0 + ir[i].done * dts[i], dts[i], cnt[i], sstart,
+                     sh.empty() ? nullptr : &hk);
       c->stream = s0;
       c->d_src = sv;
       if (st) return st;
@@ -560,7 +595,11 @@ fcw_status fcw_step_explicit(fcw_ctx* c, int32_t nrhs, void* u, void* d, const f
   if (nsteps == 0) return FCW_OK;
   SourceDev* saved = c->d_src;
   if (!src) c->d_src = nullptr;
-  st = run_steps(*c, c->tile_choice, nrhs, u, d, c->d_ubuf, t0, dt, nsteps, start);
+  StepObservers ob;
+  if (src && c->g_active) ob.loads.push_back(LoadTarget{c, d, nrhs, nsteps, start, t0, dt});
+  const StepHook hk{StepObservers::fn, &ob};
+  st = run_steps(*c, c->tile_choice, nrhs, u, d, c->d_ubuf, t0, dt, nsteps, start,
+                 ob.empty() ? nullptr : &hk);
   c->d_src = saved;
   return st;
 }
@@ -792,6 +831,7 @@ fcw_status fcw_step_imex(fcw_ctx* c, int32_t nrhs, void* u, void* d, void* v_c, 
     set_error("the IMEX scheme runs on FP64 contexts only");
     return FCW_E_UNSUPPORTED;
   }
+  if ((st = refuse_volumetric(src, nrhs))) return st;
   if ((st = prepare_call(c, nrhs, u, d, src, dt, nsteps))) return st;
   if ((st = imex_prepare(*c, dt))) return st;
   if (c->imex_nc > 0 && (!v_c || !a_c)) {
@@ -816,6 +856,7 @@ fcw_status fcw_step_consistent(fcw_ctx* c, int32_t nrhs, void* u, void* d, const
     set_error("the consistent-mass step runs on FP64 contexts only");
     return FCW_E_UNSUPPORTED;
   }
+  if ((st = refuse_volumetric(src, nrhs))) return st;
   if ((st = prepare_call(c, nrhs, u, d, src, dt, nsteps))) return st;
   if ((st = imex_prepare(*c, dt))) return st;
   if (nsteps == 0) return FCW_OK;
@@ -835,6 +876,32 @@ fcw_status fcw_apply_stiffness(fcw_ctx* c, int32_t nrhs, const void* u, void* r)
     return FCW_E_ARG;
   }
   return launch_apply(*c, nrhs, u, r);
+}
+
+fcw_status fcw_trace_error(const double* sim, int64_t sim_stride, const double* ref,
+                           int64_t ref_stride, int32_t n_samples, int32_t n_obs, double* e) {
+  g_err.clear();
+  if (!sim || !ref || !e || sim_stride < 1 || ref_stride < 1 || n_samples < 1 || n_obs < 1) {
+    set_error("need traces, strides >= 1, n_samples >= 1, n_obs >= 1 and an output");
+    return FCW_E_ARG;
+  }
+  double sum = 0.0;
+  for (int i = 0; i < n_obs; ++i) {
+    double num = 0.0, den = 0.0;
+    for (int64_t s = 1; s <= n_samples; ++s) {
+      const double a = sim[s * sim_stride * n_obs + i];
+      const double b = ref[s * ref_stride * n_obs + i];
+      num += (a - b) * (a - b);
+      den += b * b;
+    }
+    if (!(den > 0.0)) {
+      set_error("observer %d has a zero reference trace", i);
+      return FCW_E_ARG;
+    }
+    sum += std::sqrt(num) / std::sqrt(den);
+  }
+  *e = sum / n_obs;
+  return FCW_OK;
 }
 
 fcw_status fcw_query(const fcw_ctx* c, fcw_info* info) {

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "cube.h"
 #include "fcw.h"
 
 namespace fcw {
@@ -57,6 +58,7 @@ struct Ctx {
   bool poisoned = false;
   std::vector<double> void_c, void_r;  // host copies
   int nvoids = 0;
+  CubeGeo cube{};  // rotated-cube domain (cube.on = 0: none)
 
   // counts
   int64_t n_cut_cand = 0;  // cut cells before reclassification
@@ -106,6 +108,15 @@ struct Ctx {
   bool d_src_active = false;  // the sources of the current batched call are set
   int src_cap = 0;
   std::vector<fcw_source> src_staged;  // host copy of the sources d_src was computed from
+  // volumetric (Gaussian) sources of the staged set: load entries (DOF, value) of
+  // right-hand side r in [g_off[r], g_off[r+1]) (host and device copies)
+  bool g_active = false;
+  std::vector<int32_t> g_off;
+  int32_t* d_goff = nullptr;
+  int64_t* d_gdof = nullptr;
+  double* d_gval = nullptr;
+  size_t g_cap = 0;
+  std::vector<int8_t> h_cls;  // host copy of the cell classes (volumetric sources)
   // receivers of the current run (FCW_MAX_RECEIVERS) and reduction buffers of the
   // growth checks and energies: [64 rhs][3][kRedBlocks] partial sums and [64][3] totals
   RecDev* d_rec = nullptr;
@@ -224,6 +235,15 @@ struct TraceTarget {
   int64_t tlen, k0;  // rows per right-hand side; row of the call's initial state
 };
 fcw_status launch_traces(hipStream_t s, const TraceTarget* t, int n, int j);
+// volumetric loads: before step k of a call (hook call j = k - 1) the increment d of each
+// target takes dt^2 M^{-1} f_t(t_k) b (dt^2 / 2 on a start call's first step)
+struct LoadTarget {
+  Ctx* ctx;
+  void* d;
+  int nrhs, nsteps, start;
+  double t0, dt;
+};
+fcw_status launch_gauss_loads(hipStream_t s, const LoadTarget* t, int n, int j);
 // per right-hand side sums over the DOFs into c.h_red[rhs * 3 + q] (synchronises):
 // energy = false: q = 0 sum d_i^2;  energy = true: q = 0 sum m_i d_i^2, q = 1 u.Ku,
 // q = 2 d.Ku, with Ku in `r` (m_i the lumped mass)

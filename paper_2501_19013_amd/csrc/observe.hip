@@ -12,7 +12,7 @@
 #include <algorithm>
 #include <cstring>
 
-#include "common.h"
+#include "step_common.h"
 
 namespace fcw {
 
@@ -128,7 +128,50 @@ __global__ __launch_bounds__(kSumThreads) void sums_final_kernel(const double* p
   if (t == 0) totals[k] = sh[0];
 }
 
+// d[rhs][dof] += coef * M^{-1} f_t(t) b for the volumetric load entries of each
+// right-hand side (grid: entries x right-hand sides)
+template <typename T>
+__global__ void gauss_apply_kernel(const int64_t* dof, const double* val, const int32_t* off,
+                                   const SourceDev* src, const double* invm64, int64_t nnodes,
+                                   int64_t ndof, double t, double coef, T* d) {
+  const int rhs = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = off[rhs + 1] - off[rhs];
+  if (i >= n) return;
+  const int64_t e = off[rhs] + i;
+  const int64_t g = dof[e];
+  const double f = coef * invm64[g % nnodes] * ricker(t, src[rhs].f0) * val[e];
+  T* dp = d + (int64_t)rhs * ndof + g;
+  *dp = (T)((double)*dp + f);
+}
+
 }  // namespace
+
+fcw_status launch_gauss_loads(hipStream_t s, const LoadTarget* t, int n, int j) {
+  for (int i = 0; i < n; ++i) {
+    const LoadTarget& x = t[i];
+    const Ctx& c = *x.ctx;
+    // the load of step j + 1 enters the increment after step j; none after the last step
+    const int k = j + 1;
+    if (k >= x.nsteps || !c.g_active) continue;
+    int64_t nmax = 0;
+    for (int r = 0; r < x.nrhs; ++r) nmax = std::max<int64_t>(nmax, c.g_off[r + 1] - c.g_off[r]);
+    if (nmax == 0) continue;
+    const double coef = (x.start && k == 0) ? 0.5 * x.dt * x.dt : x.dt * x.dt;
+    const dim3 grid((unsigned)((nmax + 255) / 256), x.nrhs);
+    const double tk = x.t0 + k * x.dt;
+    if (c.precision == FCW_FP64)
+      gauss_apply_kernel<double><<<grid, 256, 0, s>>>(c.d_gdof, c.d_gval, c.d_goff, c.d_src,
+                                                      c.d_invm64, c.nnodes, c.ndof, tk, coef,
+                                                      (double*)x.d);
+    else
+      gauss_apply_kernel<float><<<grid, 256, 0, s>>>(c.d_gdof, c.d_gval, c.d_goff, c.d_src,
+                                                     c.d_invm64, c.nnodes, c.ndof, tk, coef,
+                                                     (float*)x.d);
+    FCW_HIP(hipGetLastError());
+  }
+  return FCW_OK;
+}
 
 fcw_status launch_traces(hipStream_t s, const TraceTarget* t, int n, int j) {
   for (int base = 0; base < n; base += kMaxTargets) {

@@ -15,6 +15,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "cube.h"
 
 namespace fcw {
 
@@ -33,6 +34,27 @@ __device__ static void legendre_pair(int n, double x, double& pn, double& pn1) {
   }
   pn = p1;
   pn1 = p0;
+}
+
+// Gauss-Legendre rule of n points on [-1, 1]: the roots of P_n by Newton's method.
+__device__ static void gl_rule(int n, double* xs, double* ws) {
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    double x = -cos(pi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double pn, pn1;
+      legendre_pair(n, x, pn, pn1);
+      double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
+      double dx = pn / d1;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    double pn, pn1;
+    legendre_pair(n, x, pn, pn1);
+    double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
+    xs[i] = x;
+    ws[i] = 2.0 / ((1.0 - x * x) * d1 * d1);
+  }
 }
 
 __global__ void ref_tables_kernel(RefTables* tab, int p) {
@@ -59,24 +81,8 @@ __global__ void ref_tables_kernel(RefTables* tab, int p) {
     legendre_pair(p, tab->gll_x[i], pn, pn1);
     tab->gll_w[i] = 2.0 / (p * (p + 1.0) * pn * pn);
   }
-  // GL with n = p+1 points: roots of P_n.
-  const int n = p + 1;
-  for (int i = 0; i < n; ++i) {
-    double x = -cos(pi * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double pn, pn1;
-      legendre_pair(n, x, pn, pn1);
-      double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
-      double dx = pn / d1;
-      x -= dx;
-      if (fabs(dx) < 1e-16) break;
-    }
-    double pn, pn1;
-    legendre_pair(n, x, pn, pn1);
-    double d1 = n * (pn1 - x * pn) / (1.0 - x * x);
-    tab->gl_x[i] = x;
-    tab->gl_w[i] = 2.0 / ((1.0 - x * x) * d1 * d1);
-  }
+  // GL with n = p+1 points
+  gl_rule(p + 1, tab->gl_x, tab->gl_w);
 }
 
 // Lagrange polynomials on the GLL nodes and their derivatives at x (product rule).
@@ -154,14 +160,15 @@ __device__ static void box_ball(int dim, const double* lo, const double* hi, con
   contained = dmax2 <= r * r;
 }
 
-__global__ void classify_kernel(Grid g, int64_t ncell, int nvoids, const double* vc,
-                                const double* vr, int8_t* cls, int32_t* iscut,
-                                int32_t* nmeet) {
+__global__ void classify_kernel(Grid g, CubeGeo cube, int64_t ncell, int nvoids,
+                                const double* vc, const double* vr, int8_t* cls,
+                                int32_t* iscut, int32_t* nmeet) {
   int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= ncell) return;
   double blo[3], bhi[3];
   cell_box(g, cell, blo, bhi);
   bool any = false, inside = false;
+  if (cube.on) cube_box(cube, blo, bhi, any, inside);
   int cnt = 0;
   for (int v = 0; v < nvoids; ++v) {
     bool m, c;
@@ -305,7 +312,7 @@ fcw_status setup_classify(Ctx& c) {
   FCW_HIP(hipMallocAsync((void**)&cutpos, n * 4, c.stream));
   FCW_HIP(hipMallocAsync((void**)&voff, n * 4, c.stream));
   const unsigned nb = (unsigned)((n + 255) / 256);
-  classify_kernel<<<nb, 256, 0, c.stream>>>(g, n, c.nvoids, c.d_void_c, c.d_void_r, c.d_cls,
+  classify_kernel<<<nb, 256, 0, c.stream>>>(g, c.cube, n, c.nvoids, c.d_void_c, c.d_void_r, c.d_cls,
                                             iscut, nmeet);
   FCW_HIP(hipGetLastError());
   int32_t ncut = 0, nv = 0;
@@ -368,6 +375,7 @@ __device__ static void tree_box_bounds(int dim, const double* clo, const double*
 
 struct TreeArgs {
   Grid g;
+  CubeGeo cube;
   const int32_t* cut_cells;
   const int32_t* vptr;
   const int32_t* vidx;
@@ -458,6 +466,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
         double lo[3], hi[3];
         tree_box_bounds(DIM, clo, chi, lvl, ix, lo, hi);
         bool any = false, inside = false;
+        if (a.cube.on && !a.reference) cube_box(a.cube, lo, hi, any, inside);
         for (int v = vbeg; v < vend; ++v) {
           int vi = a.vidx[v];
           bool m, cc;
@@ -605,7 +614,8 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
         if (kind == kKindAlpha) {
           al = a.alpha;
         } else if (kind == kKindLeaf) {
-          for (int v = vbeg; v < vend; ++v) {
+          if (a.cube.on && cube_point_outside(a.cube, x)) al = a.alpha;
+          for (int v = vbeg; v < vend && al == 1.0; ++v) {
             int vi = a.vidx[v];
             const double* cc = a.vc + (int64_t)vi * DIM;
             double d2 = 0.0;
@@ -732,6 +742,7 @@ static fcw_status dispatch_tree(Ctx& c, TreeArgs& ta, int nblocks) {
 fcw_status setup_integrate(Ctx& c) {
   TreeArgs ta{};
   ta.g = make_grid(c);
+  ta.cube = c.cube;
   ta.cut_cells = c.d_cut_cells;
   ta.vptr = c.d_cut_vptr;
   ta.vidx = c.d_cut_vidx;
@@ -1597,10 +1608,265 @@ __global__ void source_kernel(SrcArgs a) {
     for (int k = 0; k < a.g.dim; ++k) { N *= L[k][r % NP1]; r /= NP1; }
     for (int cc = 0; cc < a.ncomp; ++cc) {
       double dc = (a.ncomp == 1) ? 1.0 : in.dir[cc];
-      o.b[cc * ns + loc] = a.rho * in.amp * dc * N;
+      o.b[cc * ns + loc] = (in.sigma > 0.0) ? 0.0 : a.rho * in.amp * dc * N;
     }
   }
+  // a volumetric source has no point load: its cell lies far outside every tile
+  if (in.sigma > 0.0)
+    for (int k = 0; k < 3; ++k) o.cell[k] = -(1 << 20);
   o.f0 = in.f0;
+}
+
+// --------------------------------------------------------------------------------
+// Volumetric Gaussian sources (Sec. 3.1)
+// --------------------------------------------------------------------------------
+
+struct GaussArgs {
+  Grid g;
+  CubeGeo cube;
+  int nvoids;
+  const double* vc;
+  const double* vr;
+  double alpha, rho;
+  const RefTables* tab;
+  const int32_t* cells;  // support cells
+  int ncell;
+  double xs[3], sigma, amp;
+  int m;                 // boxes per direction in a cell
+  double* y;             // [ncell][n_s]: rho amp int alpha^FCM g N_a over the cell
+};
+
+// y[e][a] = rho amp int_cell alpha^FCM(x) exp(-|x - x_s|^2 / (2 sigma^2)) N_a(x) dx with
+// m^dim boxes and a Gauss-Legendre rule of NP1 + 2 = p + 3 points per direction on each;
+// one block per support cell, thread a sums its shape function's terms in point order.
+template <int NP1>
+__global__ __launch_bounds__(128) void gauss_cells_kernel(GaussArgs a) {
+#pragma clang fp contract(off)
+  constexpr int NQ = NP1 + 2;
+  __shared__ double qx[NQ], qw[NQ];
+  if (threadIdx.x == 0) gl_rule(NQ, qx, qw);
+  __syncthreads();
+  const int dim = a.g.dim;
+  const int ns = (dim == 3) ? NP1 * NP1 * NP1 : NP1 * NP1;
+  const int la = threadIdx.x;
+  if (la >= ns || blockIdx.x >= (unsigned)a.ncell) return;
+  int ai[3] = {la % NP1, (la / NP1) % NP1, la / (NP1 * NP1)};
+  double lo[3], hi[3];
+  cell_box(a.g, a.cells[blockIdx.x], lo, hi);
+  const double sub = a.g.h / a.m;
+  const int nbox = (dim == 3) ? a.m * a.m * a.m : a.m * a.m;
+  const int nq = (dim == 3) ? NQ * NQ * NQ : NQ * NQ;
+  const double* gll = a.tab->gll_x;
+  double acc = 0.0;
+  for (int b = 0; b < nbox; ++b) {
+    const int bi[3] = {b % a.m, (b / a.m) % a.m, b / (a.m * a.m)};
+    for (int q = 0; q < nq; ++q) {
+      const int qi[3] = {q % NQ, (q / NQ) % NQ, q / (NQ * NQ)};
+      double x[3], w = 1.0, r2 = 0.0, N = 1.0;
+      for (int k = 0; k < dim; ++k) {
+        const double blo = lo[k] + sub * (double)bi[k];
+        x[k] = blo + 0.5 * sub * (qx[qi[k]] + 1.0);
+        w = w * (qw[qi[k]] * (0.5 * sub));
+        r2 = r2 + (x[k] - a.xs[k]) * (x[k] - a.xs[k]);
+        // Lagrange polynomial a_k on the GLL nodes at the local coordinate of x
+        const double xi = 2.0 * (x[k] - lo[k]) / a.g.h - 1.0;
+        double l = 1.0;
+        for (int j = 0; j < NP1; ++j)
+          if (j != ai[k]) l *= (xi - gll[j]) / (gll[ai[k]] - gll[j]);
+        N = N * l;
+      }
+      bool fict = a.cube.on && cube_point_outside(a.cube, x);
+      for (int v = 0; v < a.nvoids && !fict; ++v) {
+        const double* c = a.vc + (int64_t)v * dim;
+        double d2 = 0.0;
+        for (int k = 0; k < dim; ++k) d2 = d2 + (x[k] - c[k]) * (x[k] - c[k]);
+        fict = d2 < a.vr[v] * a.vr[v];
+      }
+      const double al = fict ? a.alpha : 1.0;
+      const double gv = exp(-0.5 * r2 / (a.sigma * a.sigma));
+      acc = acc + ((w * al) * gv) * N;
+    }
+  }
+  a.y[(int64_t)blockIdx.x * ns + la] = a.rho * a.amp * acc;
+}
+
+// b over the support nodes: node k sums its (cell slot, local node) entries in order;
+// every component gets dir_c times it
+__global__ void gauss_gather_kernel(const double* y, int ns, const int32_t* eoff,
+                                    const int32_t* ent, const int64_t* node, int nnode,
+                                    int ncomp, double d0, double d1, double d2, int64_t nnodes,
+                                    int64_t* dof_out, double* val_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnode) return;
+  double b = 0.0;
+  for (int e = eoff[k]; e < eoff[k + 1]; ++e) b = b + y[ent[e]];
+  const double dir[3] = {d0, d1, d2};
+  for (int c = 0; c < ncomp; ++c) {
+    dof_out[(int64_t)c * nnode + k] = (int64_t)c * nnodes + node[k];
+    val_out[(int64_t)c * nnode + k] = (ncomp == 1) ? b : dir[c] * b;
+  }
+}
+
+// Load vectors of the volumetric sources among src[0..nrhs): entries [g_off[r], g_off[r+1])
+// of d_gdof / d_gval for right-hand side r (empty for point sources).
+static fcw_status prepare_gauss(Ctx& c, int nrhs, const fcw_source* src) {
+  c.g_off.assign(nrhs + 1, 0);
+  c.g_active = false;
+  bool any = false;
+  for (int r = 0; r < nrhs; ++r) any = any || src[r].sigma > 0.0;
+  if (!any) return FCW_OK;
+  if (c.h_cls.empty()) {
+    c.h_cls.resize(c.ncell_total);
+    FCW_HIP(hipMemcpyAsync(c.h_cls.data(), c.d_cls, c.ncell_total, hipMemcpyDeviceToHost,
+                           c.stream));
+    FCW_HIP(hipStreamSynchronize(c.stream));
+  }
+  const int ns = c.n_s, np1 = c.p + 1;
+  // host bookkeeping per source: support cells, their nodes and the gather lists
+  struct Part {
+    std::vector<int32_t> cells, eoff, ent;
+    std::vector<int64_t> node;
+  };
+  std::vector<Part> parts(nrhs);
+  int64_t total = 0;
+  for (int r = 0; r < nrhs; ++r) {
+    if (!(src[r].sigma > 0.0)) continue;
+    Part& pt = parts[r];
+    const double sg = src[r].sigma;
+    int ilo[3] = {0, 0, 0}, ihi[3] = {1, 1, 1};
+    for (int k = 0; k < c.dim; ++k) {
+      ilo[k] = std::max(0, (int)std::floor((src[r].x[k] - 8.0 * sg - c.lo[k]) / c.h) - 1);
+      ihi[k] = std::min(c.ncells[k], (int)std::floor((src[r].x[k] + 8.0 * sg - c.lo[k]) / c.h) + 2);
+    }
+    for (int iz = ilo[2]; iz < ihi[2]; ++iz)
+      for (int iy = ilo[1]; iy < ihi[1]; ++iy)
+        for (int ix = ilo[0]; ix < ihi[0]; ++ix) {
+          const int64_t cell = ix + (int64_t)c.ncells[0] * (iy + (int64_t)c.ncells[1] * iz);
+          if (c.h_cls[cell] == kClsOut) continue;
+          const int idx[3] = {ix, iy, iz};
+          double d2 = 0.0;
+          for (int k = 0; k < c.dim; ++k) {
+            const double blo = c.lo[k] + (double)idx[k] * c.h;
+            const double bhi = c.lo[k] + (double)(idx[k] + 1) * c.h;
+            const double gap = std::max(std::max(blo - src[r].x[k], 0.0), src[r].x[k] - bhi);
+            d2 = d2 + gap * gap;
+          }
+          if (d2 < 64.0 * sg * sg) pt.cells.push_back((int32_t)cell);
+        }
+    // the cells above come in increasing cell order (x fastest); their nodes, and per
+    // node the (slot, local node) entries in slot order
+    std::vector<std::pair<int64_t, int32_t>> pairs;  // (node, slot * ns + a)
+    for (size_t q = 0; q < pt.cells.size(); ++q) {
+      const int64_t cell = pt.cells[q];
+      const int64_t cx = cell % c.ncells[0], cy = (cell / c.ncells[0]) % c.ncells[1],
+                    cz = cell / ((int64_t)c.ncells[0] * c.ncells[1]);
+      for (int a = 0; a < ns; ++a) {
+        const int ax = a % np1, ay = (a / np1) % np1, az = a / (np1 * np1);
+        const int64_t gx = cx * c.p + ax, gy = cy * c.p + ay, gz = (c.dim == 3) ? cz * c.p + az : 0;
+        const int64_t nd = gx + (int64_t)c.npts[0] * (gy + (int64_t)c.npts[1] * gz);
+        pairs.emplace_back(nd, (int32_t)(q * ns + a));
+      }
+    }
+    std::stable_sort(pairs.begin(), pairs.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                       return x.first < y.first;
+                     });
+    for (size_t i = 0; i < pairs.size(); ++i) {
+      if (i == 0 || pairs[i].first != pairs[i - 1].first) {
+        pt.node.push_back(pairs[i].first);
+        pt.eoff.push_back((int32_t)pt.ent.size());
+      }
+      pt.ent.push_back(pairs[i].second);
+    }
+    pt.eoff.push_back((int32_t)pt.ent.size());
+    total += (int64_t)pt.node.size() * c.ncomp;
+  }
+  for (int r = 0; r < nrhs; ++r)
+    c.g_off[r + 1] = c.g_off[r] + (int32_t)(parts[r].node.size() * c.ncomp);
+  if ((size_t)total > c.g_cap) {
+    if (c.d_gdof) FCW_HIP(hipFree(c.d_gdof));
+    if (c.d_gval) FCW_HIP(hipFree(c.d_gval));
+    c.d_gdof = nullptr;
+    c.d_gval = nullptr;
+    c.footprint -= (int64_t)c.g_cap * 16;
+    FCW_HIP(hipMalloc((void**)&c.d_gdof, total * sizeof(int64_t)));
+    FCW_HIP(hipMalloc((void**)&c.d_gval, total * sizeof(double)));
+    c.g_cap = (size_t)total;
+    c.footprint += (int64_t)c.g_cap * 16;
+  }
+  if (!c.d_goff) {
+    FCW_HIP(hipMalloc((void**)&c.d_goff, (kMaxSrc + 1) * sizeof(int32_t)));
+    c.footprint += (kMaxSrc + 1) * sizeof(int32_t);
+  }
+  FCW_HIP(hipMemcpyAsync(c.d_goff, c.g_off.data(), (nrhs + 1) * sizeof(int32_t),
+                         hipMemcpyHostToDevice, c.stream));
+  for (int r = 0; r < nrhs; ++r) {
+    Part& pt = parts[r];
+    if (pt.cells.empty()) continue;
+    const int nc = (int)pt.cells.size(), nn = (int)pt.node.size();
+    int32_t *dcells = nullptr, *deoff = nullptr, *dent = nullptr;
+    int64_t* dnode = nullptr;
+    double* dy = nullptr;
+    auto release = [&]() {
+      if (dcells) (void)hipFree(dcells);
+      if (deoff) (void)hipFree(deoff);
+      if (dent) (void)hipFree(dent);
+      if (dnode) (void)hipFree(dnode);
+      if (dy) (void)hipFree(dy);
+    };
+    hipError_t e = hipMalloc((void**)&dcells, nc * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&deoff, (nn + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&dent, pt.ent.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&dnode, nn * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&dy, (size_t)nc * ns * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dcells, pt.cells.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(deoff, pt.eoff.data(), (nn + 1) * sizeof(int32_t), hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dent, pt.ent.data(), pt.ent.size() * sizeof(int32_t), hipMemcpyHostToDevice, c.stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dnode, pt.node.data(), nn * sizeof(int64_t), hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) {
+      release();
+      return hip_fail(e, "volumetric source staging");
+    }
+    GaussArgs ga{};
+    ga.g = make_grid(c);
+    ga.cube = c.cube;
+    ga.nvoids = c.nvoids;
+    ga.vc = c.d_void_c;
+    ga.vr = c.d_void_r;
+    ga.alpha = c.alpha;
+    ga.rho = c.rho;
+    ga.tab = c.d_tab;
+    ga.cells = dcells;
+    ga.ncell = nc;
+    for (int k = 0; k < 3; ++k) ga.xs[k] = src[r].x[k];
+    ga.sigma = src[r].sigma;
+    ga.amp = src[r].amp;
+    ga.m = std::max(1, std::min(64, (int)std::ceil(c.h / src[r].sigma)));
+    ga.y = dy;
+    switch (np1) {
+      case 2: gauss_cells_kernel<2><<<nc, 128, 0, c.stream>>>(ga); break;
+      case 3: gauss_cells_kernel<3><<<nc, 128, 0, c.stream>>>(ga); break;
+      case 4: gauss_cells_kernel<4><<<nc, 128, 0, c.stream>>>(ga); break;
+      case 5: gauss_cells_kernel<5><<<nc, 128, 0, c.stream>>>(ga); break;
+      default:
+        release();
+        set_error("volumetric sources not built for p=%d", c.p);
+        return FCW_E_UNSUPPORTED;
+    }
+    gauss_gather_kernel<<<(nn + 255) / 256, 256, 0, c.stream>>>(
+        dy, ns, deoff, dent, dnode, nn, c.ncomp, src[r].dir[0], src[r].dir[1], src[r].dir[2],
+        c.nnodes, c.d_gdof + c.g_off[r], c.d_gval + c.g_off[r]);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    release();
+    if (e != hipSuccess) return hip_fail(e, "volumetric source integration");
+  }
+  c.g_active = true;
+  return FCW_OK;
 }
 
 // Receivers: the cell holding each point (the rule of the sources) and N_a(x_r).
@@ -1682,6 +1948,12 @@ fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src, bool remembe
     set_error("at most %d right-hand sides per call (got %d)", kMaxSrc, nrhs);
     return FCW_E_ARG;
   }
+  if (!remember)
+    for (int r = 0; r < nrhs; ++r)
+      if (src[r].sigma > 0.0) {
+        set_error("volumetric sources need fcw_step_explicit or fcw_run (source %d)", r);
+        return FCW_E_ARG;
+      }
   if (!c.d_src) {
     // SourceDev[kMaxSrc] followed by a staging copy of the caller's fcw_source[kMaxSrc]
     FCW_HIP(hipMalloc((void**)&c.d_src, kMaxSrc * (sizeof(SourceDev) + sizeof(fcw_source))));
@@ -1719,7 +1991,13 @@ fcw_status prepare_sources(Ctx& c, int nrhs, const fcw_source* src, bool remembe
   FCW_HIP(hipGetLastError());
   // the staged host array must stay valid until the copy has run
   FCW_HIP(hipStreamSynchronize(c.stream));
-  if (remember) c.src_staged.assign(src, src + nrhs);
+  if (!remember) return FCW_OK;  // (volumetric sources were refused above)
+  fcw_status st = prepare_gauss(c, nrhs, src);
+  if (st) {
+    c.src_staged.clear();
+    return st;
+  }
+  c.src_staged.assign(src, src + nrhs);
   return FCW_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_apply_stiffness",
            "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
-           "fcw_export", "fcw_destroy", "fcw_last_error")
+           "fcw_export", "fcw_destroy", "fcw_last_error", "fcw_trace_error")
 
 
 class ProblemDesc(C.Structure):
@@ -37,12 +37,14 @@ class ProblemDesc(C.Structure):
                 ("tree_depth", C.c_int32), ("nvoids", C.c_int32),
                 ("void_center", C.POINTER(C.c_double)), ("void_radius", C.POINTER(C.c_double)),
                 ("alpha", C.c_double), ("rho", C.c_double), ("c", C.c_double), ("E", C.c_double),
-                ("nu", C.c_double), ("precision", C.c_int32), ("stream", C.c_void_p)]
+                ("nu", C.c_double), ("precision", C.c_int32), ("stream", C.c_void_p),
+                ("cube_center", C.c_double * 3), ("cube_half", C.c_double),
+                ("cube_rot", C.c_double * 9)]
 
 
 class Source(C.Structure):
     _fields_ = [("x", C.c_double * 3), ("dir", C.c_double * 3), ("f0", C.c_double),
-                ("amp", C.c_double)]
+                ("amp", C.c_double), ("sigma", C.c_double)]
 
 
 class RunResult(C.Structure):
@@ -115,6 +117,8 @@ def load(path=LIB_PATH):
     lib.fcw_set_stream.argtypes = [vp, vp]
     lib.fcw_kernel_times.argtypes = [vp, i32, i32, C.POINTER(f64), C.POINTER(f64)]
     lib.fcw_run.argtypes = [C.POINTER(RunItem), i32, i32]
+    lib.fcw_trace_error.argtypes = [C.POINTER(f64), C.c_int64, C.POINTER(f64), C.c_int64, i32,
+                                    i32, C.POINTER(f64)]
     lib.fcw_destroy.argtypes = [vp]
     lib.fcw_destroy.restype = None
     lib.fcw_last_error.argtypes = []
@@ -152,6 +156,7 @@ def _sources(srcs):
         arr[i].dir[:] = d[:3]
         arr[i].f0 = float(s.get("f0", 10.0))
         arr[i].amp = float(s.get("amp", 1.0))
+        arr[i].sigma = float(s.get("sigma", 0.0))
     return arr
 
 
@@ -180,6 +185,13 @@ def assemble_cells(cfg, precision="fp64", stream=None):
     desc.nu = float(cfg.get("nu", 0.3))
     desc.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     desc.stream = stream
+    cube = cfg.get("cube")
+    if cube is not None:
+        desc.cube_center[:] = [float(v) for v in list(cube["center"]) + [0.0] * (3 - dim)]
+        desc.cube_half = float(cube["half"])
+        rot = np.zeros((3, 3))
+        rot[:dim, :dim] = np.asarray(cube["rot"], dtype=np.float64).reshape(dim, dim)
+        desc.cube_rot[:] = [float(v) for v in rot.ravel()]
     ctx = C.c_void_p()
     _check(lib.fcw_assemble_cells(C.byref(desc), C.byref(ctx)))
     return ctx
@@ -339,6 +351,22 @@ def export(ctx, which):
     out = np.empty(n.value, dtype=_ARR_DTYPE.get(which, np.float64))
     _check(lib.fcw_export(ctx, int(which), out.ctypes.data, n.value, C.byref(n)))
     return out
+
+
+def trace_error(sim, ref, sim_stride, ref_stride, n_samples):
+    """fcw_trace_error: eq. error of host traces [rows][n_obs] sampled every sim_stride /
+    ref_stride rows (rows 1 .. n_samples of each)."""
+    sim = np.ascontiguousarray(sim, dtype=np.float64)
+    ref = np.ascontiguousarray(ref, dtype=np.float64)
+    nobs = sim.shape[1]
+    if (ref.shape[1] != nobs or sim.shape[0] < n_samples * sim_stride + 1
+            or ref.shape[0] < n_samples * ref_stride + 1):
+        raise ValueError("traces too short for the requested samples")
+    e = C.c_double()
+    P = C.POINTER(C.c_double)
+    _check(load().fcw_trace_error(sim.ctypes.data_as(P), int(sim_stride), ref.ctypes.data_as(P),
+                                  int(ref_stride), int(n_samples), int(nobs), C.byref(e)))
+    return e.value
 
 
 def destroy(ctx):

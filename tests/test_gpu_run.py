@@ -218,16 +218,71 @@ def test_energy_matches_oracle(c1):
     s.close()
 
 
-def test_receiver_errors(c1):
+def test_receiver_errors_and_boundary_points(c1):
+    """A receiver outside the box is refused; one on the hole's surface or inside the hole
+    reads the fictitious-domain field there, as the oracle's observer rows do."""
+    import torch
     from paper_2501_19013_amd import fcw
     from paper_2501_19013_amd.solver import Solver
-    cfg, _, dt = c1
+    cfg, disc, dt = c1
     s = Solver(cfg, precision="fp64")
     u, d = s.zeros(1), s.zeros(1)
     tr = _traces_buf(1, 5, 1)
-    for bad in ((0.5, 0.5), (1.2, 0.3)):  # inside the hole; outside the box
-        with pytest.raises(fcw.FcwError) as e:
-            fcw.run([dict(ctx=s.ctx, nrhs=1, u=u, d=d, dt=dt, nsteps=5, start=1,
-                          receivers=[bad], traces=tr)])
-        assert e.value.status == fcw.FCW_E_ARG
+    with pytest.raises(fcw.FcwError) as e:
+        fcw.run([dict(ctx=s.ctx, nrhs=1, u=u, d=d, dt=dt, nsteps=5, start=1,
+                      receivers=[(1.2, 0.3)], traces=tr)])
+    assert e.value.status == fcw.FCW_E_ARG
+    rec = [(0.75, 0.5), (0.6, 0.55)]  # on the hole's surface; inside the hole
+    nsteps = 120
+    tr = _traces_buf(1, nsteps, len(rec))
+    fcw.run([dict(ctx=s.ctx, nrhs=1, u=u, d=d, sources=SRC2[:1], dt=dt, nsteps=nsteps, start=1,
+                  receivers=rec, traces=tr)])
+    torch.cuda.synchronize()
+    ref = _oracle_traces(disc, dt, nsteps, SRC2[:1], rec)[0]
+    got = tr.cpu().numpy()[0, :, :, 0]
+    assert np.abs(ref).max() > 0
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
     s.close()
+
+
+def test_gaussian_source_2d_chunked_and_batched(c1):
+    """A volumetric Gaussian source (and a point source on the second right-hand side):
+    fcw_step_explicit in two calls against the oracle (FP64, 1e-10); fcw_run with a second
+    problem in the same launches equals the problem run alone in one call, bit for bit,
+    and the second problem matches its oracle run."""
+    import torch
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cfg, disc, dt = c1
+    srcs = [dict(x=(0.2, 0.15), sigma=0.03, f0=10.0, amp=1.0), SRC2[1]]
+    nsteps = 130
+    refs = [timestep.cdm(disc, dt, nsteps, sources=[q])["u"] for q in srcs]
+    s = Solver(cfg, precision="fp64")
+    u, d = s.zeros(2), s.zeros(2)
+    s.step(u, d, srcs, dt, 47, start=True)
+    s.step(u, d, srcs, dt, nsteps - 47, t0=47 * dt)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    for q in range(2):
+        assert np.linalg.norm(got[q] - refs[q]) <= 1e-10 * np.linalg.norm(refs[q]), q
+    # batched with another problem of the same kind
+    cfg2 = dict(cfg)
+    cc, rr = workloads.random_circles(seed=43, count=5, rmin=0.03, rmax=0.07,
+                                      keep_clear=((0.1, 0.1), (0.7, 0.3), (0.2, 0.15)))
+    cfg2.update(ncells=(20, 20), void_center=cc, void_radius=rr)
+    s2 = Solver(cfg2, precision="fp64")
+    dt2 = 0.9 * s2.critical_dt()
+    ua, da = s.zeros(2), s.zeros(2)
+    ub, db = s2.zeros(2), s2.zeros(2)
+    fcw.run([dict(ctx=s.ctx, nrhs=2, u=ua, d=da, sources=srcs, dt=dt, nsteps=nsteps, start=1),
+             dict(ctx=s2.ctx, nrhs=2, u=ub, d=db, sources=srcs, dt=dt2, nsteps=90, start=1)])
+    # the same problem alone in one call (one call: the same source times as the batch)
+    u1, d1 = s.zeros(2), s.zeros(2)
+    s.step(u1, d1, srcs, dt, nsteps, start=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(ua.cpu().numpy(), u1.cpu().numpy())
+    disc2 = problem.build(problem.Problem.from_config(cfg2))
+    ref2 = timestep.cdm(disc2, dt2, 90, sources=[srcs[0]])["u"]
+    assert np.linalg.norm(ub[0].cpu().numpy() - ref2) <= 1e-10 * np.linalg.norm(ref2)
+    s.close()
+    s2.close()
