@@ -213,10 +213,12 @@ typedef struct {
 enum { FCW_RUN_GRAPH = 1 };
 
 /* Advance several problems, each by its own nsteps central-difference steps.  Problems
- * of one kind (2-D scalar, same p and precision) are advanced together: one launch per
- * step covers every (problem, right-hand side, tile) of the group, problems that have
- * finished their steps drop out of later launches.  Other problems run one after
- * another.  All work goes on the stream of the first problem's context.  With
+ * of the first problem's kind (2-D scalar with the same p and precision, or 3-D with the
+ * same p, components and precision) are advanced together: one cut-cell launch and one
+ * step launch per step cover every problem, right-hand side and tile of the group (3-D:
+ * the first problem's step configuration for all, its resident blocks shared out by
+ * tiles), and problems that have finished their steps drop out of later launches.  Other
+ * problems run one after another.  All work goes on the stream of the first problem's context.  With
  * FCW_RUN_GRAPH the launches of a group are captured once into a HIP graph and replayed
  * (the graph is cached and reused while the group's shape is unchanged); a group with
  * receivers or growth checks runs without a graph.  Sources, state layout and errors as

@@ -475,7 +475,7 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
       cnt[i] = k;
       const double t0 = r.t0 + ir[i].done * dts[i];
       const int start = (r.start && ir[i].done == 0) ? 1 : 0;
-      if (groupable_2d(*owner, *r.ctx)) {
+      if (groupable_2d(*owner, *r.ctx) || groupable_3d(*owner, *r.ctx)) {
         group.push_back(GroupMember{r.ctx, r.nrhs, r.u, r.d, r.ctx->d_ubuf, t0, dts[i], k, start});
         if (r.nrec > 0)
           ghook.traces.push_back(TraceTarget{r.ctx, r.u, r.ctx->d_ubuf, r.nrhs, k, r.nrec,
@@ -495,7 +495,10 @@ fcw_status fcw_run(const fcw_run_item* items, int32_t n, int32_t flags) {
       if (!g.ctx->d_src_active) g.ctx->d_src = nullptr;
     }
     const StepHook gh{StepObservers::fn, &ghook};
-    if (!group.empty()) st = run_group(*owner, group, graph2, ghook.empty() ? nullptr : &gh);
+    if (!group.empty())
+      st = (owner->dim == 3)
+               ? run_group3d(*owner, group, graph2, ghook.empty() ? nullptr : &gh)
+               : run_group(*owner, group, graph2, ghook.empty() ? nullptr : &gh);
     for (size_t k = 0; k < group.size(); ++k) group[k].ctx->d_src = saved[k];
     if (st) return st;
     for (int i : solo) {

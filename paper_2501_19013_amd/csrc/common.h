@@ -250,6 +250,10 @@ fcw_status launch_gauss_loads(hipStream_t s, const LoadTarget* t, int n, int j);
 fcw_status state_sums(Ctx& c, hipStream_t s, int nrhs, const void* u, const void* d,
                       const void* r, bool energy);
 bool groupable_2d(const Ctx& a, const Ctx& b);
+// one batched group of 3-D problems of one kind (dim 3, same p, ncomp and precision)
+fcw_status run_group3d(Ctx& owner, const std::vector<GroupMember>& m, bool graph,
+                       const StepHook* hook = nullptr);
+bool groupable_3d(const Ctx& a, const Ctx& b);
 fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
 // lanczos.hip
 fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax);

@@ -41,7 +41,7 @@ __device__ static inline void load_dword_to_lds(const void* gsrc, void* lds_wave
 }
 
 template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, int MODE, bool BF, int NW>
-__global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
+__global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> ain) {
   constexpr int NT = 64 * NW;  // threads of the block (NW waves)
   constexpr int NP1 = P + 1;
   constexpr int NS = ipow(NP1, DIM);
@@ -89,6 +89,27 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
   __shared__ double ft_s;
   __shared__ int src_on;
 
+  // ---- the block's problem: the launch argument itself, or in a batched launch the
+  // record of the problem whose block range holds this block ----
+  StepArgs<T> a = ain;
+  int bx = (int)blockIdx.x, nbk = (int)gridDim.x;
+  if (MODE == kModeStep && ain.nprob > 0) {
+    int pi = 0;
+    while (pi + 1 < ain.nprob && ain.bstart[pi + 1] <= bx) ++pi;
+    a = ain.probs[pi];
+    const int j = ain.jstep;
+    if (j >= a.nsteps || (int)blockIdx.y >= a.nrhs) return;
+    bx -= ain.bstart[pi];
+    nbk = ain.bstart[pi + 1] - ain.bstart[pi];
+    // the state after step j of a call sits in the caller's buffer when nsteps - 1 - j is
+    // even (the last step always writes it)
+    T* ua = a.u_out;
+    const bool par = ((a.nsteps - 1 - j) & 1) != 0;
+    a.u_in = par ? ua : a.u_alt;
+    a.u_out = par ? a.u_alt : ua;
+    a.t = __dadd_rn(a.t0, __dmul_rn((double)j, a.dt));  // as the host forms t0 + j dt
+    a.start = (a.start && j == 0) ? 1 : 0;
+  }
   const int rhs = blockIdx.y;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -135,7 +156,7 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
 
   // ---- the block's tiles: a stretch of the tiles of its XCD (blocks b, b + 8, ... run
   // on one XCD), so neighbouring tiles share halo rows in that XCD's L2 ----
-  const int nbx = (int)(gridDim.x / 8);
+  const int nbx = nbk / 8;
   // cell infos of the region of a tile (class or cut-cell index), one per thread and it
   auto load_info = [&](int tile, int out[NCI]) {
     const int rx = (tile % a.ntile[0]) * TX - 1;
@@ -156,11 +177,11 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> a) {
   // with its first loads
   int inf_next[NCI];
   {
-    const int t0 = (int)(blockIdx.x % 8) * a.chunk + (int)(blockIdx.x / 8);
-    if ((int)(blockIdx.x / 8) < a.chunk && t0 < a.ntiles) load_info(t0, inf_next);
+    const int t0 = (bx % 8) * a.chunk + bx / 8;
+    if (bx / 8 < a.chunk && t0 < a.ntiles) load_info(t0, inf_next);
   }
-  for (int tk = (int)(blockIdx.x / 8); tk < a.chunk; tk += nbx) {
-    const int tile = (int)(blockIdx.x % 8) * a.chunk + tk;
+  for (int tk = bx / 8; tk < a.chunk; tk += nbx) {
+    const int tile = (bx % 8) * a.chunk + tk;
     if (tile >= a.ntiles) break;
     const int tx = tile % a.ntile[0];
     const int ty = (DIM >= 2) ? (tile / a.ntile[0]) % a.ntile[1] : 0;
@@ -586,6 +607,17 @@ static StepArgs<T> make_args(const Ctx& c, int tx, int ty, int tz) {
 
 using RunFn = fcw_status (*)(Ctx&, int, int, const void*, void*, void*, double, double, int);
 
+// A step configuration's batched form (several problems of its kind per launch).
+struct BatchOps {
+  int (*blocks_per_xcd)();                  // resident blocks per XCD of the kernel
+  int (*ntiles)(const Ctx&);                // tiles of a problem
+  // record of one problem's call: caller state ua, partner ub, increment d, time origin,
+  // step, step count, start flag, right-hand sides
+  void (*fill)(Ctx&, void*, void*, void*, void*, double, double, int, int, int);
+  fcw_status (*run)(hipStream_t, const void*, const int32_t*, int, int, int, int);
+  size_t rec_size;
+};
+
 template <typename T, int DIM, int P, int NCOMP, int TX, int TY, int TZ, bool BF = false, int NW = 4>
 struct TileCfg {
   // 3-D: persistent launch, 8 x (blocks per XCD) blocks each walking its XCD's tiles, so
@@ -644,12 +676,45 @@ struct TileCfg {
     StepArgs<T> a = args(c, uin, uout, d, t, dt, start, mode);
     return launch(tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF, NW>, c, a, nrhs);
   }
+  // ---- batched form ----
+  static int blocks_per_xcd() {
+    return resident_per_xcd(
+        (const void*)tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF, NW>, 64 * NW);
+  }
+  static int ntiles(const Ctx& c) { return make_args<T>(c, TX, TY, TZ).ntiles; }
+  static void fill(Ctx& c, void* out, void* ua, void* ub, void* d, double t0, double dt,
+                   int nsteps, int start, int nrhs) {
+    StepArgs<T> a = args(c, ua, ua, d, t0, dt, start, kModeStep);
+    a.u_alt = (T*)ub;
+    a.t0 = t0;
+    a.dt = dt;
+    a.nsteps = nsteps;
+    a.nrhs = nrhs;
+    std::memcpy(out, &a, sizeof a);
+  }
+  static fcw_status run_batch(hipStream_t s, const void* recs, const int32_t* bstart, int nprob,
+                              int nblocks, int maxrhs, int j) {
+    StepArgs<T> a{};
+    a.probs = (const StepArgs<T>*)recs;
+    a.bstart = bstart;
+    a.nprob = nprob;
+    a.jstep = j;
+    tile_kernel<T, DIM, P, NCOMP, TX, TY, TZ, kModeStep, BF, NW>
+        <<<dim3(nblocks, maxrhs, 1), 64 * NW, 0, s>>>(a);
+    FCW_HIP(hipGetLastError());
+    return FCW_OK;
+  }
+  static const BatchOps* ops() {
+    static const BatchOps o{&blocks_per_xcd, &ntiles, &fill, &run_batch, sizeof(StepArgs<T>)};
+    return &o;
+  }
 };
 
 struct Cand {
   RunFn fn;
   int tile[3];
   int nw;  // waves per block
+  const BatchOps* ops;
 };
 
 // Candidate tile shapes per problem kind; entry 0 is the default and serves every mode.
@@ -659,13 +724,16 @@ static int candidates(const Ctx& c, Cand* out) {
   int n = 0;
 #define FCW_C0(D, PP, NC, TX, TY, TZ)                  \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run, {TX, TY, TZ}, 4};
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run, {TX, TY, TZ}, 4,              \
+                    TileCfg<T, D, PP, NC, TX, TY, TZ>::ops()};
 #define FCW_C(D, PP, NC, TX, TY, TZ)                   \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run_step, {TX, TY, TZ}, 4};
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ>::run_step, {TX, TY, TZ}, 4,         \
+                    TileCfg<T, D, PP, NC, TX, TY, TZ>::ops()};
 #define FCW_CW(D, PP, NC, TX, TY, TZ, NW)              \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::run_step, {TX, TY, TZ}, NW};
+    out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::run_step, {TX, TY, TZ}, NW, \
+                    TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::ops()};
   if constexpr (F64) {
     FCW_C0(2, 1, 1, 32, 16, 1) FCW_C(2, 1, 1, 16, 16, 1)
     FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1)
@@ -708,13 +776,16 @@ static int candidates_bf(const Ctx& c, Cand* out) {
   int n = 0;
 #define FCW_B0(D, PP, NC, TX, TY, TZ)                  \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run, {TX, TY, TZ}, 4};
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run, {TX, TY, TZ}, 4,    \
+                    TileCfg<float, D, PP, NC, TX, TY, TZ, true>::ops()};
 #define FCW_B(D, PP, NC, TX, TY, TZ)                   \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run_step, {TX, TY, TZ}, 4};
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true>::run_step, {TX, TY, TZ}, 4, \
+                    TileCfg<float, D, PP, NC, TX, TY, TZ, true>::ops()};
 #define FCW_BW(D, PP, NC, TX, TY, TZ, NW)              \
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
-    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true, NW>::run_step, {TX, TY, TZ}, NW};
+    out[n++] = Cand{&TileCfg<float, D, PP, NC, TX, TY, TZ, true, NW>::run_step, {TX, TY, TZ}, \
+                    NW, TileCfg<float, D, PP, NC, TX, TY, TZ, true, NW>::ops()};
   FCW_B0(2, 1, 1, 32, 32, 1)
   FCW_B0(2, 2, 1, 16, 16, 1) FCW_B(2, 2, 1, 16, 8, 1)
   FCW_B0(2, 3, 1, 16, 16, 1) FCW_B(2, 3, 1, 16, 8, 1)
@@ -926,6 +997,123 @@ fcw_status run_group(Ctx& owner, const std::vector<GroupMember>& m, bool graph,
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     owner.graph_fn = (const void*)sc.f2d;
     owner.graph_nitems = nitems;
+    owner.graph_nsteps = nmax;
+    owner.graph_ncut = ncutblk;
+    owner.graph_wl = owner.d_wl;
+    owner.graph_nprob = nprob;
+    owner.graph_ncutprob = ncutprob;
+  }
+  FCW_HIP(hipGraphLaunch(owner.graph_exec, owner.stream));
+  return FCW_OK;
+}
+
+bool groupable_3d(const Ctx& a, const Ctx& b) {
+  return a.dim == 3 && b.dim == 3 && a.ncomp == b.ncomp && a.p == b.p &&
+         a.precision == b.precision;
+}
+
+// A batched group of 3-D problems of one kind: the owner's step configuration (kernel and
+// tile shape) for every member; the resident blocks of that kernel are shared out in
+// proportion to the members' tiles (at least one per XCD each), and every launch walks
+// each member's tiles with its own share.  One cut-cell launch and one step launch per
+// step cover all members.
+fcw_status run_group3d(Ctx& owner, const std::vector<GroupMember>& m, bool graph,
+                       const StepHook* hook) {
+  const bool fp64 = owner.precision == FCW_FP64;
+  Cand cs[kMaxCand];
+  const int nc = cands_for(owner, fp64, cs);
+  if (nc == 0) {
+    set_error("no step kernel built for this 3-D kind");
+    return FCW_E_UNSUPPORTED;
+  }
+  int choice = owner.tile_choice;
+  if (choice < 0 || choice >= nc) choice = 0;
+  const BatchOps* ops = cs[choice].ops;
+  const size_t rs = ops->rec_size;
+  const size_t cps = cutprob_size(fp64);
+  std::vector<const GroupMember*> act;
+  int64_t tiles_total = 0;
+  for (const GroupMember& g : m)
+    if (g.nsteps > 0) {
+      act.push_back(&g);
+      tiles_total += ops->ntiles(*g.ctx);
+    }
+  if (act.empty()) return FCW_OK;
+  const int nprob = (int)act.size();
+  const int per_xcd = std::max(1, ops->blocks_per_xcd());
+  std::vector<char> rec(rs * nprob), cut;
+  std::vector<int32_t> bstart(nprob + 1, 0);
+  int maxrhs = 1, nmax = 0, ncutprob = 0;
+  int64_t ncutblk = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const GroupMember& g = *act[i];
+    Ctx& c = *g.ctx;
+    fcw_status st = ensure_ycut(c, g.nrhs);
+    if (st) return st;
+    if (c.n_cut_cand > 0) {
+      cut.resize(cps * (ncutprob + 1));
+      ncutblk += cutprob_fill(c, cut.data() + cps * ncutprob, g.u, g.scratch, g.nrhs, g.nsteps,
+                              ncutblk);
+      ++ncutprob;
+    }
+    if (g.nsteps % 2 == 1)
+      FCW_HIP(hipMemcpyAsync(g.scratch, g.u, (size_t)g.nrhs * c.ndof * c.state_bytes(),
+                             hipMemcpyDeviceToDevice, owner.stream));
+    ops->fill(c, rec.data() + rs * i, g.u, g.scratch, g.d, g.t0, g.dt, g.nsteps, g.start,
+              g.nrhs);
+    const int nt = ops->ntiles(c);
+    const int chunk = (nt + 7) / 8;
+    const int share = (int)((int64_t)per_xcd * nt / std::max<int64_t>(tiles_total, 1));
+    const int nbx = std::max(1, std::min(chunk, share));
+    bstart[i + 1] = bstart[i] + 8 * nbx;
+    maxrhs = std::max(maxrhs, g.nrhs);
+    nmax = std::max(nmax, g.nsteps);
+  }
+  const int nblocks = bstart[nprob];
+  // work list: records, block starts (padded to 16 bytes), cut-cell records
+  const size_t bs_bytes = ((bstart.size() * sizeof(int32_t)) + 15) / 16 * 16;
+  std::vector<char> host(rec.size() + bs_bytes + cut.size(), 0);
+  std::memcpy(host.data(), rec.data(), rec.size());
+  std::memcpy(host.data() + rec.size(), bstart.data(), bstart.size() * sizeof(int32_t));
+  if (!cut.empty()) std::memcpy(host.data() + rec.size() + bs_bytes, cut.data(), cut.size());
+  fcw_status st = stage_worklist(owner, host.data(), host.size());
+  if (st) return st;
+  const int32_t* dbs = (const int32_t*)((char*)owner.d_wl + rec.size());
+  const void* dcut = (const char*)owner.d_wl + rec.size() + bs_bytes;
+  auto step = [&](int j) -> fcw_status {
+    if (ncutblk > 0) {
+      fcw_status s2 = launch_cut(owner, owner.stream, dcut, ncutprob, nullptr, ncutblk, j);
+      if (s2) return s2;
+    }
+    return ops->run(owner.stream, owner.d_wl, dbs, nprob, nblocks, maxrhs, j);
+  };
+  if (!graph || hook) {
+    if (hook && (st = hook->fn(hook->arg, owner.stream, -1))) return st;
+    for (int j = 0; j < nmax; ++j) {
+      if ((st = step(j))) return st;
+      if (hook && (st = hook->fn(hook->arg, owner.stream, j))) return st;
+    }
+    return FCW_OK;
+  }
+  // graph replay, cached while the kernels, the work-list buffer and its layout, the
+  // cut-block count and the step count stay the same
+  if (!(owner.graph_exec && owner.graph_fn == (const void*)ops &&
+        owner.graph_nitems == nblocks && owner.graph_nsteps == nmax &&
+        owner.graph_ncut == ncutblk && owner.graph_wl == owner.d_wl &&
+        owner.graph_nprob == nprob && owner.graph_ncutprob == ncutprob)) {
+    if (owner.graph_exec) FCW_HIP(hipGraphExecDestroy(owner.graph_exec));
+    owner.graph_exec = nullptr;
+    hipGraph_t gr = nullptr;
+    FCW_HIP(hipStreamBeginCapture(owner.stream, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < nmax && st == FCW_OK; ++j) st = step(j);
+    hipError_t e = hipStreamEndCapture(owner.stream, &gr);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&owner.graph_exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    owner.graph_fn = (const void*)ops;
+    owner.graph_nitems = nblocks;
     owner.graph_nsteps = nmax;
     owner.graph_ncut = ncutblk;
     owner.graph_wl = owner.d_wl;

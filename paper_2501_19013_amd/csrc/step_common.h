@@ -55,6 +55,18 @@ struct StepArgs {
   const T* ycut;  // [nrhs][ncand][n_loc] cut-cell products of this step (step / apply)
   const void* kref_bf;  // [n_loc^2] bf16 K_ref (BF16 form)
   int64_t ncand;
+  // Batched launches (several problems of one kind; step mode only): the launch argument
+  // carries nprob > 0, the device records of the problems and the first block of each
+  // (bstart[nprob] = grid size), and the step index jstep of the call.  A record holds
+  // the caller's state in u_out and its ping-pong partner in u_alt, the time origin t0,
+  // the step dt, the step count and right-hand sides of its call, and start as for the
+  // whole call; the kernel derives u_in / u_out, t and start of step jstep from them.
+  const StepArgs* probs;
+  const int32_t* bstart;
+  int nprob, jstep;
+  T* u_alt;
+  double t0, dt;
+  int nsteps, nrhs;
 };
 
 __device__ static inline double ricker(double t, double f0) {

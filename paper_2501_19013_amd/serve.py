@@ -10,9 +10,9 @@ counts) arrive over time.  The loop
   stream), so set-ups overlap each other and the stepping of the problems already
   resident;
 * keeps every admitted problem's fields resident on the device and advances all of
-  them by one quantum of steps per round: problems of one kind (2-D scalar, same p
-  and precision) share one fused launch per step through fcw_run, others follow on the
-  same stream;
+  them by one quantum of steps per round: problems of one kind (dimension, components,
+  p; one precision) share one fused launch per step through fcw_run, the kinds follow
+  one another on the same stream;
 * retires a problem when its steps are done (its latency is completion - arrival) and
   frees its memory, so waiting requests can join at the next quantum boundary.
 
@@ -198,10 +198,8 @@ class Server:
                                             dt=r.dt or 0.0,
                                             dt_max=dt_max if math.isfinite(dt_max) else 0.0,
                                             nsteps=n, start=int(r.steps_done == 0)))
-                    if key[0] == 2 and key[1] == 1:
-                        outs = fcw.run(entries, graph=self.graph)
-                    else:
-                        outs = [fcw.run([e])[0] for e in entries]
+                    # one kind per call: the library advances the members together
+                    outs = fcw.run(entries, graph=self.graph)
                     for r, o in zip(members, outs):
                         r.dt = r.req.dt = o["dt_used"]
             self.stream.synchronize()

@@ -151,3 +151,92 @@ def test_graph_cache_follows_member_layout():
         assert np.array_equal(a, b)
     for s in big + small:
         s.close()
+
+
+# ---------------------------------------------------------------- 3-D problems of one kind
+
+SRC3 = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0),
+        dict(x=(0.62, 0.33, 0.41), dir=(0.0, 0.6, 0.8), f0=14.0, amp=-0.5)]
+
+
+def _cfg3(n, seed, hi=None):
+    cc, rr = workloads.random_spheres(seed=seed, porosity=0.12, rmin=0.06, rmax=0.12,
+                                      n_probe=20000, keep_clear=tuple(q["x"] for q in SRC3))
+    kw = {} if hi is None else dict(hi=hi)
+    return workloads._base(3, n, 2, cc, rr, ncomp=3, tree_depth=2, **kw)
+
+
+@pytest.fixture(scope="module")
+def problems3d():
+    import torch
+    from paper_2501_19013_amd.solver import Solver
+    stream = torch.cuda.Stream()
+    out = []
+    for n, seed, nsteps, hi in (((6, 6, 6), 31, 57, None), ((8, 7, 5), 32, 40, (0.8, 0.7, 0.5)),
+                                ((5, 5, 5), 33, 73, None)):
+        cfg = _cfg3(n, seed, hi)
+        s = Solver(cfg, precision="fp32", stream=stream)
+        out.append((cfg, s, 0.9 * s.critical_dt(), nsteps))
+    return stream, out
+
+
+def _alone3(s, dt, nsteps):
+    import torch
+    u, d = s.zeros(2), s.zeros(2)
+    s.step(u, d, SRC3, dt, nsteps, start=True)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().copy()
+
+
+def test_3d_batched_equals_alone(problems3d):
+    """Three 3-D elastic problems of different sizes and step counts in shared launches
+    equal each problem run alone, bit for bit (same kernel, same per-node order)."""
+    import torch
+    from paper_2501_19013_amd import fcw
+    stream, probs = problems3d
+    alone = [_alone3(s, dt, n) for _, s, dt, n in probs]
+    states = [(s.zeros(2), s.zeros(2)) for _, s, _, _ in probs]
+    with torch.cuda.stream(stream):
+        fcw.run([dict(ctx=s.ctx, nrhs=2, u=u, d=d, sources=SRC3, dt=dt, nsteps=n, start=1)
+                 for (_, s, dt, n), (u, d) in zip(probs, states)])
+    torch.cuda.synchronize()
+    for (u, _), ref in zip(states, alone):
+        assert np.abs(ref).max() > 0
+        assert np.array_equal(u.cpu().numpy(), ref)
+
+
+def test_3d_batched_matches_oracle(problems3d):
+    import torch
+    from paper_2501_19013_amd import fcw
+    stream, probs = problems3d
+    (cfg, s, dt, n), (_, s2, dt2, n2) = probs[1], probs[0]
+    u, d = s.zeros(2), s.zeros(2)
+    u2, d2 = s2.zeros(2), s2.zeros(2)
+    with torch.cuda.stream(stream):
+        fcw.run([dict(ctx=s.ctx, nrhs=2, u=u, d=d, sources=SRC3, dt=dt, nsteps=n, start=1),
+                 dict(ctx=s2.ctx, nrhs=2, u=u2, d=d2, sources=SRC3, dt=dt2, nsteps=n2, start=1)])
+    torch.cuda.synchronize()
+    disc = problem.build(problem.Problem.from_config(cfg))
+    for r in range(2):
+        ref = timestep.cdm(disc, dt, n, sources=[SRC3[r]])["u"]
+        got = u[r].double().cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+def test_3d_graph_replays_equal_eager(problems3d):
+    import torch
+    from paper_2501_19013_amd import fcw
+    stream, probs = problems3d
+    q = 15
+    eager = [(s.zeros(2), s.zeros(2)) for _, s, _, _ in probs]
+    graph = [(s.zeros(2), s.zeros(2)) for _, s, _, _ in probs]
+    for k in range(3):
+        for st, use_graph in ((eager, False), (graph, True)):
+            with torch.cuda.stream(stream):
+                fcw.run([dict(ctx=s.ctx, nrhs=2, u=u, d=d, sources=SRC3, t0=k * q * dt, dt=dt,
+                              nsteps=q, start=int(k == 0))
+                         for (_, s, dt, _), (u, d) in zip(probs, st)], graph=use_graph)
+            torch.cuda.synchronize()
+            _ = (eager[0][0] * 2.0).sum().item()
+        for (ue, _), (ug, _) in zip(eager, graph):
+            assert np.array_equal(ue.cpu().numpy(), ug.cpu().numpy()), k
