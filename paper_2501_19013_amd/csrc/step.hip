@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "step_common.h"
+#include "zmarch.h"
 
 namespace fcw {
 
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> ain) {
   }
   if (tid == 0) u_s[ZSLOT] = T(0);  // never written by the staging below
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  block_sync();
 
   // ---- the block's tiles: a stretch of the tiles of its XCD (blocks b, b + 8, ... run
   // on one XCD), so neighbouring tiles share halo rows in that XCD's L2 ----
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> ain) {
       }
     }
     if (DIRECT) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    block_sync();
 
     // ---- uncut cells: batched K_ref contraction on the matrix cores ----
     // Every non-cut cell of the region gets its row of y_s here: uncut cells their
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> ain) {
       }
     }
     if (MODE != kModeLanczos) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    block_sync();
 
     // ---- owned nodes: fixed-order gather of element results + update ----
     // The cells around node g along one axis are a = g/P - 1 (when g is a positive
@@ -557,7 +558,7 @@ __global__ __launch_bounds__(64 * NW) void tile_kernel(StepArgs<T> ain) {
           a.u_out[(int64_t)comp * a.nnodes + node] = s * r[comp];
       }
     }
-    __syncthreads();  // the next tile reuses the LDS
+    block_sync();  // the next tile reuses the LDS
   }
 }
 
@@ -710,11 +711,57 @@ struct TileCfg {
   }
 };
 
+// 3-D z-marching kernel (zmarch.h): tile = (TX, TY, cell layers per item); the state
+// of one right-hand side must stay below 2 GiB (32-bit buffer offsets)
+template <typename T, int P, int NCOMP, int TX, int TY, int ZR, int NW>
+struct ZCfg {
+  using Base = TileCfg<T, 3, P, NCOMP, TX, TY, ZR, false, NW>;
+  static constexpr void (*kern)(StepArgs<T>) = zmarch_kernel<T, P, NCOMP, TX, TY, ZR, NW>;
+  static bool fits(const Ctx& c) {
+    return c.ndof * (int64_t)sizeof(T) < 0x7FFFFFF0 && c.ncells[0] * (int64_t)c.ncells[1] *
+                                                               c.ncells[2] * 4 < 0x7FFFFFF0;
+  }
+  static fcw_status run_step(Ctx& c, int mode, int nrhs, const void* uin, void* uout, void* d,
+                             double t, double dt, int start) {
+    if (mode != kModeStep || !fits(c)) {
+      set_error("z-marching kernel: step mode and states below 2 GiB only");
+      return FCW_E_UNSUPPORTED;
+    }
+    if (!c.skip_cut) {
+      fcw_status st = launch_cut_products(c, nrhs, uin);
+      if (st) return st;
+    }
+    StepArgs<T> a = Base::args(c, uin, uout, d, t, dt, start, kModeStep);
+    const int nbx = std::min(a.chunk, resident_per_xcd((const void*)kern, 64 * NW));
+    kern<<<dim3(8 * nbx, nrhs, 1), 64 * NW, 0, c.stream>>>(a);
+    FCW_HIP(hipGetLastError());
+    return FCW_OK;
+  }
+  static int blocks_per_xcd() { return resident_per_xcd((const void*)kern, 64 * NW); }
+  static fcw_status run_batch(hipStream_t s, const void* recs, const int32_t* bstart, int nprob,
+                              int nblocks, int maxrhs, int j) {
+    StepArgs<T> a{};
+    a.probs = (const StepArgs<T>*)recs;
+    a.bstart = bstart;
+    a.nprob = nprob;
+    a.jstep = j;
+    kern<<<dim3(nblocks, maxrhs, 1), 64 * NW, 0, s>>>(a);
+    FCW_HIP(hipGetLastError());
+    return FCW_OK;
+  }
+  static const BatchOps* ops() {
+    static const BatchOps o{&blocks_per_xcd, &Base::ntiles, &Base::fill, &run_batch,
+                            sizeof(StepArgs<T>)};
+    return &o;
+  }
+};
+
 struct Cand {
   RunFn fn;
   int tile[3];
   int nw;  // waves per block
   const BatchOps* ops;
+  bool zm = false;  // the z-marching kernel
 };
 
 // Candidate tile shapes per problem kind; entry 0 is the default and serves every mode.
@@ -734,6 +781,10 @@ static int candidates(const Ctx& c, Cand* out) {
   if (c.dim == D && c.p == PP && c.ncomp == NC)        \
     out[n++] = Cand{&TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::run_step, {TX, TY, TZ}, NW, \
                     TileCfg<T, D, PP, NC, TX, TY, TZ, false, NW>::ops()};
+#define FCW_CZ(PP, NC, TX, TY, ZR, NW)                 \
+  if (c.dim == 3 && c.p == PP && c.ncomp == NC && ZCfg<T, PP, NC, TX, TY, ZR, NW>::fits(c)) \
+    out[n++] = Cand{&ZCfg<T, PP, NC, TX, TY, ZR, NW>::run_step, {TX, TY, ZR}, NW,           \
+                    ZCfg<T, PP, NC, TX, TY, ZR, NW>::ops(), true};
   if constexpr (F64) {
     FCW_C0(2, 1, 1, 32, 16, 1) FCW_C(2, 1, 1, 16, 16, 1)
     FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1)
@@ -762,14 +813,17 @@ static int candidates(const Ctx& c, Cand* out) {
     FCW_C0(3, 1, 3, 8, 4, 4)
     FCW_C0(3, 2, 3, 4, 4, 4) FCW_C(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
     FCW_CW(3, 2, 3, 4, 4, 4, 8) FCW_CW(3, 2, 3, 8, 4, 4, 8)
+    FCW_CZ(2, 3, 8, 8, 16, 6) FCW_CZ(2, 3, 8, 8, 32, 6)
+    FCW_CZ(2, 3, 8, 4, 16, 6) FCW_CZ(2, 3, 8, 4, 32, 6)
   }
 #undef FCW_C0
 #undef FCW_C
 #undef FCW_CW
+#undef FCW_CZ
   return n;
 }
 
-constexpr int kMaxCand = 10;
+constexpr int kMaxCand = 16;
 
 // BF16 form: FP32 state, bf16 operands of the uncut contraction
 static int candidates_bf(const Ctx& c, Cand* out) {
@@ -835,6 +889,7 @@ struct StepCand {
   RunFn fgen = nullptr;
   int tile[3] = {0, 0, 0};
   int nw = 4;
+  bool zm = false;
 };
 
 static int step_candidates(const Ctx& c, int i, StepCand* out) {
@@ -851,6 +906,7 @@ static int step_candidates(const Ctx& c, int i, StepCand* out) {
       out->fgen = cs[i - n2].fn;
       for (int k = 0; k < 3; ++k) out->tile[k] = cs[i - n2].tile[k];
       out->nw = cs[i - n2].nw;
+      out->zm = cs[i - n2].zm;
     }
   }
   return n2 + ng;
@@ -864,6 +920,12 @@ int tile_candidates(const Ctx& c, int i, int tile[3], std::string* name) {
     for (int k = 0; k < 3; ++k) tile[k] = sc.tile[k];
   if (name && sc.f2d) {
     step2d_candidates(c.p, c.precision == FCW_FP64, i, nullptr, nullptr, name);
+  } else if (name && sc.zm) {
+    char b[128];
+    std::snprintf(b, sizeof b, "fcw::zmarch_kernel<%s, %d, %d, %d, %d, %d, %d>",
+                  c.precision == FCW_FP64 ? "double" : "float", c.p, c.ncomp, sc.tile[0],
+                  sc.tile[1], sc.tile[2], sc.nw);
+    *name = b;
   } else if (name) {
     // the kernel's name as a profiler prints it (single-problem launches)
     char b[128];

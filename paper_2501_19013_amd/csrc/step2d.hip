@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void step2d_kernel(
     src_on = hit ? 1 : 0;
     ft_s = hit ? ricker(t, sf0) : 0.0;
   }
-  __syncthreads();
+  block_sync();
 
   // ---- element products of every region cell into y_s (stride NLP) ----
   {
@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void step2d_kernel(
     }
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  block_sync();
 
   // ---- update, one owned row per wave instruction ----
   const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
@@ -514,7 +514,11 @@ __global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
     }
   };
 
-  // ---- prologue: infos, flags, 1-D inverse weights, source, the ring cell row ----
+  // ---- prologue: the ring cell row's node rows (and, PD = 2, the first owned cell
+  // row's) go first, so their loads overlap those of the infos, flags, 1-D inverse
+  // weights and K_ref ----
+  stage_rows((cy0 - 1) * P, P + 1);
+  if constexpr (PD == 2) stage_rows(cy0 * P + 1, P);
   for (int i = tid; i < NIR * NCR; i += 64 * NW) {
     const int cy = cy0 - 1 + i / NCR, cx = cx0 - 1 + i % NCR;
     const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1;
@@ -551,9 +555,8 @@ __global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
       const T v = pr.kref[min(r, NL - 1) * NL + min(cc, NL - 1)];
       areg[mb][kk] = (r < NL && cc < NL) ? v : T(0);
     }
-  stage_rows((cy0 - 1) * P, P + 1);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
+  block_sync();
   stage_cut(cy0 - 1, y_b[0]);
 
   // per-lane constants of the MFMA B operand: local node (ix, iy) of this lane's k rows
@@ -599,8 +602,8 @@ __global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
   };
 
   if constexpr (PD == 2) {
-    // the first owned cell row goes ahead as well (waited for with the ring row's loads)
-    stage_rows(cy0 * P + 1, P);
+    // the first owned cell row's operands go ahead as well (its node rows came with the
+    // ring row's)
     load_upd(cy0, d_nn, m_nn, st_nn);
   }
   const T dt2h = (pr.start && j == 0) ? T(0.5) * pr.dt2 : pr.dt2;
@@ -653,7 +656,7 @@ __global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
         }
       }
     }
-    __syncthreads();
+    block_sync();
 
     // ---- C: update of node rows cy P .. cy P + P - 1 ----
     if (!ring) {
@@ -708,7 +711,7 @@ __global__ __launch_bounds__(64 * NW, 24 / NW) void stream2d_kernel(
     } else {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
-    __syncthreads();
+    block_sync();
     const int t3 = bp;
     bp = bc;
     bc = bn;

@@ -69,6 +69,20 @@ struct StepArgs {
   int nsteps, nrhs;
 };
 
+// Workgroup barrier of the step kernels: this wave's LDS operations are complete
+// (lgkmcnt(0)) and every wave has arrived.  Unlike __syncthreads() it does not also wait
+// for outstanding vector-memory operations (its release fence does): the step kernels
+// keep loads for later rows or layers, and their stores, in flight across barriers and
+// order them with explicit vmcnt waits.  No step kernel reads global data written by
+// another wave of the same launch.
+__device__ static inline void block_sync() {
+  asm volatile("" ::: "memory");
+  // lgkmcnt(0); vmcnt (63) and expcnt (7) not waited for
+  __builtin_amdgcn_s_waitcnt((15 & 15) | (7 << 4) | (0 << 8) | (3 << 14));
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 __device__ static inline double ricker(double t, double f0) {
   const double pi = 3.14159265358979323846;
   const double ts = 2.0 * sqrt(6.0) / (pi * f0);
