@@ -316,13 +316,13 @@ fcw_status fcw_query(const fcw_ctx* ctx, fcw_info* info);
  * query the count; capacity is in elements. */
 enum {
   FCW_ARR_CELL_CLASS = 0, /* int8 [ncells]: 0 OUT, 1 UNCUT, 2 CUT (after reclassification) */
-  FCW_ARR_CUT_CELLS = 1,  /* int32 [n_cut] cell index of each kept cut cell */
+  FCW_ARR_CUT_CELLS = 1,  /* int32 [n_cut_candidates] cell of each cut candidate (dropped ones are OUT in FCW_ARR_CELL_CLASS) */
   FCW_ARR_K_REF = 2,      /* double [n_loc*n_loc] uncut stiffness, row-major */
-  FCW_ARR_K_CUT = 3,      /* double [n_cut*n_loc*n_loc] cut-cell stiffness */
-  FCW_ARR_M_CUT = 4,      /* double [n_cut*n_s*n_s] cut-cell scalar consistent mass */
-  FCW_ARR_LUMPED_CUT = 5, /* double [n_cut*n_s] stabilised lumped diagonal */
+  FCW_ARR_K_CUT = 3,      /* double [n_cut_candidates*n_loc*n_loc] cut-cell stiffness */
+  FCW_ARR_M_CUT = 4,      /* double [n_cut_candidates*n_s*n_s] cut-cell scalar consistent mass */
+  FCW_ARR_LUMPED_CUT = 5, /* double [n_cut_candidates*n_s] stabilised lumped diagonal */
   FCW_ARR_MASS = 6,       /* double [nnodes] assembled lumped mass */
-  FCW_ARR_EVS_MARGIN = 7, /* double [n_cut] */
+  FCW_ARR_EVS_MARGIN = 7, /* double [n_cut_candidates] */
   FCW_ARR_IMEX_DOFS = 8   /* int64 [n_c] implicit DOFs of the prepared IMEX scheme */
 };
 fcw_status fcw_export(const fcw_ctx* ctx, int32_t which, void* dst, int64_t capacity,
@@ -341,6 +341,68 @@ fcw_status fcw_trace_error(const double* sim, int64_t sim_stride, const double* 
 
 /* Release every device allocation of the context. */
 void fcw_destroy(fcw_ctx* ctx);
+
+/* ---- IGA-FCM: B-spline discretisation of the same immersed problem ----------------------
+ * (Sec. 2.2: B-spline shape functions, the isogeometric variant of the finite cell method;
+ * Sec. 2.4: row-sum lumping; Table methods: IGA-FCM, alpha stabilisation, epsilon = 0,
+ * central differences).  Degree p, maximum continuity, open uniform knot vectors: n cells
+ * of a direction carry n + p functions, cell c supports functions c .. c + p, DOF
+ * i0 + nb0 (i1 + nb1 i2) with nb_k = n_k + p.  The mass is row-sum lumped,
+ * m_i = int alpha rho N_i (positive on every DOF supported by a kept cell; the others are
+ * inactive, with zero mass, and stay zero).  Scalar wave equation only; 2-D p = 2..4,
+ * 3-D p = 2..3; FP64 or FP32 steps (the precision of the cells' context); at least
+ * 2p + 1 cells per direction. */
+typedef struct fcw_iga fcw_iga;
+typedef struct {
+  int64_t ndof;           /* prod nbasis */
+  int32_t nbasis[3];      /* n_k + p (1 beyond dim) */
+  int32_t n_s, precision; /* (p+1)^dim functions per cell; FCW_FP64 or FCW_FP32 */
+  int64_t n_cut, n_uncut, n_out;
+  double dt_crit;         /* 0 until fcw_iga_critical_dt has run */
+  int64_t footprint_bytes;
+} fcw_iga_info;
+
+/* Build the B-spline problem from a context whose cells are assembled
+ * (fcw_assemble_cells; no stabilisation needed): its classification and the tree
+ * quadrature of its cut cells are reused, each element matrix transformed to the B-spline
+ * basis of the same polynomial space.  The IGA object holds its own copies afterwards
+ * (the cells' context may be destroyed).  Synchronises.  FCW_E_UNSUPPORTED for vector
+ * problems, other degrees or BF16; FCW_E_ARG for fewer than 2p + 1 cells. */
+fcw_status fcw_iga_create(fcw_ctx* cells, fcw_iga** out);
+
+/* dt_crit = 2 / sqrt(lambda_max(M^{-1} K)) with the lumped mass (Sec. 2.3), by the FP64
+ * Lanczos iteration of fcw_critical_dt (same rtol, max_iter and FCW_E_NOCONV rule). */
+fcw_status fcw_iga_critical_dt(fcw_iga* iga, int32_t max_iter, double rtol, double* dt_crit);
+
+/* nsteps steps of eq. cdm in increment form with the lumped mass, as fcw_step_explicit:
+ * u, d device [nrhs][ndof] in the step precision (d = u_k - u_{k-1}; on a start call
+ * d = dt v_0 and the first step is the Newmark beta = 0 start-up); src host [nrhs] point
+ * sources (x, f0, amp; dir and sigma unused, sigma > 0 gives FCW_E_UNSUPPORTED), the load
+ * of right-hand side r being f_t(t) rho amp N_i(x_s) with the Ricker f_t of eq.
+ * source_time at t = t0 + k dt.  Asynchronous on the cells' stream; nrhs <= 64.
+ * FCW_E_ARG for a source outside the box. */
+fcw_status fcw_iga_step(fcw_iga* iga, int32_t nrhs, void* u, void* d, const fcw_source* src,
+                        double t0, double dt, int32_t nsteps, int32_t start);
+
+/* r = K u (the step kernel's stiffness action), device [nrhs][ndof], step precision. */
+fcw_status fcw_iga_apply_stiffness(fcw_iga* iga, int32_t nrhs, const void* u, void* r);
+
+fcw_status fcw_iga_query(const fcw_iga* iga, fcw_iga_info* info);
+
+/* Copy an FP64 array to host memory (synchronous); as fcw_export. */
+enum {
+  FCW_IGA_ARR_MASS = 0,    /* double [ndof] row-sum lumped mass */
+  FCW_IGA_ARR_K_CLASS = 1, /* double [(2p+1)^dim][n_s*n_s] stiffness of an uncut cell of
+                              each position class q_0 + (2p+1)(q_1 + (2p+1) q_2), where
+                              along a direction cell c of n has class c (c < p), p (inside)
+                              or 2p - (n - 1 - c) (c > n - 1 - p); row-major */
+  FCW_IGA_ARR_K_CUT = 2    /* double [n_cut_candidates][n_s*n_s] stiffness of each cut cell
+                              in the order of FCW_ARR_CUT_CELLS (zero for dropped ones) */
+};
+fcw_status fcw_iga_export(const fcw_iga* iga, int32_t which, void* dst, int64_t capacity,
+                          int64_t* count);
+
+void fcw_iga_destroy(fcw_iga* iga);
 
 /* Thread-local message of the last failing call ("" if none). */
 const char* fcw_last_error(void);

@@ -257,6 +257,19 @@ bool groupable_3d(const Ctx& a, const Ctx& b);
 fcw_status launch_apply_scaled64(Ctx& c, const double* v, double* w);
 // lanczos.hip
 fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax);
+// the iteration on any FP64 operator w = apply(arg, v) of length n (already scaled by
+// M^{-1/2} on both sides); the start vector is nonzero where mask[i % nmask] > 0, n =
+// nmask * ncomp
+struct LanczosOp {
+  hipStream_t stream;
+  int64_t n;
+  const double* mask;
+  int64_t nmask;
+  int ncomp;
+  fcw_status (*apply)(void* arg, const double* v, double* w);
+  void* arg;
+};
+fcw_status lanczos_run(const LanczosOp& op, int max_iter, double rtol, double* lmax);
 
 // small helpers usable on host and device
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }

@@ -2,7 +2,7 @@
 //   dt_crit = 2 / sqrt(lambda_max(K, M)),
 // with lambda_max the largest eigenvalue of the symmetric operator M^{-1/2} K M^{-1/2}
 // on the active DOFs.  FP64 Lanczos iteration on the device (the operator is the tile
-// stiffness kernel in FP64); the largest eigenvalue theta of the tridiagonal Lanczos
+// stiffness kernel in FP64, or the B-spline step kernel's stiffness action); the largest eigenvalue theta of the tridiagonal Lanczos
 // matrix is found by Sturm-sequence bisection in a one-thread kernel, with the residual
 // norm of its Ritz pair.  The iteration stops when that residual is below rtol theta and
 // reports theta + residual (Ritz values approach lambda_max from below, so theta alone
@@ -205,25 +205,26 @@ __global__ void tridiag_max_kernel(const double* alpha, const double* beta, int 
   tridiag_top(alpha, beta, k, work, out);
 }
 
-fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
-  const int64_t n = c.ndof;
+fcw_status lanczos_run(const LanczosOp& op, int max_iter, double rtol, double* lmax) {
+  const int64_t n = op.n;
+  const hipStream_t stream = op.stream;
   double *v0 = nullptr, *v1 = nullptr, *w = nullptr, *ab = nullptr, *part = nullptr;
   const size_t vb = (size_t)n * sizeof(double);
-  FCW_HIP(hipMallocAsync((void**)&v0, vb, c.stream));
-  FCW_HIP(hipMallocAsync((void**)&v1, vb, c.stream));
-  FCW_HIP(hipMallocAsync((void**)&w, vb, c.stream));
+  FCW_HIP(hipMallocAsync((void**)&v0, vb, stream));
+  FCW_HIP(hipMallocAsync((void**)&v1, vb, stream));
+  FCW_HIP(hipMallocAsync((void**)&w, vb, stream));
   // alpha, beta, two result words, the tridiagonal solver's work (6 max_iter)
-  FCW_HIP(hipMallocAsync((void**)&ab, (8 * (size_t)max_iter + 2) * sizeof(double), c.stream));
-  FCW_HIP(hipMallocAsync((void**)&part, 2 * kRedBlocks * sizeof(double), c.stream));
+  FCW_HIP(hipMallocAsync((void**)&ab, (8 * (size_t)max_iter + 2) * sizeof(double), stream));
+  FCW_HIP(hipMallocAsync((void**)&part, 2 * kRedBlocks * sizeof(double), stream));
   double* alpha = ab;
   double* beta = ab + max_iter;
   double* res = ab + 2 * max_iter;
   double* twork = ab + 2 * max_iter + 2;
   double* part2 = part + kRedBlocks;
 
-  start_vector_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(w, c.d_invm64, c.nnodes,
-                                                                  c.ncomp, part);
-  scale_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(v1, w, n, part, nullptr);
+  start_vector_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(w, op.mask, op.nmask, op.ncomp,
+                                                                  part);
+  scale_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(v1, w, n, part, nullptr);
   FCW_HIP(hipGetLastError());
   double* vcur = v1;
   double* vprev = v0;
@@ -232,24 +233,24 @@ fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
   const int check = 20;
   fcw_status st = FCW_OK;
   for (int j = 0; j < max_iter; ++j) {
-    st = launch_apply_scaled64(c, vcur, w);
+    st = op.apply(op.arg, vcur, w);
     if (st != FCW_OK) break;
-    dot_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(w, vcur, n, part);
-    axpy_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(
+    dot_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(w, vcur, n, part);
+    axpy_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(
         w, vcur, j > 0 ? vprev : nullptr, n, part, alpha + j, j > 0 ? beta + j - 1 : nullptr,
         part2);
-    scale_kernel<<<kRedBlocks, kRedThreads, 0, c.stream>>>(vprev, w, n, part2, beta + j);
+    scale_kernel<<<kRedBlocks, kRedThreads, 0, stream>>>(vprev, w, n, part2, beta + j);
     FCW_HIP(hipGetLastError());
     double* t = vprev;
     vprev = vcur;
     vcur = t;
     const int k = j + 1;
     if (k % check == 0 || k == max_iter) {
-      tridiag_max_kernel<<<1, 64, 0, c.stream>>>(alpha, beta, k, twork, res);
+      tridiag_max_kernel<<<1, 64, 0, stream>>>(alpha, beta, k, twork, res);
       double hb[3];
-      FCW_HIP(hipMemcpyAsync(&hb[0], res, 2 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
-      FCW_HIP(hipMemcpyAsync(&hb[2], beta + j, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-      FCW_HIP(hipStreamSynchronize(c.stream));
+      FCW_HIP(hipMemcpyAsync(&hb[0], res, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+      FCW_HIP(hipMemcpyAsync(&hb[2], beta + j, sizeof(double), hipMemcpyDeviceToHost, stream));
+      FCW_HIP(hipStreamSynchronize(stream));
       theta = hb[0];
       // residual norm of the Ritz pair: beta_k |s_k|
       resid = fabs(hb[2]) * hb[1];
@@ -264,12 +265,12 @@ fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
       }
     }
   }
-  FCW_HIP(hipFreeAsync(v0, c.stream));
-  FCW_HIP(hipFreeAsync(v1, c.stream));
-  FCW_HIP(hipFreeAsync(w, c.stream));
-  FCW_HIP(hipFreeAsync(ab, c.stream));
-  FCW_HIP(hipFreeAsync(part, c.stream));
-  FCW_HIP(hipStreamSynchronize(c.stream));
+  FCW_HIP(hipFreeAsync(v0, stream));
+  FCW_HIP(hipFreeAsync(v1, stream));
+  FCW_HIP(hipFreeAsync(w, stream));
+  FCW_HIP(hipFreeAsync(ab, stream));
+  FCW_HIP(hipFreeAsync(part, stream));
+  FCW_HIP(hipStreamSynchronize(stream));
   if (st != FCW_OK) return st;
   if (!(theta > 0.0) || !std::isfinite(theta)) {
     set_error("Lanczos iteration gave no positive eigenvalue (%g)", theta);
@@ -284,6 +285,15 @@ fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
   // eigenvalue it approximates, so the step derived from it errs on the safe side
   *lmax = theta + resid;
   return FCW_OK;
+}
+
+static fcw_status apply_scaled_ctx(void* arg, const double* v, double* w) {
+  return launch_apply_scaled64(*(Ctx*)arg, v, w);
+}
+
+fcw_status lanczos_lambda_max(Ctx& c, int max_iter, double rtol, double* lmax) {
+  LanczosOp op{c.stream, c.ndof, c.d_invm64, c.nnodes, c.ncomp, apply_scaled_ctx, &c};
+  return lanczos_run(op, max_iter, rtol, lmax);
 }
 
 }  // namespace fcw

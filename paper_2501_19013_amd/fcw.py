@@ -28,7 +28,9 @@ EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
            "fcw_apply_stiffness",
            "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
-           "fcw_export", "fcw_destroy", "fcw_last_error", "fcw_trace_error")
+           "fcw_export", "fcw_destroy", "fcw_last_error", "fcw_trace_error",
+           "fcw_iga_create", "fcw_iga_critical_dt", "fcw_iga_step", "fcw_iga_apply_stiffness",
+           "fcw_iga_query", "fcw_iga_export", "fcw_iga_destroy")
 
 
 class ProblemDesc(C.Structure):
@@ -80,6 +82,20 @@ class Info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class IgaInfo(C.Structure):
+    _fields_ = [("ndof", C.c_int64), ("nbasis", C.c_int32 * 3), ("n_s", C.c_int32),
+                ("precision", C.c_int32), ("n_cut", C.c_int64), ("n_uncut", C.c_int64),
+                ("n_out", C.c_int64), ("dt_crit", C.c_double), ("footprint_bytes", C.c_int64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["nbasis"] = tuple(self.nbasis)
+        return d
+
+
+FCW_IGA_ARR_MASS, FCW_IGA_ARR_K_CLASS, FCW_IGA_ARR_K_CUT = 0, 1, 2
+
+
 class FcwError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fcw status {status}: {msg}")
@@ -123,8 +139,16 @@ def load(path=LIB_PATH):
     lib.fcw_destroy.restype = None
     lib.fcw_last_error.argtypes = []
     lib.fcw_last_error.restype = C.c_char_p
+    lib.fcw_iga_create.argtypes = [vp, C.POINTER(vp)]
+    lib.fcw_iga_critical_dt.argtypes = [vp, i32, f64, C.POINTER(f64)]
+    lib.fcw_iga_step.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
+    lib.fcw_iga_apply_stiffness.argtypes = [vp, i32, vp, vp]
+    lib.fcw_iga_query.argtypes = [vp, C.POINTER(IgaInfo)]
+    lib.fcw_iga_export.argtypes = [vp, i32, vp, C.c_int64, C.POINTER(C.c_int64)]
+    lib.fcw_iga_destroy.argtypes = [vp]
+    lib.fcw_iga_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("fcw_destroy", "fcw_last_error"):
+        if name not in ("fcw_destroy", "fcw_last_error", "fcw_iga_destroy"):
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -372,6 +396,49 @@ def trace_error(sim, ref, sim_stride, ref_stride, n_samples):
 def destroy(ctx):
     if ctx:
         load().fcw_destroy(ctx)
+
+
+def iga_create(ctx):
+    """fcw_iga_create: the B-spline (IGA-FCM) problem on the assembled cells of ``ctx``."""
+    g = C.c_void_p()
+    _check(load().fcw_iga_create(ctx, C.byref(g)))
+    return g
+
+
+def iga_critical_dt(g, max_iter=4000, rtol=1e-9):
+    out = C.c_double()
+    _check(load().fcw_iga_critical_dt(g, int(max_iter), float(rtol), C.byref(out)))
+    return out.value
+
+
+def iga_step(g, nrhs, u, d, sources, t0, dt, nsteps, start):
+    srcs = _sources(sources)
+    _check(load().fcw_iga_step(g, int(nrhs), _ptr(u), _ptr(d), srcs, float(t0), float(dt),
+                               int(nsteps), int(start)))
+
+
+def iga_apply_stiffness(g, nrhs, u, r):
+    _check(load().fcw_iga_apply_stiffness(g, int(nrhs), _ptr(u), _ptr(r)))
+
+
+def iga_query(g):
+    info = IgaInfo()
+    _check(load().fcw_iga_query(g, C.byref(info)))
+    return info.as_dict()
+
+
+def iga_export(g, which):
+    lib = load()
+    n = C.c_int64()
+    _check(lib.fcw_iga_export(g, int(which), None, 0, C.byref(n)))
+    out = np.empty(n.value, dtype=np.float64)
+    _check(lib.fcw_iga_export(g, int(which), out.ctypes.data, n.value, C.byref(n)))
+    return out
+
+
+def iga_destroy(g):
+    if g:
+        load().fcw_iga_destroy(g)
 
 
 def last_error():
