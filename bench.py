@@ -32,8 +32,9 @@ the FP32 and FP64 device states after the same steps from rest at that dt are co
 the oracle's (`rel_l2_vs_oracle`).
 
 Further legs in the same JSON line: `c3` (3-D elastic 96^3 p=2: FP32, split BF16, FP64),
-`imex` (the semi-explicit scheme of Alg. imex, FP64, on the same void field at 64^2 p=3)
-and `serving` (p50/p99 latency of a seeded request stream).
+`imex` (the semi-explicit scheme of Alg. imex, FP64, on the same void field at 64^2 p=3),
+`iga` (IGA-FCM with B-splines and row-sum lumping on the 512^2 void field, p=4, FP32) and
+`serving` (p50/p99 latency of a seeded request stream).
 """
 from __future__ import annotations
 
@@ -343,6 +344,68 @@ def bench_imex(steps, warmup):
                 solve_bytes_per_step=8 * nc * nc)
 
 
+def bench_iga(steps, warmup):
+    """IGA-FCM (B-splines, row-sum lumped mass, central differences) on the c2 void field:
+    512 x 512 cells, p = 4, 516^2 DOFs, FP32 steps with an FP64 run of the same steps for
+    the relative L2 difference.  One launch per step (iga_step_kernel).  Algorithmic bytes
+    per step: 5 s N_dof (read u_k, d_k, 1/m; write u_{k+1}, d_{k+1}) + N_cut n_s^2 s (the
+    cut cells' matrices) + 4 N_cells (cell infos); flops: 2 n_s^2 per kept cell, on the
+    FP32 vector units (157.3 TFLOP/s)."""
+    import torch
+    import workloads
+    from paper_2501_19013_amd import fcw
+    cfg = workloads.config("c2")
+    src = cfg["sources"]
+    out = dict(workload="c2 void field, IGA-FCM: maximum-continuity B-splines p=4 on 512x512 "
+                        "cells (516^2 DOFs), row-sum lumped mass, alpha=1e-12, Ricker f0=10 at "
+                        "(0.1,0.1), dt=0.9 dt_crit of the lumped system")
+    states = {}
+    for prec in ("fp32", "fp64"):
+        ctx = fcw.assemble_cells(cfg, precision=prec)
+        g = fcw.iga_create(ctx)
+        info = fcw.iga_query(g)
+        if prec == "fp32":
+            dt = 0.9 * fcw.iga_critical_dt(g, max_iter=4000, rtol=1e-7)
+        dtype = torch.float32 if prec == "fp32" else torch.float64
+        u = torch.zeros((1, info["ndof"]), dtype=dtype, device="cuda:0")
+        d = torch.zeros_like(u)
+        fcw.iga_step(g, 1, u, d, src, 0.0, dt, warmup, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fcw.iga_step(g, 1, u, d, src, warmup * dt, dt, steps, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        mass = fcw.iga_export(g, fcw.FCW_IGA_ARR_MASS)
+        active = int((mass > 0).sum())
+        states[prec] = u[0].double().cpu().numpy()
+        ncut = info["n_cut"]
+        fcw.iga_destroy(g)
+        fcw.destroy(ctx)
+        if prec == "fp32":
+            ns = info["n_s"]
+            ncells = 512 * 512
+            byts = 5 * 4 * info["ndof"] + ncut * ns * ns * 4 + 4 * ncells
+            flops = 2 * ns * ns * (info["n_cut"] + info["n_uncut"])
+            t = ms * 1e-3 / steps
+            hbm = dict(bound="hbm", achieved=byts / t / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                       frac=byts / t / 1e9 / HBM_PEAK_GBS, algorithmic_bytes_per_launch=byts)
+            alu = dict(bound="alu", achieved=flops / t / 1e12, peak=157.3, unit="TFLOP/s",
+                       frac=flops / t / 1e12 / 157.3, algorithmic_flops_per_launch=flops)
+            main, other = (hbm, alu) if byts / (HBM_PEAK_GBS * 1e9) >= flops / 157.3e12 else (alu, hbm)
+            main = dict(main, kernel="fcw::iga_step_kernel<float, 2, 4>", other=other,
+                        note="ms_per_step includes the launch of each step (one kernel per step)")
+            out.update(value=active * steps / (ms * 1e-3), unit="DOF-updates/s",
+                       ms_per_step=ms / steps, steps=steps, ndof=info["ndof"], active_dof=active,
+                       n_cut=ncut, dt=dt, dt_crit=info["dt_crit"] or dt / 0.9, roofline=main)
+        else:
+            out["fp64_ms_per_step"] = ms / steps
+    out["rel_l2_fp32_vs_fp64"] = float(np.linalg.norm(states["fp32"] - states["fp64"])
+                                       / np.linalg.norm(states["fp64"]))
+    return out
+
+
 def bench_serve(count, scale, rate, quantum):
     """Serving loop over the first `count` requests of the request stream (seed 5),
     cell counts per side scaled by `scale`; Poisson arrivals at `rate` requests/s
@@ -389,6 +452,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
     ap.add_argument("--imex-steps", type=int, default=200,
                     help="steps of the IMEX leg (0 skips it)")
+    ap.add_argument("--iga-steps", type=int, default=500, help="steps of the IGA-FCM leg (0: skip)")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--c3-warmup", type=int, default=10)
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving leg (0: skip)")
@@ -452,6 +516,10 @@ def main():
         res["imex"] = bench_imex(args.imex_steps, 5)
         print(f"[bench] imex: {res['imex']['ms_per_step']:.3f} ms/step, "
               f"{res['imex']['n_implicit']} implicit DOFs", file=sys.stderr, flush=True)
+    if args.iga_steps > 0:
+        res["iga"] = bench_iga(args.iga_steps, 10)
+        print(f"[bench] iga: {res['iga']['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,
+              flush=True)
     if args.serve_count > 0:
         res["serving"] = bench_serve(args.serve_count, args.serve_scale,
                                      None if args.serve_rate <= 0 else args.serve_rate,

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -60,7 +61,7 @@ struct IgaCtx {
   double* d_rcut = nullptr;       // [ncand][n_s] cut-cell row sums of the mass
   double* d_mass = nullptr;       // [ndof] row-sum lumped mass
   double* d_sqim = nullptr;       // [ndof] sqrt(1/mass) on active DOFs, 0 elsewhere
-  void* d_kcls = nullptr;         // step precision copies
+  void* d_kcls = nullptr;         // FP32 copies of the matrices (FP32 contexts only)
   void* d_kcut = nullptr;
   void* d_invm = nullptr;
   IgaSrc* d_src = nullptr;        // [kMaxSrc]
@@ -503,10 +504,18 @@ static fcw_status iga_launch_t(IgaCtx& c, int nrhs, const void* uin, void* uout,
   for (int k = 0; k < 3; ++k) { a.n[k] = c.n[k]; a.nb[k] = c.nb[k]; }
   a.ndof = c.ndof;
   a.info = c.d_info;
-  a.kcls = (const T*)c.d_kcls;
-  a.kint = (const T*)c.d_kcls + (size_t)S::QINT * S::NS * S::NS;
-  a.kcut = (const T*)c.d_kcut;
+  // the FP64 kernel (FP64 steps, and the Lanczos operator of every context) reads the FP64
+  // matrices; the step-precision copies serve FP32 steps; the inverse mass is read by steps
+  // only, which run in the context's precision
+  const bool f64 = std::is_same<T, double>::value;
+  a.kcls = f64 ? (const T*)c.d_kcls64 : (const T*)c.d_kcls;
+  a.kint = a.kcls + (size_t)S::QINT * S::NS * S::NS;
+  a.kcut = f64 ? (const T*)c.d_kcut64 : (const T*)c.d_kcut;
   a.invm = (const T*)c.d_invm;
+  if (!apply && (int)c.esize() != (int)sizeof(T)) {
+    set_error("IGA step kernel precision differs from the context's");
+    return FCW_E_STATE;
+  }
   a.uin = (const T*)uin;
   a.uout = (T*)uout;
   a.d = (T*)d;
@@ -659,7 +668,8 @@ fcw_status fcw_iga_create(fcw_ctx* cells, fcw_iga** out) {
       (st = iga_malloc(c, &c.d_kcut64, nc * ns2 * 8)) || (st = iga_malloc(c, &c.d_rcut, nc * ns * 8)) ||
       (st = iga_malloc(c, &c.d_mass, (size_t)c.ndof * 8)) ||
       (st = iga_malloc(c, &c.d_sqim, (size_t)c.ndof * 8)) ||
-      (st = iga_malloc(c, &c.d_kcls, nq * ns2 * es)) || (st = iga_malloc(c, &c.d_kcut, nc * ns2 * es)) ||
+      (c.precision != FCW_FP64 && ((st = iga_malloc(c, &c.d_kcls, nq * ns2 * es)) ||
+                                    (st = iga_malloc(c, &c.d_kcut, nc * ns2 * es)))) ||
       (st = iga_malloc(c, &c.d_invm, (size_t)c.ndof * es)) ||
       (st = iga_malloc(c, &c.d_src, (size_t)kMaxSrc * sizeof(IgaSrc))))
     return fail(st);
@@ -723,8 +733,6 @@ fcw_status fcw_iga_create(fcw_ctx* cells, fcw_iga** out) {
   const int64_t nkc = nq * (int64_t)ns2, nkk = (int64_t)nc * ns2;
   if (c.precision == FCW_FP64) {
     iga_invm_kernel<double><<<gd, 256, 0, c.stream>>>(c.d_mass, (double*)c.d_invm, c.ndof);
-    iga_cast_kernel<double><<<(unsigned)((nkc + 255) / 256), 256, 0, c.stream>>>(c.d_kcls64, (double*)c.d_kcls, nkc);
-    iga_cast_kernel<double><<<(unsigned)((nkk + 255) / 256), 256, 0, c.stream>>>(c.d_kcut64, (double*)c.d_kcut, nkk);
   } else {
     iga_invm_kernel<float><<<gd, 256, 0, c.stream>>>(c.d_mass, (float*)c.d_invm, c.ndof);
     iga_cast_kernel<float><<<(unsigned)((nkc + 255) / 256), 256, 0, c.stream>>>(c.d_kcls64, (float*)c.d_kcls, nkc);

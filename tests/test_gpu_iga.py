@@ -136,6 +136,21 @@ def test_iga_critical_dt(name):
         fcw.destroy(ctx)
 
 
+def test_iga_critical_dt_of_an_fp32_context():
+    """The Lanczos operator runs in FP64 on the FP64 matrices whatever the step precision,
+    so an FP32 context gives the FP64 context's step bit for bit."""
+    from paper_2501_19013_amd import fcw
+    out = []
+    for prec in ("fp32", "fp64"):
+        ctx, g = _device("3d_p2", prec)
+        try:
+            out.append(fcw.iga_critical_dt(g, max_iter=3000, rtol=1e-9))
+        finally:
+            fcw.iga_destroy(g)
+            fcw.destroy(ctx)
+    assert out[0] == out[1]
+
+
 def _run_device(name, precision, dt, nsteps, nrhs=2, chunks=(None,)):
     import torch
     from paper_2501_19013_amd import fcw
