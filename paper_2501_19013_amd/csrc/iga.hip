@@ -393,7 +393,13 @@ struct IgaShape {
   static constexpr int NCR = CX * CY * CZ, NUR = UX * UY * UZ, NOWN = TX * TY * TZ;
   static constexpr int NCLS = 2 * P + 1;
   static constexpr int QINT = DIM == 2 ? P + NCLS * P : P + NCLS * (P + NCLS * P);
-  static constexpr size_t lds_bytes() { return ((size_t)NUR + (size_t)NCR * NS) * sizeof(T); }
+  // matrix-core form of the interior class: 16-cell batches, K in NMB x NKS A fragments
+  static constexpr int NMB = (NS + 15) / 16, NKS = (NS + 3) / 4;
+  static constexpr bool MF = NMB * NKS <= 32;
+  static constexpr int NSP = NS | 1;  // product stride per cell (odd: conflict-free)
+  static constexpr size_t lds_bytes() {
+    return ((size_t)NUR + (size_t)NCR * NSP) * sizeof(T) + (size_t)(2 * NCR + 1) * 4;
+  }
 };
 
 template <typename T, int DIM, int P>
@@ -402,65 +408,164 @@ __global__ __launch_bounds__(256) void iga_step_kernel(IgaStepArgs<T> a) {
   constexpr int P1 = S::P1, NS = S::NS;
   extern __shared__ __attribute__((aligned(16))) unsigned char iga_lds[];
   T* us = reinterpret_cast<T*>(iga_lds);  // [UZ][UY][UX]
-  T* ys = us + S::NUR;                    // [NCR][NS]
+  T* ys = us + S::NUR;                    // [NCR][NSP]
+  int* cin = reinterpret_cast<int*>(ys + (size_t)S::NCR * S::NSP);  // [NCR] cell codes
+  int* glist = cin + S::NCR;  // [NCR] cells with their own matrix (cut, boundary class)
+  int* gcnt = glist + S::NCR;
+  constexpr int NSP = S::NSP;
+  static_assert(NS <= 64, "one row per lane in the per-cell matrix products");
   const int tid = threadIdx.x;
   const int rhs = DIM == 3 ? (int)blockIdx.z / ((a.nb[2] + S::TZ - 1) / S::TZ) : (int)blockIdx.z;
   const int bz = DIM == 3 ? (int)blockIdx.z % ((a.nb[2] + S::TZ - 1) / S::TZ) : 0;
   const int X0 = blockIdx.x * S::TX, Y0 = blockIdx.y * S::TY, Z0 = bz * S::TZ;
   const int64_t off = (int64_t)rhs * a.ndof;
   const T* u = a.uin + off;
+  // the owned DOF's update operands go first (in flight through the product phases)
+  const int ox = tid % S::TX, oy = (tid / S::TX) % S::TY, oz = tid / (S::TX * S::TY);
+  const int gx = X0 + ox, gy = Y0 + oy, gz = Z0 + oz;
+  const bool own = tid < S::NOWN && gx < a.nb[0] && gy < a.nb[1] && gz < a.nb[2];
+  const int64_t g = own ? gx + (int64_t)a.nb[0] * (gy + (int64_t)a.nb[1] * gz) : 0;
+  T d_own = (T)0, im_own = (T)0;
+  if (own && !a.apply) {
+    d_own = a.d[off + g];
+    im_own = a.invm[g];
+  }
+  // the interior matrix as MFMA A fragments (lane lc + 16 lk holds K_int[16 mb + lc][4 kk +
+  // lk]) and the LDS offsets of this lane's B rows (function 4 kk + lk of a cell)
+  constexpr int NMBX = S::MF ? S::NMB : 1, NKSX = S::MF ? S::NKS : 1;
+  T areg[NMBX][NKSX];
+  int offk[NKSX];
+  if constexpr (S::MF) {
+    const int lc = tid & 15, lk = (tid & 63) >> 4;
+#pragma unroll
+    for (int kk = 0; kk < S::NKS; ++kk) {
+      const int e = 4 * kk + lk;
+      const int ee = e < NS ? e : 0;  // padded k rows read a real value (A is zero there)
+      const int jx = ee % P1, jy = (ee / P1) % P1, jz = ee / (P1 * P1);
+      offk[kk] = jx + S::UX * (jy + S::UY * (DIM == 3 ? jz : 0));
+#pragma unroll
+      for (int mb = 0; mb < S::NMB; ++mb) {
+        const int r = mb * 16 + lc;
+        areg[mb][kk] = (r < NS && e < NS) ? a.kint[r * NS + e] : (T)0;
+      }
+    }
+  }
   // u of the DOFs [X0 - P, X0 + TX + P) (per direction), zero outside the grid
   for (int e = tid; e < S::NUR; e += 256) {
     const int ex = e % S::UX, ey = (e / S::UX) % S::UY, ez = e / (S::UX * S::UY);
-    const int gx = X0 - P + ex, gy = Y0 - P + ey, gz = Z0 - (DIM == 3 ? P : 0) + ez;
-    const bool in = gx >= 0 && gx < a.nb[0] && gy >= 0 && gy < a.nb[1] && gz >= 0 &&
-                    gz < a.nb[2];
-    us[e] = in ? u[gx + (int64_t)a.nb[0] * (gy + (int64_t)a.nb[1] * gz)] : (T)0;
+    const int hx = X0 - P + ex, hy = Y0 - P + ey, hz = Z0 - (DIM == 3 ? P : 0) + ez;
+    const bool in = hx >= 0 && hx < a.nb[0] && hy >= 0 && hy < a.nb[1] && hz >= 0 &&
+                    hz < a.nb[2];
+    us[e] = in ? u[hx + (int64_t)a.nb[0] * (hy + (int64_t)a.nb[1] * hz)] : (T)0;
   }
-  __syncthreads();
-  // products of the cells [X0 - P, X0 + TX) (per direction)
+  // codes of the cells [X0 - P, X0 + TX) (per direction): kInfoOut, kInfoUncut for the
+  // interior class, the cut candidate (>= 0), or -3 - q for an uncut cell of class q
   for (int cl = tid; cl < S::NCR; cl += 256) {
     const int lx = cl % S::CX, ly = (cl / S::CX) % S::CY, lz = cl / (S::CX * S::CY);
     const int cx = X0 - P + lx, cy = Y0 - P + ly, cz = Z0 - (DIM == 3 ? P : 0) + lz;
-    T* y = ys + (size_t)cl * NS;
     int32_t inf = kInfoOut;
     if (cx >= 0 && cx < a.n[0] && cy >= 0 && cy < a.n[1] && cz >= 0 && cz < a.n[2])
       inf = a.info[cx + (int64_t)a.n[0] * (cy + (int64_t)a.n[1] * cz)];
+    if (inf == kInfoUncut) {
+      int q = iga_class(P, a.n[0], cx) + S::NCLS * iga_class(P, a.n[1], cy);
+      if (DIM == 3) q += S::NCLS * S::NCLS * iga_class(P, a.n[2], cz);
+      if (q != S::QINT) inf = -3 - q;
+    }
+    cin[cl] = inf;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    // wave 0 lists the cells with their own matrix, in region order
+    int base = 0;
+    for (int c0 = 0; c0 < S::NCR; c0 += 64) {
+      const int cl = c0 + tid;
+      const int v = cl < S::NCR ? cin[cl] : kInfoOut;
+      const bool g = v >= 0 || v <= -3;
+      const unsigned long long m = __ballot(g);
+      if (g) glist[base + __popcll(m & ((1ull << tid) - 1ull))] = cl;
+      base += __popcll(m);
+    }
+    if (tid == 0) *gcnt = base;
+  }
+  if constexpr (S::MF) {
+    // interior-class cells on the matrix cores: Y (NS x 16 cells) = K_int U, lane lc + 16 lk
+    // holds K_int[16 mb + lc][4 kk + lk] and u of cell 16 b + lc at function 4 kk + lk
+    const int lane = tid & 63, wave = tid >> 6, lc = lane & 15, lk = lane >> 4;
+    constexpr int NB = (S::NCR + 15) / 16;
+    for (int b = wave; b < NB; b += 4) {
+      const int cl = min(b * 16 + lc, S::NCR - 1);
+      const int lx = cl % S::CX, ly = (cl / S::CX) % S::CY, lz = cl / (S::CX * S::CY);
+      const int base = lx + S::UX * (ly + S::UY * lz);
+      T bv[S::NKS];
+#pragma unroll
+      for (int kk = 0; kk < S::NKS; ++kk) bv[kk] = us[base + offk[kk]];
+      const bool mine = b * 16 + lc < S::NCR && cin[cl] == kInfoUncut;
+#pragma unroll
+      for (int mb = 0; mb < S::NMB; ++mb) {
+        typename Mma<T>::acc acc = typename Mma<T>::acc{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < S::NKS; ++kk) acc = Mma<T>::mma(areg[mb][kk], bv[kk], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mb * 16 + Mma<T>::row(lk, r);
+          if (mine && row < NS) ys[(size_t)cl * NSP + row] = acc[r];
+        }
+      }
+    }
+  }
+  // outside cells: zeros; without the matrix-core form, interior cells one per thread
+  for (int cl = tid; cl < S::NCR; cl += 256) {
+    const int inf = cin[cl];
+    T* y = ys + (size_t)cl * NSP;
     if (inf == kInfoOut) {
       for (int i = 0; i < NS; ++i) y[i] = (T)0;
-      continue;
-    }
-    T ue[NS];
+    } else if (!S::MF && inf == kInfoUncut) {
+      const int lx = cl % S::CX, ly = (cl / S::CX) % S::CY, lz = cl / (S::CX * S::CY);
+      T ue[NS];
 #pragma unroll
-    for (int e = 0; e < NS; ++e) {
-      const int jx = e % P1, jy = (e / P1) % P1, jz = e / (P1 * P1);
-      ue[e] = us[(lx + jx) + S::UX * ((ly + jy) + S::UY * (lz + (DIM == 3 ? jz : 0)))];
-    }
-    int q = iga_class(P, a.n[0], cx) + S::NCLS * iga_class(P, a.n[1], cy);
-    if (DIM == 3) q += S::NCLS * S::NCLS * iga_class(P, a.n[2], cz);
-    if (inf == kInfoUncut && q == S::QINT) {
-      // interior class: one matrix for every lane on this path (uniform loads)
+      for (int e = 0; e < NS; ++e) {
+        const int jx = e % P1, jy = (e / P1) % P1, jz = e / (P1 * P1);
+        ue[e] = us[(lx + jx) + S::UX * ((ly + jy) + S::UY * (lz + (DIM == 3 ? jz : 0)))];
+      }
+      // one matrix for every lane on this path (uniform loads)
       for (int i = 0; i < NS; ++i) {
         T acc = (T)0;
 #pragma unroll
         for (int j = 0; j < NS; ++j) acc += a.kint[i * NS + j] * ue[j];
         y[i] = acc;
       }
-    } else {
-      const T* K = inf >= 0 ? a.kcut + (size_t)inf * NS * NS : a.kcls + (size_t)q * NS * NS;
-      for (int i = 0; i < NS; ++i) {
-        T acc = (T)0;
-#pragma unroll
-        for (int j = 0; j < NS; ++j) acc += K[i * NS + j] * ue[j];
-        y[i] = acc;
-      }
     }
   }
   __syncthreads();
-  if (tid >= S::NOWN) return;
-  const int ox = tid % S::TX, oy = (tid / S::TX) % S::TY, oz = tid / (S::TX * S::TY);
-  const int gx = X0 + ox, gy = Y0 + oy, gz = Z0 + oz;
-  if (gx >= a.nb[0] || gy >= a.nb[1] || gz >= a.nb[2]) return;
+  // cells with their own matrix (cut cells; uncut cells of a boundary class): LPC lanes
+  // per cell, lane r forms row r with all NS matrix loads issued together
+  {
+    constexpr int LPC = NS <= 32 ? 32 : 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r = lane % LPC, slot = lane / LPC;
+    const int ng = *gcnt;
+    for (int g0 = (wave * 64 / LPC); g0 < ng; g0 += 4 * 64 / LPC) {
+      const int gi = g0 + slot;
+      if (gi >= ng || r >= NS) continue;
+      const int cl = glist[gi];
+      const int inf = cin[cl];
+      const T* K = inf >= 0 ? a.kcut + (size_t)inf * NS * NS
+                            : a.kcls + (size_t)(-3 - inf) * NS * NS;
+      T kr[NS];
+#pragma unroll
+      for (int j = 0; j < NS; ++j) kr[j] = K[(size_t)r * NS + j];
+      const int lx = cl % S::CX, ly = (cl / S::CX) % S::CY, lz = cl / (S::CX * S::CY);
+      T acc = (T)0;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int jx = j % P1, jy = (j / P1) % P1, jz = j / (P1 * P1);
+        acc += kr[j] * us[(lx + jx) + S::UX * ((ly + jy) + S::UY * (lz + (DIM == 3 ? jz : 0)))];
+      }
+      ys[(size_t)cl * NSP + r] = acc;
+    }
+  }
+  __syncthreads();
+  if (!own) return;
   // the cells of this DOF: local cell ox + P - jx for jx = 0..P (lower cells first)
   T acc = (T)0;
   for (int jz = (DIM == 3 ? P : 0); jz >= 0; --jz)
@@ -468,9 +573,8 @@ __global__ __launch_bounds__(256) void iga_step_kernel(IgaStepArgs<T> a) {
 #pragma unroll
       for (int jx = P; jx >= 0; --jx) {
         const int cl = (ox + P - jx) + S::CX * ((oy + P - jy) + S::CY * (oz + (DIM == 3 ? P : 0) - jz));
-        acc += ys[(size_t)cl * NS + jx + P1 * (jy + P1 * jz)];
+        acc += ys[(size_t)cl * NSP + jx + P1 * (jy + P1 * jz)];
       }
-  const int64_t g = gx + (int64_t)a.nb[0] * (gy + (int64_t)a.nb[1] * gz);
   if (a.apply) {
     a.uout[off + g] = acc;
     return;
@@ -480,8 +584,7 @@ __global__ __launch_bounds__(256) void iga_step_kernel(IgaStepArgs<T> a) {
   const int sx = gx - s.c[0], sy = gy - s.c[1], sz = gz - s.c[2];
   if (sx >= 0 && sx <= P && sy >= 0 && sy <= P && (DIM == 2 || (sz >= 0 && sz <= P)))
     F = (T)(ricker(a.t, s.f0) * s.b[sx + P1 * (sy + P1 * (DIM == 3 ? sz : 0))]);
-  const T im = a.invm[g];
-  const T dn = a.d[off + g] + (T)a.dt2 * im * (F - acc);
+  const T dn = d_own + (T)a.dt2 * im_own * (F - acc);
   a.d[off + g] = dn;
   a.uout[off + g] = us[(ox + P) + S::UX * ((oy + P) + S::UY * (oz + (DIM == 3 ? P : 0)))] + dn;
 }
