@@ -143,14 +143,14 @@ def cell_shape(prob, kv, cell, pts):
     mi = element.local_multi_index(p, dim)
     vals, ders = [], []
     for k in range(dim):
-        # the pieces of the cell's own knot span (span c + p), also for a point on the
-        # cell's upper face
+        # functions c .. c + p depend on the knots t_c .. t_{c+2p+1} only: the recursion
+        # runs on that slice, where the cell's own knot span (span c + p of the whole
+        # vector, also for a point on the cell's upper face) is span p
         c = int(ci[k])
         x = pts[:, k]
-        V = bspline_values(kv[k], p, x, span=c + p)
-        D = bspline_derivatives(kv[k], p, x, span=c + p)
-        vals.append(V[:, c:c + p + 1])
-        ders.append(D[:, c:c + p + 1])
+        t = kv[k][c:c + 2 * p + 2]
+        vals.append(bspline_values(t, p, x, span=p))
+        ders.append(bspline_derivatives(t, p, x, span=p))
     npts, ns = pts.shape[0], mi.shape[0]
     N = np.ones((npts, ns))
     G = np.ones((npts, dim, ns))
@@ -171,6 +171,23 @@ def element_matrices(prob, kv, cell, pts, wts, alpha_vals):
     return K, M
 
 
+def cell_matrices(prob, kv, cell, cls_value):
+    """(K, M) of one cell of class cls_value (UNCUT: the GL rule; CUT: the space tree), or
+    None for a cut cell whose tree finds only void (the cell is then dropped)."""
+    lo = prob.cell_lo(int(cell))
+    hi = lo + prob.h
+    if cls_value == geometry.UNCUT:
+        pts, wts = element.box_rule(prob.p, lo, hi)
+        av = np.ones(len(wts))
+    else:
+        pts, wts, av, all_void = quadrature.tree_rule(prob.p, lo, hi, prob.void_center,
+                                                      prob.void_radius, prob.alpha,
+                                                      prob.tree_depth, prob.cube)
+        if all_void:
+            return None
+    return element_matrices(prob, kv, int(cell), pts, wts, av)
+
+
 def build(prob):
     """Assemble the IGA-FCM problem of a scalar ``Problem`` (its p, grid, voids, cube,
     alpha, rho, c, tree depth)."""
@@ -180,19 +197,11 @@ def build(prob):
     kv = knots(prob)
     Ks, Ms, keep = [], [], []
     for cell in np.flatnonzero(cls != geometry.OUT):
-        lo = prob.cell_lo(int(cell))
-        hi = lo + prob.h
-        if cls[cell] == geometry.UNCUT:
-            pts, wts = element.box_rule(prob.p, lo, hi)
-            av = np.ones(len(wts))
-        else:
-            pts, wts, av, all_void = quadrature.tree_rule(prob.p, lo, hi, prob.void_center,
-                                                          prob.void_radius, prob.alpha,
-                                                          prob.tree_depth, prob.cube)
-            if all_void:
-                cls[cell] = geometry.OUT
-                continue
-        K, M = element_matrices(prob, kv, int(cell), pts, wts, av)
+        km = cell_matrices(prob, kv, int(cell), cls[cell])
+        if km is None:
+            cls[cell] = geometry.OUT
+            continue
+        K, M = km
         Ks.append(K)
         Ms.append(M)
         keep.append(int(cell))
