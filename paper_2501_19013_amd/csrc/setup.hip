@@ -425,11 +425,18 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   constexpr int EPT = (NENT + kTreeThreads - 1) / kTreeThreads;
   constexpr int NG = (NCOMP == 1) ? 1 : DIM * DIM;
   constexpr int PD = 2 + 2 * DIM * NP1;  // per point: w_mass, w_stiff, L[DIM][NP1], dL[DIM][NP1]
+  // leaf points are taken NBQ at a time; each point's shape values N[NS] and reference
+  // gradients G[DIM][NS] are formed once (PDQ doubles with the two weights), so the
+  // per-entry loop reads two values per function instead of re-forming the products
+  constexpr int PDQ = 2 + (1 + DIM) * NS;
+  constexpr int NBQ_ = (32 * 1024) / (PDQ * 8);
+  constexpr int NBQ = NBQ_ < 1 ? 1 : (NBQ_ > kTreeBatch ? kTreeBatch : NBQ_);
 
   __shared__ uint32_t lst[2][kTreeMaxBoxes];
   __shared__ uint32_t outl[kTreeMaxBoxes];
   __shared__ int scan_sh[512];
-  __shared__ double pts[kTreeBatch * PD];
+  __shared__ double pts[NBQ * PD];
+  __shared__ double ptq[NBQ * PDQ];
   __shared__ int s_ncur, s_nout;
 
   const int q = blockIdx.x;
@@ -506,15 +513,14 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   const int nout = s_nout;
 
   // ---- integration ----
-  int ei[EPT], ej[EPT];
+  int eij[EPT];  // row | column << 16 of each entry of this thread
   double accM[EPT], accG[EPT][NG];
   for (int e = 0; e < EPT; ++e) {
     int lin = tid + e * kTreeThreads;
     int j = 0;
     while ((j + 1) * (j + 2) / 2 <= lin) ++j;
     int i = lin - j * (j + 1) / 2;
-    ei[e] = (lin < NENT) ? i : 0;
-    ej[e] = (lin < NENT) ? j : 0;
+    eij[e] = (lin < NENT) ? (i | (j << 16)) : 0;
     accM[e] = 0.0;
     for (int g = 0; g < NG; ++g) accG[e][g] = 0.0;
   }
@@ -554,7 +560,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
     for (int e = 0; e < EPT; ++e) {
       if (tid + e * kTreeThreads >= NENT) break;
       int ia[3] = {0, 0, 0}, ja[3] = {0, 0, 0};
-      int ri = ei[e], rj = ej[e];
+      int ri = eij[e] & 0xFFFF, rj = eij[e] >> 16;
       for (int k = 0; k < DIM; ++k) {
         ia[k] = ri % NP1; ri /= NP1;
         ja[k] = rj % NP1; rj /= NP1;
@@ -591,8 +597,8 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   __syncthreads();
   const uint32_t* leafl = lst[0];
   const int npts_total = s_nleaf * NPB;
-  for (int pb = 0; pb < npts_total; pb += kTreeBatch) {
-    if (tid < kTreeBatch) {
+  for (int pb = 0; pb < npts_total; pb += NBQ) {
+    if (tid < NBQ) {
       int ip = pb + tid;
       double* d = pts + tid * PD;
       if (ip < npts_total) {
@@ -634,46 +640,62 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
       }
     }
     __syncthreads();
-    const int nb = min(kTreeBatch, npts_total - pb);
+    // N_a = prod_k L_k(i_k(a)) and G_b,a = dL_b(i_b(a)) prod_{k != b} L_k(i_k(a)), products
+    // taken in increasing k
+    for (int t = tid; t < NBQ * NS; t += kTreeThreads) {
+      const int qp = t / NS, an = t % NS;
+      const double* d = pts + qp * PD;
+      const double* L = d + 2;
+      const double* dL = d + 2 + DIM * NP1;
+      double* o = ptq + qp * PDQ;
+      int ia[3] = {0, 0, 0};
+      int ri = an;
+      for (int k = 0; k < DIM; ++k) { ia[k] = ri % NP1; ri /= NP1; }
+      double Nv = 1.0;
+      for (int k = 0; k < DIM; ++k) Nv *= L[k * NP1 + ia[k]];
+      o[2 + an] = Nv;
+      for (int b = 0; b < DIM; ++b) {
+        double v = dL[b * NP1 + ia[b]];
+        for (int k = 0; k < DIM; ++k) {
+          if (k == b) continue;
+          v *= L[k * NP1 + ia[k]];
+        }
+        o[2 + (1 + b) * NS + an] = v;
+      }
+      if (an == 0) {
+        o[0] = d[0];
+        o[1] = d[1];
+      }
+    }
+    __syncthreads();
+    const int nb = min(NBQ, npts_total - pb);
     for (int e = 0; e < EPT; ++e) {
       if (tid + e * kTreeThreads >= NENT) break;
-      int ia[3], ja[3];
-      int ri = ei[e], rj = ej[e];
-      for (int k = 0; k < DIM; ++k) {
-        ia[k] = ri % NP1; ri /= NP1;
-        ja[k] = rj % NP1; rj /= NP1;
-      }
+      const int ri = eij[e] & 0xFFFF, rj = eij[e] >> 16;
       double sm = 0.0;
       double sg[NG];
       for (int g = 0; g < NG; ++g) sg[g] = 0.0;
+#pragma unroll 1
       for (int qp = 0; qp < nb; ++qp) {
-        const double* d = pts + qp * PD;
-        const double* L = d + 2;
-        const double* dL = d + 2 + DIM * NP1;
-        double Ni = 1.0, Nj = 1.0;
+        // the entry's offsets are re-formed here (opaque to loop-invariant hoisting, which
+        // would keep them live for every entry of the thread across the point loop)
+        int oi = ri, oj = rj;
+        asm volatile("" : "+v"(oi), "+v"(oj));
+        const double* o = ptq + qp * PDQ;
+        const double Ni = o[2 + oi], Nj = o[2 + oj];
         double gi[DIM], gj[DIM];
-        for (int k = 0; k < DIM; ++k) {
-          Ni *= L[k * NP1 + ia[k]];
-          Nj *= L[k * NP1 + ja[k]];
-        }
         for (int b = 0; b < DIM; ++b) {
-          double vi = dL[b * NP1 + ia[b]], vj = dL[b * NP1 + ja[b]];
-          for (int k = 0; k < DIM; ++k) {
-            if (k == b) continue;
-            vi *= L[k * NP1 + ia[k]];
-            vj *= L[k * NP1 + ja[k]];
-          }
-          gi[b] = vi;
-          gj[b] = vj;
+          gi[b] = o[2 + (1 + b) * NS + oi];
+          gj[b] = o[2 + (1 + b) * NS + oj];
         }
-        sm += d[0] * Ni * Nj;
+        sm += o[0] * Ni * Nj;
         if (NCOMP == 1) {
           double s = 0.0;
           for (int b = 0; b < DIM; ++b) s += gi[b] * gj[b];
-          sg[0] += d[1] * s;
+          sg[0] += o[1] * s;
         } else {
           for (int b = 0; b < DIM; ++b)
-            for (int c2 = 0; c2 < DIM; ++c2) sg[b * DIM + c2] += d[1] * gi[b] * gj[c2];
+            for (int c2 = 0; c2 < DIM; ++c2) sg[b * DIM + c2] += o[1] * gi[b] * gj[c2];
         }
       }
       accM[e] += sm;
@@ -688,7 +710,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   double* M = a.mout + (int64_t)q * NS * NS;
   for (int e = 0; e < EPT; ++e) {
     if (tid + e * kTreeThreads >= NENT) break;
-    const int i = ei[e], j = ej[e];
+    const int i = eij[e] & 0xFFFF, j = eij[e] >> 16;
     const double m = a.rho * accM[e];
     M[i * NS + j] = m;
     M[j * NS + i] = m;
