@@ -415,6 +415,102 @@ __device__ static void scan2_256(int a, int b, int& pa, int& pb, int& ta, int& t
   __syncthreads();
 }
 
+// ---- leaf integration of 3-D scalar cut cells on the matrix cores ----
+// Over a batch of leaf points the leaf parts are K += sum_(q,b) w1_q G_b(q) G_b(q)^T and
+// M += sum_q w0_q N(q) N(q)^T: products of an (n_s x kappa) and a (kappa x n_s) operand
+// with kappa the (point, direction) rows.  The n_s x n_s outputs (padded to NT x NT tiles
+// of 16) keep their upper tiles in mfma_f64_16x16x4 accumulators, K tiles then M tiles,
+// tile t on wave t mod 4.
+typedef double tree_f64x4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+struct TreeTiles {
+  static constexpr int NUT = NT * (NT + 1) / 2;
+  int I[2 * NUT], J[2 * NUT], mat[2 * NUT];
+  constexpr TreeTiles() : I(), J(), mat() {
+    int t = 0;
+    for (int m = 0; m < 2; ++m)
+      for (int jj = 0; jj < NT; ++jj)
+        for (int ii = 0; ii <= jj; ++ii) {
+          I[t] = ii;
+          J[t] = jj;
+          mat[t] = m;
+          ++t;
+        }
+  }
+};
+
+// one batch: gk rows (point, direction) and nk rows (point) of LS doubles, weights
+// wq[point] = (w0, w1); lane l16 + 16 k4 holds operand row 4 ks + k4, column 16 blk + l16
+template <int NT, int W, int NBQ, int LS, int TPW>
+__device__ static __attribute__((always_inline)) void tree_leaf_mfma(const double* gk, const double* nk, const double* wq,
+                                      int lane, tree_f64x4 (&acc)[TPW]) {
+  constexpr TreeTiles<NT> tt{};
+  constexpr int NTILE = 2 * TreeTiles<NT>::NUT;
+  const int l16 = lane & 15, k4 = lane >> 4;
+  // K: 3 NBQ rows
+#pragma unroll 1
+  for (int ks = 0; ks < 3 * NBQ / 4; ++ks) {
+    const int r = 4 * ks + k4;
+    const double w = wq[(r / 3) * 2 + 1];
+    double bf[NT], af[NT];
+#pragma unroll
+    for (int jb = 0; jb < NT; ++jb) {
+      bf[jb] = gk[r * LS + jb * 16 + l16];
+      af[jb] = w * bf[jb];
+    }
+#pragma unroll
+    for (int m = 0; m < TPW; ++m) {
+      const int t = W + 4 * m;
+      if (t < NTILE && tt.mat[t] == 0)
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[tt.I[t]], bf[tt.J[t]], acc[m], 0, 0, 0);
+    }
+  }
+  // M: NBQ rows
+#pragma unroll 1
+  for (int ks = 0; ks < NBQ / 4; ++ks) {
+    const int r = 4 * ks + k4;
+    const double w = wq[r * 2];
+    double bf[NT], af[NT];
+#pragma unroll
+    for (int jb = 0; jb < NT; ++jb) {
+      bf[jb] = nk[r * LS + jb * 16 + l16];
+      af[jb] = w * bf[jb];
+    }
+#pragma unroll
+    for (int m = 0; m < TPW; ++m) {
+      const int t = W + 4 * m;
+      if (t < NTILE && tt.mat[t] == 1)
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[tt.I[t]], bf[tt.J[t]], acc[m], 0, 0, 0);
+    }
+  }
+}
+
+// adds the wave's tiles (times c^2 rho for K, rho for M) to the full symmetric K and M
+template <int NT, int W, int NS, int TPW>
+__device__ static __attribute__((always_inline)) void tree_leaf_store(double* K, double* M, double krho, double rho, int lane,
+                                       const tree_f64x4 (&acc)[TPW]) {
+  constexpr TreeTiles<NT> tt{};
+  constexpr int NTILE = 2 * TreeTiles<NT>::NUT;
+  const int l16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < TPW; ++m) {
+    const int t = W + 4 * m;
+    if (t >= NTILE) continue;
+    double* D = tt.mat[t] == 0 ? K : M;
+    const double sc = tt.mat[t] == 0 ? krho : rho;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = tt.I[t] * 16 + 4 * r + k4, j = tt.J[t] * 16 + l16;
+      if (i < NS && j < NS) {
+        const double v = sc * acc[m][r];
+        D[i * NS + j] += v;
+        if (tt.I[t] != tt.J[t]) D[j * NS + i] += v;
+      }
+    }
+  }
+}
+
 template <int DIM, int P, int NCOMP>
 __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a) {
 #pragma clang fp contract(off)
@@ -429,14 +525,20 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   // gradients G[DIM][NS] are formed once (PDQ doubles with the two weights), so the
   // per-entry loop reads two values per function instead of re-forming the products
   constexpr int PDQ = 2 + (1 + DIM) * NS;
-  constexpr int NBQ_ = (32 * 1024) / (PDQ * 8);
+  // 3-D scalar cells integrate their leaves on the matrix cores (tree_leaf_mfma)
+  constexpr bool MFL = DIM == 3 && NCOMP == 1;
+  constexpr int NT = (NS + 15) / 16;
+  constexpr int LS = (NT % 2 == 0) ? NT * 16 + 16 : NT * 16;  // row stride: 2-way banks
+  constexpr int TPW = (2 * TreeTiles<NT>::NUT + 3) / 4;
+  constexpr int NBQ_ = MFL ? (NT >= 8 ? 8 : 16) : (32 * 1024) / (PDQ * 8);
   constexpr int NBQ = NBQ_ < 1 ? 1 : (NBQ_ > kTreeBatch ? kTreeBatch : NBQ_);
+  static_assert(!MFL || NBQ % 4 == 0, "whole k-steps of four operand rows");
 
   __shared__ uint32_t lst[2][kTreeMaxBoxes];
   __shared__ uint32_t outl[kTreeMaxBoxes];
   __shared__ int scan_sh[512];
   __shared__ double pts[NBQ * PD];
-  __shared__ double ptq[NBQ * PDQ];
+  __shared__ double ptq[MFL ? NBQ * (4 * LS + 2) : NBQ * PDQ];
   __shared__ int s_ncur, s_nout;
 
   const int q = blockIdx.x;
@@ -597,7 +699,8 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
   __syncthreads();
   const uint32_t* leafl = lst[0];
   const int npts_total = s_nleaf * NPB;
-  for (int pb = 0; pb < npts_total; pb += NBQ) {
+  // weights, 1-D Lagrange values and derivatives of the leaf points pb .. pb + NBQ - 1
+  auto prep_points = [&](int pb) {
     if (tid < NBQ) {
       int ip = pb + tid;
       double* d = pts + tid * PD;
@@ -639,97 +742,166 @@ __global__ __launch_bounds__(kTreeThreads) void tree_integrate_kernel(TreeArgs a
         for (int k = 0; k < PD; ++k) d[k] = 0.0;
       }
     }
-    __syncthreads();
-    // N_a = prod_k L_k(i_k(a)) and G_b,a = dL_b(i_b(a)) prod_{k != b} L_k(i_k(a)), products
-    // taken in increasing k
-    for (int t = tid; t < NBQ * NS; t += kTreeThreads) {
-      const int qp = t / NS, an = t % NS;
-      const double* d = pts + qp * PD;
-      const double* L = d + 2;
-      const double* dL = d + 2 + DIM * NP1;
-      double* o = ptq + qp * PDQ;
-      int ia[3] = {0, 0, 0};
-      int ri = an;
-      for (int k = 0; k < DIM; ++k) { ia[k] = ri % NP1; ri /= NP1; }
-      double Nv = 1.0;
-      for (int k = 0; k < DIM; ++k) Nv *= L[k * NP1 + ia[k]];
-      o[2 + an] = Nv;
-      for (int b = 0; b < DIM; ++b) {
-        double v = dL[b * NP1 + ia[b]];
-        for (int k = 0; k < DIM; ++k) {
-          if (k == b) continue;
-          v *= L[k * NP1 + ia[k]];
-        }
-        o[2 + (1 + b) * NS + an] = v;
-      }
-      if (an == 0) {
-        o[0] = d[0];
-        o[1] = d[1];
-      }
-    }
-    __syncthreads();
-    const int nb = min(NBQ, npts_total - pb);
+  };
+  auto write_out = [&]() {
+    constexpr int NL = NCOMP * NS;
+    double* K = a.kout + (int64_t)q * NL * NL;
+    double* M = a.mout + (int64_t)q * NS * NS;
     for (int e = 0; e < EPT; ++e) {
       if (tid + e * kTreeThreads >= NENT) break;
-      const int ri = eij[e] & 0xFFFF, rj = eij[e] >> 16;
-      double sm = 0.0;
-      double sg[NG];
-      for (int g = 0; g < NG; ++g) sg[g] = 0.0;
-#pragma unroll 1
-      for (int qp = 0; qp < nb; ++qp) {
-        // the entry's offsets are re-formed here (opaque to loop-invariant hoisting, which
-        // would keep them live for every entry of the thread across the point loop)
-        int oi = ri, oj = rj;
-        asm volatile("" : "+v"(oi), "+v"(oj));
-        const double* o = ptq + qp * PDQ;
-        const double Ni = o[2 + oi], Nj = o[2 + oj];
-        double gi[DIM], gj[DIM];
-        for (int b = 0; b < DIM; ++b) {
-          gi[b] = o[2 + (1 + b) * NS + oi];
-          gj[b] = o[2 + (1 + b) * NS + oj];
+      const int i = eij[e] & 0xFFFF, j = eij[e] >> 16;
+      const double m = a.rho * accM[e];
+      M[i * NS + j] = m;
+      M[j * NS + i] = m;
+      if (NCOMP == 1) {
+        const double k = a.c2 * a.rho * accG[e][0];
+        K[i * NL + j] = k;
+        K[j * NL + i] = k;
+      } else {
+        double tr = 0.0;
+        for (int b = 0; b < DIM; ++b) tr += accG[e][b * DIM + b];
+        for (int cc = 0; cc < NCOMP; ++cc)
+          for (int ee = 0; ee < NCOMP; ++ee) {
+            // K[(c,i),(e,j)] = lam G_ce[i][j] + mu G_ec[i][j] + mu delta_ce sum_a G_aa[i][j]
+            double v = a.lam * accG[e][cc * DIM + ee] + a.mu * accG[e][ee * DIM + cc] +
+                       (cc == ee ? a.mu * tr : 0.0);
+            K[(cc * NS + i) * NL + ee * NS + j] = v;
+            K[(ee * NS + j) * NL + cc * NS + i] = v;
+          }
+      }
+    }
+  };
+  if constexpr (MFL) {
+    // the constant boxes' sums go out first; the leaves are added on the matrix cores
+    write_out();
+    __syncthreads();
+    double* gk = ptq;                    // [NBQ][DIM][LS]
+    double* nk = ptq + NBQ * DIM * LS;   // [NBQ][LS]
+    double* wq = ptq + NBQ * 4 * LS;     // [NBQ][2]
+    const int wave = tid >> 6, lane = tid & 63;
+    tree_f64x4 acc[TPW];
+#pragma unroll
+    for (int m = 0; m < TPW; ++m) acc[m] = tree_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int pb = 0; pb < npts_total; pb += NBQ) {
+      prep_points(pb);
+      __syncthreads();
+      // operand rows: N and the reference gradients of every point (zero beyond n_s)
+      for (int t = tid; t < NBQ * NT * 16; t += kTreeThreads) {
+        const int qp = t / (NT * 16), an = t % (NT * 16);
+        const double* d = pts + qp * PD;
+        const double* L = d + 2;
+        const double* dL = d + 2 + DIM * NP1;
+        double Nv = 0.0, Gv[DIM];
+        for (int b = 0; b < DIM; ++b) Gv[b] = 0.0;
+        if (an < NS) {
+          int ia[3] = {0, 0, 0};
+          int ri = an;
+          for (int k = 0; k < DIM; ++k) { ia[k] = ri % NP1; ri /= NP1; }
+          Nv = 1.0;
+          for (int k = 0; k < DIM; ++k) Nv *= L[k * NP1 + ia[k]];
+          for (int b = 0; b < DIM; ++b) {
+            double v = dL[b * NP1 + ia[b]];
+            for (int k = 0; k < DIM; ++k) {
+              if (k == b) continue;
+              v *= L[k * NP1 + ia[k]];
+            }
+            Gv[b] = v;
+          }
         }
-        sm += o[0] * Ni * Nj;
-        if (NCOMP == 1) {
-          double s = 0.0;
-          for (int b = 0; b < DIM; ++b) s += gi[b] * gj[b];
-          sg[0] += o[1] * s;
-        } else {
-          for (int b = 0; b < DIM; ++b)
-            for (int c2 = 0; c2 < DIM; ++c2) sg[b * DIM + c2] += o[1] * gi[b] * gj[c2];
+        nk[qp * LS + an] = Nv;
+        for (int b = 0; b < DIM; ++b) gk[(qp * DIM + b) * LS + an] = Gv[b];
+        if (an == 0) {
+          wq[qp * 2] = d[0];
+          wq[qp * 2 + 1] = d[1];
         }
       }
-      accM[e] += sm;
-      for (int g = 0; g < NG; ++g) accG[e][g] += sg[g];
+      __syncthreads();
+      switch (wave) {
+        case 0: tree_leaf_mfma<NT, 0, NBQ, LS, TPW>(gk, nk, wq, lane, acc); break;
+        case 1: tree_leaf_mfma<NT, 1, NBQ, LS, TPW>(gk, nk, wq, lane, acc); break;
+        case 2: tree_leaf_mfma<NT, 2, NBQ, LS, TPW>(gk, nk, wq, lane, acc); break;
+        default: tree_leaf_mfma<NT, 3, NBQ, LS, TPW>(gk, nk, wq, lane, acc); break;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-
-  // ---- write K (n_loc x n_loc) and scalar M (n_s x n_s), both full symmetric ----
-  constexpr int NL = NCOMP * NS;
-  double* K = a.kout + (int64_t)q * NL * NL;
-  double* M = a.mout + (int64_t)q * NS * NS;
-  for (int e = 0; e < EPT; ++e) {
-    if (tid + e * kTreeThreads >= NENT) break;
-    const int i = eij[e] & 0xFFFF, j = eij[e] >> 16;
-    const double m = a.rho * accM[e];
-    M[i * NS + j] = m;
-    M[j * NS + i] = m;
-    if (NCOMP == 1) {
-      const double k = a.c2 * a.rho * accG[e][0];
-      K[i * NL + j] = k;
-      K[j * NL + i] = k;
-    } else {
-      double tr = 0.0;
-      for (int b = 0; b < DIM; ++b) tr += accG[e][b * DIM + b];
-      for (int cc = 0; cc < NCOMP; ++cc)
-        for (int ee = 0; ee < NCOMP; ++ee) {
-          // K[(c,i),(e,j)] = lam G_ce[i][j] + mu G_ec[i][j] + mu delta_ce sum_a G_aa[i][j]
-          double v = a.lam * accG[e][cc * DIM + ee] + a.mu * accG[e][ee * DIM + cc] +
-                     (cc == ee ? a.mu * tr : 0.0);
-          K[(cc * NS + i) * NL + ee * NS + j] = v;
-          K[(ee * NS + j) * NL + cc * NS + i] = v;
+    double* Kq = a.kout + (int64_t)q * NS * NS;
+    double* Mq = a.mout + (int64_t)q * NS * NS;
+    const double krho = a.c2 * a.rho;
+    switch (wave) {
+      case 0: tree_leaf_store<NT, 0, NS, TPW>(Kq, Mq, krho, a.rho, lane, acc); break;
+      case 1: tree_leaf_store<NT, 1, NS, TPW>(Kq, Mq, krho, a.rho, lane, acc); break;
+      case 2: tree_leaf_store<NT, 2, NS, TPW>(Kq, Mq, krho, a.rho, lane, acc); break;
+      default: tree_leaf_store<NT, 3, NS, TPW>(Kq, Mq, krho, a.rho, lane, acc); break;
+    }
+  } else {
+    for (int pb = 0; pb < npts_total; pb += NBQ) {
+      prep_points(pb);
+      __syncthreads();
+      // N_a = prod_k L_k(i_k(a)) and G_b,a = dL_b(i_b(a)) prod_{k != b} L_k(i_k(a)), products
+      // taken in increasing k
+      for (int t = tid; t < NBQ * NS; t += kTreeThreads) {
+        const int qp = t / NS, an = t % NS;
+        const double* d = pts + qp * PD;
+        const double* L = d + 2;
+        const double* dL = d + 2 + DIM * NP1;
+        double* o = ptq + qp * PDQ;
+        int ia[3] = {0, 0, 0};
+        int ri = an;
+        for (int k = 0; k < DIM; ++k) { ia[k] = ri % NP1; ri /= NP1; }
+        double Nv = 1.0;
+        for (int k = 0; k < DIM; ++k) Nv *= L[k * NP1 + ia[k]];
+        o[2 + an] = Nv;
+        for (int b = 0; b < DIM; ++b) {
+          double v = dL[b * NP1 + ia[b]];
+          for (int k = 0; k < DIM; ++k) {
+            if (k == b) continue;
+            v *= L[k * NP1 + ia[k]];
+          }
+          o[2 + (1 + b) * NS + an] = v;
         }
+        if (an == 0) {
+          o[0] = d[0];
+          o[1] = d[1];
+        }
+      }
+      __syncthreads();
+      const int nb = min(NBQ, npts_total - pb);
+      for (int e = 0; e < EPT; ++e) {
+        if (tid + e * kTreeThreads >= NENT) break;
+        const int ri = eij[e] & 0xFFFF, rj = eij[e] >> 16;
+        double sm = 0.0;
+        double sg[NG];
+        for (int g = 0; g < NG; ++g) sg[g] = 0.0;
+  #pragma unroll 1
+        for (int qp = 0; qp < nb; ++qp) {
+          // the entry's offsets are re-formed here (opaque to loop-invariant hoisting, which
+          // would keep them live for every entry of the thread across the point loop)
+          int oi = ri, oj = rj;
+          asm volatile("" : "+v"(oi), "+v"(oj));
+          const double* o = ptq + qp * PDQ;
+          const double Ni = o[2 + oi], Nj = o[2 + oj];
+          double gi[DIM], gj[DIM];
+          for (int b = 0; b < DIM; ++b) {
+            gi[b] = o[2 + (1 + b) * NS + oi];
+            gj[b] = o[2 + (1 + b) * NS + oj];
+          }
+          sm += o[0] * Ni * Nj;
+          if (NCOMP == 1) {
+            double s = 0.0;
+            for (int b = 0; b < DIM; ++b) s += gi[b] * gj[b];
+            sg[0] += o[1] * s;
+          } else {
+            for (int b = 0; b < DIM; ++b)
+              for (int c2 = 0; c2 < DIM; ++c2) sg[b * DIM + c2] += o[1] * gi[b] * gj[c2];
+          }
+        }
+        accM[e] += sm;
+        for (int g = 0; g < NG; ++g) accG[e][g] += sg[g];
+      }
+      __syncthreads();
     }
+
+    write_out();
   }
   if (tid == 0 && !a.reference) {
     int allv = 1;
