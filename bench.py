@@ -415,7 +415,7 @@ def bench_serve(count, scale, rate, quantum):
     reqs = requests_from_stream(workloads.request_stream(seed=5, count=count, rate=rate),
                                 scale=scale)
     srv = Server(precision="fp32", quantum=quantum)
-    m = srv.run(reqs)
+    m = srv.run(reqs, log=lambda msg: print(f"[bench] serving {msg}", file=sys.stderr, flush=True))
     srv.close()
     n2 = sum(1 for r in reqs if r.cfg["dim"] == 2)
     m.update(requests=count, scale=scale, rate_per_s=rate, quantum=quantum,

@@ -136,8 +136,9 @@ class Server:
         # quantum and is kept for the later ones
         return _Resident(req=req, ctx=ctx, u=u, d=d, dt=None, footprint=fp)
 
-    def run(self, requests, time_scale=1.0):
-        """Serve ``requests`` (arrival times in seconds); returns a metrics dict."""
+    def run(self, requests, time_scale=1.0, log=None, log_every=20.0):
+        """Serve ``requests`` (arrival times in seconds); returns a metrics dict.  ``log``, if
+        given, is called with a one-line status about every ``log_every`` seconds."""
         torch = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
         waiting, resident, finished = [], [], []
@@ -149,8 +150,13 @@ class Server:
         max_resident = peak_reserved = quanta = 0
         step_s = 0.0
         pi = 0
+        next_log = log_every
         while pi < len(pending) or waiting or resident or setting_up:
             t = now()
+            if log is not None and t >= next_log:
+                log(f"t={t:.0f} s: {len(finished)}/{len(pending)} finished, {len(resident)} "
+                    f"resident, {len(setting_up)} in set-up, {len(waiting)} waiting")
+                next_log = t + log_every
             while pi < len(pending) and pending[pi].arrival <= t:
                 waiting.append(pending[pi])
                 pi += 1
