@@ -336,12 +336,14 @@ def bench_imex(steps, warmup):
     ms_con = e0.elapsed_time(e1)
     s.close()
     return dict(workload="2-D scalar, the c2 void field at 64x64 cells, p=3 GLL, FP64, IMEX "
-                         "(Alg. imex, beta=1/4, gamma=1/2), dense FP64 Cholesky of S and M^cc",
+                         "(Alg. imex, beta=1/4, gamma=1/2), dense FP64 Cholesky of S and M^cc, "
+                         "S^-1 as packed upper tiles",
                 value=active * steps / (ms * 1e-3), unit="DOF-updates/s", ms_per_step=ms / steps,
                 steps=steps, n_implicit=nc, active_dof=active, prepare_s=t_prep, dt=dt,
                 explicit_ms_per_step=ms_exp / steps,
                 consistent_mass_cdm_ms_per_step=ms_con / steps,
-                solve_bytes_per_step=8 * nc * nc)
+                # S^-1 as the packed 32 x 32 tiles of its upper triangle
+                solve_bytes_per_step=8 * 1024 * ((nc + 31) // 32) * ((nc + 31) // 32 + 1) // 2)
 
 
 def bench_iga(steps, warmup):

@@ -271,9 +271,12 @@ fcw_status fcw_kernel_times(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, double* 
  * rest of the active DOFs are explicit.  Assembles M^cc (the consistent cut-cell masses
  * M^o_e without stabilisation plus the GLL diagonals of the uncut cells on implicit
  * DOFs) and S = M^cc + dt^2/4 K^cc, dense, and factors both by Cholesky on the device
- * (FP64).  *n_c receives the number of implicit DOFs, whose global indices
+ * (FP64); the steps use S^{-1} and (M^cc)^{-1} (kept as the packed 32 x 32 tiles of their
+ * upper triangles) and the rows of K at the implicit DOFs (kept as padded sparse rows).
+ * *n_c receives the number of implicit DOFs, whose global indices
  * FCW_ARR_IMEX_DOFS exports (ascending: component-major, then node).
- * FP64 contexts only (FCW_E_UNSUPPORTED otherwise, and when n_c > FCW_IMEX_MAX_NC);
+ * FP64 contexts only (FCW_E_UNSUPPORTED otherwise, when n_c > FCW_IMEX_MAX_NC and when
+ * ndof >= 2^31);
  * FCW_E_NOCONV if a matrix is not positive definite.  Requires the stabilised state.
  * fcw_step_imex calls it itself when dt changes. */
 fcw_status fcw_imex_prepare(fcw_ctx* ctx, double dt, int64_t* n_c);

@@ -143,6 +143,11 @@ struct Ctx {
   int64_t* d_imex_dofs = nullptr;  // [imex_nc] global DOF of each implicit DOF
   double* d_imex_s = nullptr;      // [3][imex_nc^2] L of S (row-major, lower), L^T, S^{-1}
   double* d_imex_m = nullptr;      // [3][imex_nc^2] the same for M^cc
+  double* d_imex_sp = nullptr;     // S^{-1} as its upper 64 x 64 tiles, packed row by row
+  double* d_imex_mp = nullptr;     // (M^cc)^{-1}, the same
+  int32_t* d_imex_kcol = nullptr;  // [imex_nc][imex_kw] the implicit rows of K: columns
+  double* d_imex_kval = nullptr;   // [imex_nc][imex_kw] and values (0 in padding slots)
+  int imex_kw = 0;
   double* d_imex_work = nullptr;   // per-call work vectors
   size_t imex_work_bytes = 0;
   int32_t* d_imex_flag = nullptr;  // [1] non-positive pivot seen

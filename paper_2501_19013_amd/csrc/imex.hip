@@ -9,17 +9,20 @@
 //   1. explicit DOFs: the central-difference step of the explicit solver (its tile and
 //      cut-cell kernels; the values it leaves on implicit DOFs are replaced below);
 //   2. implicit predictors u_p = u_k + dt v_k + (1/2 - beta) dt^2 a_k on the implicit
-//      DOFs, the explicit DOFs' new values serving as theirs;
-//   3. r = K u_p (the explicit solver's stiffness action);
-//   4. S a_{k+1} = F_{k+1} - r on the implicit DOFs, S = M^cc + beta dt^2 K^cc: a dense
-//      product with S^{-1}, formed once from the Cholesky factor of S (forward and
-//      backward sweeps against the unit vectors, one workgroup per column);
+//      DOFs (left in a vector over the implicit DOFs by the previous step's corrector),
+//      the explicit DOFs' new values serving as theirs;
+//   3. b = F_{k+1} - K^c u_p on the implicit DOFs: the implicit rows of K (every column
+//      they touch) assembled once as padded sparse rows, one wave per row;
+//   4. S a_{k+1} = b, S = M^cc + beta dt^2 K^cc: a product with S^{-1}, formed once from
+//      the Cholesky factor of S (forward and backward sweeps against the unit vectors,
+//      one workgroup per column) and held as the 32 x 32 tiles of its upper triangle
+//      (each off-diagonal tile serves its row block and, transposed, its column block);
 //   5. v_{k+1} = v_k + dt ((1 - gamma) a_k + gamma a_{k+1}),
-//      u_{k+1} = u_p + beta dt^2 a_{k+1}.
+//      u_{k+1} = u_p + beta dt^2 a_{k+1} (in the kernel that sums the tile products).
 //
 // The same set-up serves central differences with the consistent cut-DOF mass (the
 // consistent-mass spectral cell method, eq. cdm with M = diag(M^dd, M^cc)): per step
-// a = (M^cc)^{-1} (F_k - K u_k) on the implicit DOFs, the lumped step elsewhere.
+// a = (M^cc)^{-1} (F_k - K^c u_k) on the implicit DOFs, the lumped step elsewhere.
 //
 // S and M^cc are assembled dense (entry by entry from the cells around the two nodes,
 // in a fixed order) and factored on the device by a blocked right-looking Cholesky.
@@ -81,60 +84,108 @@ struct ImexAsm {
   double bdt2;          // beta dt^2
 };
 
+// node coordinates of a DOF
+__device__ inline void dof_coords(const ImexAsm& a, int64_t g, int& comp, int x[3]) {
+  comp = (int)(g / a.nnodes);
+  const int64_t nd = g % a.nnodes;
+  x[0] = (int)(nd % a.np[0]);
+  x[1] = (int)((nd / a.np[0]) % a.np[1]);
+  x[2] = (int)(nd / ((int64_t)a.np[0] * a.np[1]));
+}
+
+// K and M entries of the DOF pair (node xi, component ci), (node xj, component cj): the
+// cells around node i, in a fixed order; those that also hold node j contribute
+__device__ void pair_sums(const ImexAsm& a, const int xi[3], int ci, const int xj[3], int cj,
+                          double& ks, double& ms) {
+  ks = 0.0;
+  ms = 0.0;
+  for (int k = 0; k < a.dim; ++k)
+    if (abs(xi[k] - xj[k]) > a.p) return;
+  const int nz = (a.dim == 3) ? 2 : 1;
+  for (int sz = 0; sz < nz; ++sz)
+    for (int sy = 0; sy < 2; ++sy)
+      for (int sx = 0; sx < 2; ++sx) {
+        const int sel[3] = {sx, sy, sz};
+        int cc[3] = {0, 0, 0};
+        bool ok = true;
+        for (int k = 0; k < a.dim; ++k) {
+          // candidate cells along axis k: floor(x/p) and, on a cell boundary, floor(x/p)-1
+          const int cand = (sel[k] == 0) ? xi[k] / a.p : xi[k] / a.p - 1;
+          if (sel[k] == 1 && xi[k] % a.p != 0) ok = false;
+          if (cand < 0 || cand >= a.n[k]) ok = false;
+          if (xj[k] < cand * a.p || xj[k] > cand * a.p + a.p) ok = false;
+          cc[k] = cand;
+        }
+        if (!ok) continue;
+        const int64_t cell = cc[0] + (int64_t)a.n[0] * (cc[1] + (int64_t)a.n[1] * cc[2]);
+        const int inf = a.info[cell];
+        if (inf == kInfoOut) continue;
+        const int np1 = a.p + 1;
+        const int li = (xi[0] - cc[0] * a.p) + np1 * ((xi[1] - cc[1] * a.p) +
+                                                       np1 * (a.dim == 3 ? xi[2] - cc[2] * a.p : 0));
+        const int lj = (xj[0] - cc[0] * a.p) + np1 * ((xj[1] - cc[1] * a.p) +
+                                                       np1 * (a.dim == 3 ? xj[2] - cc[2] * a.p : 0));
+        const int ri = ci * a.ns + li, rj = cj * a.ns + lj;
+        if (inf >= 0) {
+          ks += a.kcut[((int64_t)inf * a.nl + ri) * a.nl + rj];
+          if (ci == cj) ms += a.mcut[((int64_t)inf * a.ns + li) * a.ns + lj];
+        } else {
+          ks += a.kref[(int64_t)ri * a.nl + rj];
+          if (ci == cj && li == lj) ms += a.lref[li];
+        }
+      }
+}
+
 __global__ void imex_assemble_kernel(ImexAsm a) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = blockIdx.y + (int64_t)gridDim.y * blockIdx.z;
   if (i >= a.nc || j >= a.nc) return;
-  const int64_t gi = a.dofs[i], gj = a.dofs[j];
-  const int ci = (int)(gi / a.nnodes), cj = (int)(gj / a.nnodes);
-  const int64_t ni = gi % a.nnodes, nj = gj % a.nnodes;
-  int xi[3], xj[3];
-  xi[0] = (int)(ni % a.np[0]); xi[1] = (int)((ni / a.np[0]) % a.np[1]);
-  xi[2] = (int)(ni / ((int64_t)a.np[0] * a.np[1]));
-  xj[0] = (int)(nj % a.np[0]); xj[1] = (int)((nj / a.np[0]) % a.np[1]);
-  xj[2] = (int)(nj / ((int64_t)a.np[0] * a.np[1]));
-  double ks = 0.0, ms = 0.0;
-  bool near = true;
-  for (int k = 0; k < a.dim; ++k)
-    if (abs(xi[k] - xj[k]) > a.p) near = false;
-  if (near) {
-    // the cells around node i, in a fixed order; those that also hold node j contribute
-    const int nz = (a.dim == 3) ? 2 : 1;
-    for (int sz = 0; sz < nz; ++sz)
-      for (int sy = 0; sy < 2; ++sy)
-        for (int sx = 0; sx < 2; ++sx) {
-          const int sel[3] = {sx, sy, sz};
-          int cc[3] = {0, 0, 0};
-          bool ok = true;
-          for (int k = 0; k < a.dim; ++k) {
-            // candidate cells along axis k: floor(x/p) and, on a cell boundary, floor(x/p)-1
-            const int cand = (sel[k] == 0) ? xi[k] / a.p : xi[k] / a.p - 1;
-            if (sel[k] == 1 && xi[k] % a.p != 0) ok = false;
-            if (cand < 0 || cand >= a.n[k]) ok = false;
-            if (xj[k] < cand * a.p || xj[k] > cand * a.p + a.p) ok = false;
-            cc[k] = cand;
-          }
-          if (!ok) continue;
-          const int64_t cell = cc[0] + (int64_t)a.n[0] * (cc[1] + (int64_t)a.n[1] * cc[2]);
-          const int inf = a.info[cell];
-          if (inf == kInfoOut) continue;
-          const int np1 = a.p + 1;
-          const int li = (xi[0] - cc[0] * a.p) + np1 * ((xi[1] - cc[1] * a.p) +
-                                                         np1 * (a.dim == 3 ? xi[2] - cc[2] * a.p : 0));
-          const int lj = (xj[0] - cc[0] * a.p) + np1 * ((xj[1] - cc[1] * a.p) +
-                                                         np1 * (a.dim == 3 ? xj[2] - cc[2] * a.p : 0));
-          const int ri = ci * a.ns + li, rj = cj * a.ns + lj;
-          if (inf >= 0) {
-            ks += a.kcut[((int64_t)inf * a.nl + ri) * a.nl + rj];
-            if (ci == cj) ms += a.mcut[((int64_t)inf * a.ns + li) * a.ns + lj];
-          } else {
-            ks += a.kref[(int64_t)ri * a.nl + rj];
-            if (ci == cj && li == lj) ms += a.lref[li];
-          }
-        }
-  }
+  int ci, cj, xi[3], xj[3];
+  dof_coords(a, a.dofs[i], ci, xi);
+  dof_coords(a, a.dofs[j], cj, xj);
+  double ks, ms;
+  pair_sums(a, xi, ci, xj, cj, ks, ms);
   a.M[i * a.nc + j] = ms;
   a.S[i * a.nc + j] = ms + a.bdt2 * ks;
+}
+
+// The implicit rows of K, padded to W = ncomp (2p+1)^dim slots: slot (cj, o) of row i is
+// the DOF of component cj at node x_i + o, o in [-p, p]^dim (x fastest).  The column is
+// that DOF's global index, or -(its implicit index + 1) when it is implicit (the steps
+// take those values from a vector over the implicit DOFs).  A slot off the grid holds row
+// i's own column with the value 0.
+__global__ void imex_kc_assemble_kernel(ImexAsm a, int W, const int32_t* mark,
+                                        const int32_t* pos, int64_t ncn, int32_t* col,
+                                        double* val) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nc * W) return;
+  const int64_t i = t / W;
+  int w = (int)(t % W);
+  const int64_t gi = a.dofs[i];
+  int ci, xi[3];
+  dof_coords(a, gi, ci, xi);
+  const int side = 2 * a.p + 1;
+  int span = 1;
+  for (int k = 0; k < a.dim; ++k) span *= side;
+  const int cj = w / span;
+  w %= span;
+  int xj[3] = {0, 0, 0};
+  bool in = true;
+  for (int k = 0; k < a.dim; ++k) {
+    xj[k] = xi[k] + (w % side) - a.p;
+    w /= side;
+    if (xj[k] < 0 || xj[k] >= a.np[k]) in = false;
+  }
+  double ks = 0.0, ms;
+  int cc = ci;
+  int64_t nj = gi % a.nnodes;
+  if (in) {
+    pair_sums(a, xi, ci, xj, cj, ks, ms);
+    cc = cj;
+    nj = xj[0] + (int64_t)a.np[0] * (xj[1] + (int64_t)a.np[1] * xj[2]);
+  }
+  col[t] = mark[nj] ? (int32_t)(-(cc * ncn + pos[nj]) - 1) : (int32_t)(cc * a.nnodes + nj);
+  val[t] = ks;
 }
 
 // ---- blocked right-looking Cholesky, lower, row-major, in place ----
@@ -307,57 +358,182 @@ __global__ __launch_bounds__(256) void chol_solve_kernel(const double* L, const 
   for (int64_t i = t; i < n; i += 256) xr[i] = xs[i];
 }
 
-// x_r = A b_r for every right-hand side r, A dense symmetric n x n (row-major): one wave
-// per row, each row read once for up to 8 right-hand sides
-__global__ __launch_bounds__(256) void sym_gemv_kernel(const double* A, int64_t n, const double* b,
-                                                       double* x, int nrhs) {
+// ---- the inverses as the 32 x 32 tiles of their upper triangle ----
+
+constexpr int kTile = 32;
+
+// packed position of tile (I, J), I <= J, in a T x T tile grid (row I's tiles follow
+// those of rows 0 .. I-1)
+__host__ __device__ inline int64_t tile_index(int64_t I, int64_t J, int64_t T) {
+  return I * T - I * (I - 1) / 2 + (J - I);
+}
+
+// tile (I, J) at packed position q
+__device__ inline void tile_at(int64_t q, int64_t T, int64_t& I, int64_t& J) {
+  const double b = 2.0 * (double)T + 1.0;
+  int64_t i = (int64_t)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
+  i = max((int64_t)0, min(i, T - 1));
+  while (i > 0 && tile_index(i, i, T) > q) --i;
+  while (i + 1 < T && tile_index(i + 1, i + 1, T) <= q) ++i;
+  I = i;
+  J = i + (q - tile_index(i, i, T));
+}
+
+// P[tile (I, J)][r][c] = (A_ij + A_ji) / 2 at i = 32 I + r, j = 32 J + c (0 beyond n):
+// the inverse from column-wise solves is symmetric up to rounding; both halves are kept
+__global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T, double* P) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T * (T + 1) / 2 * kTile * kTile) return;
+  const int64_t q = t / (kTile * kTile);
+  const int e = (int)(t % (kTile * kTile));
+  int64_t I, J;
+  tile_at(q, T, I, J);
+  const int64_t i = I * kTile + e / kTile, j = J * kTile + e % kTile;
+  P[t] = (i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0;
+}
+
+// Partial products of x = A b over the packed upper tiles, one wave per tile (I, J): the
+// tile's rows against b's block J go to part[J][r][block I] and, for I < J, its columns
+// against b's block I to part[I][r][block J].  part is [T][nrhs][32 T]; every entry is
+// written by exactly one tile, and x_i is the sum of part[0 .. T-1][r][i].
+// Lane layout: columns 2 cp, 2 cp + 1 (cp = lane mod 16), rows rs + 4 k (k < 8,
+// rs = lane / 16): each load instruction reads four 256-byte tile rows.
+__global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, int64_t n, int64_t T,
+                                                        const double* b, int nrhs,
+                                                        double* part) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const double* row = A + i * n;
-  for (int r0 = 0; r0 < nrhs; r0 += 8) {
-    const int nr = min(8, nrhs - r0);
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t j = lane; j < n; j += 64) {
-      const double aij = row[j];
-  #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < nr) acc[q] += aij * b[(int64_t)(r0 + q) * n + j];
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= T * (T + 1) / 2) return;
+  const int cp = lane & 15, rs = lane >> 4;
+  int64_t I, J;
+  tile_at(q, T, I, J);
+  const double2* tile = (const double2*)(P + q * kTile * kTile);
+  double2 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = tile[(rs + 4 * k) * (kTile / 2) + cp];
+  const int64_t stride = T * kTile;
+  const bool off_diag = I < J;
+  const int64_t iB = I * kTile + (lane & 31), jB = J * kTile + (lane & 31);
+  const int b3 = (cp >> 3) & 1, b2 = (cp >> 2) & 1, b1 = (cp >> 1) & 1;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* br = b + (int64_t)r * n;
+    const double bI = iB < n ? br[iB] : 0.0, bJ = jB < n ? br[jB] : 0.0;
+    const double bj0 = __shfl(bJ, 2 * cp), bj1 = __shfl(bJ, 2 * cp + 1);
+    double s[8];
+    double cs0 = 0.0, cs1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      s[k] = v[k].x * bj0 + v[k].y * bj1;
+      const double bi = __shfl(bI, rs + 4 * k);
+      cs0 += v[k].x * bi;
+      cs1 += v[k].y * bi;
     }
-  #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      double v = acc[q];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (q < nr && lane == 0) x[(int64_t)(r0 + q) * n + i] = v;
+    // row sums over the 16 lanes of a row group: three halving exchanges leave each lane
+    // one row (k = 4 b3 + 2 b2 + b1), then one butterfly step
+    double t4[4], t2[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double send = b3 ? s[j] : s[j + 4];
+      const double keep = b3 ? s[j + 4] : s[j];
+      t4[j] = keep + __shfl_xor(send, 8);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double send = b2 ? t4[j] : t4[j + 2];
+      const double keep = b2 ? t4[j + 2] : t4[j];
+      t2[j] = keep + __shfl_xor(send, 4);
+    }
+    double w;
+    {
+      const double send = b1 ? t2[0] : t2[1];
+      const double keep = b1 ? t2[1] : t2[0];
+      w = keep + __shfl_xor(send, 2);
+    }
+    w += __shfl_xor(w, 1);
+    if ((cp & 1) == 0)
+      part[(J * nrhs + r) * stride + I * kTile + rs + 4 * (4 * b3 + 2 * b2 + b1)] = w;
+    if (off_diag) {
+      // column sums over the four row groups
+      cs0 += __shfl_xor(cs0, 16);
+      cs1 += __shfl_xor(cs1, 16);
+      cs0 += __shfl_xor(cs0, 32);
+      cs1 += __shfl_xor(cs1, 32);
+      if (lane < 16)
+        *(double2*)(part + (I * nrhs + r) * stride + J * kTile + 2 * cp) = make_double2(cs0, cs1);
     }
   }
 }
 
-// the same for one right-hand side: 16-byte loads of the row and of b, two rows per wave
-// pass in flight (n even: rows start 16-byte aligned)
-__global__ __launch_bounds__(256) void sym_gemv1_kernel(const double* A, int64_t n,
-                                                        const double* b, double* x) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const double2* row = (const double2*)(A + i * n);
-  const double2* bv = (const double2*)b;
-  const int64_t n2 = n / 2;
-  double acc0 = 0.0, acc1 = 0.0;
-  int64_t j = lane;
-  for (; j + 64 < n2; j += 128) {
-    const double2 a0 = row[j], a1 = row[j + 64];
-    const double2 b0 = bv[j], b1 = bv[j + 64];
-    acc0 += a0.x * b0.x + a0.y * b0.y;
-    acc1 += a1.x * b1.x + a1.y * b1.y;
+// the updates that consume x = A b on the implicit DOFs ([nrhs][nc] vectors)
+struct ImexUpd {
+  double* u;             // [nrhs][ndof]
+  double* d;             // [nrhs][ndof]
+  const int64_t* dofs;   // [nc]
+  double* uold;          // u_k; receives u_{k+1}
+  double* dold;          // d_k; receives d_{k+1} (consistent mass)
+  double* v;             // v_k -> v_{k+1} (IMEX)
+  double* a;             // a_k -> a_{k+1} (IMEX)
+  double* upred;         // IMEX predictor of this step; receives the next step's
+  int64_t ndof;
+  double dt;             // IMEX step
+  double w;              // consistent mass: dt^2, or dt^2 / 2 on a starting step
+};
+
+// IMEX corrector with a_{k+1} = x: v += dt ((1 - gamma) a_k + gamma a_{k+1}),
+// u = u_p + beta dt^2 a_{k+1}, d = u - u_k; u_{k+1} and the next step's predictor kept
+__device__ inline void imex_correct_at(const ImexUpd& e, int64_t t, int64_t r, int64_t i,
+                                       double an) {
+  const int64_t g = r * e.ndof + e.dofs[i];
+  const double vn = e.v[t] + e.dt * ((1.0 - kGamma) * e.a[t] + kGamma * an);
+  const double un = e.upred[t] + kBeta * e.dt * e.dt * an;
+  e.v[t] = vn;
+  e.u[g] = un;
+  e.d[g] = un - e.uold[t];
+  e.uold[t] = un;
+  e.a[t] = an;
+  e.upred[t] = un + e.dt * vn + (0.5 - kBeta) * e.dt * e.dt * an;
+}
+
+// consistent-mass central differences with a = x: d = d_k + w a, u = u_k + d
+__device__ inline void cons_fix_at(const ImexUpd& e, int64_t t, int64_t r, int64_t i,
+                                   double an) {
+  const int64_t g = r * e.ndof + e.dofs[i];
+  const double dn = e.dold[t] + e.w * an;
+  const double un = e.uold[t] + dn;
+  e.d[g] = dn;
+  e.u[g] = un;
+  e.dold[t] = dn;
+  e.uold[t] = un;
+}
+
+constexpr int kUpdImex = 1, kUpdCons = 2;
+
+// x[r][i] = sum over Y of part[Y][r][i], i < n, handed to the update MODE: 16 i per
+// workgroup, sixteen groups of lanes each summing every sixteenth Y, then the groups in a
+// fixed order
+template <int MODE>
+__global__ __launch_bounds__(256) void symp_reduce_kernel(const double* part, int64_t n,
+                                                          int64_t T, int nrhs, ImexUpd e) {
+  __shared__ double red[16][16];
+  const int il = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t nb = (n + 15) / 16;
+  const int64_t r = blockIdx.x / nb;
+  const int64_t i = (blockIdx.x % nb) * 16 + il;
+  const int64_t stride = T * kTile;
+  double s = 0.0;
+  if (i < n)
+    for (int64_t y = g; y < T; y += 16) s += part[(y * nrhs + r) * stride + i];
+  red[g][il] = s;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += red[q][il];
+    if (MODE == kUpdImex)
+      imex_correct_at(e, r * n + i, r, i, acc);
+    else
+      cons_fix_at(e, r * n + i, r, i, acc);
   }
-  if (j < n2) {
-    const double2 a0 = row[j], b0 = bv[j];
-    acc0 += a0.x * b0.x + a0.y * b0.y;
-  }
-  double v = acc0 + acc1;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if (lane == 0) x[i] = v;
 }
 
 __global__ void identity_kernel(double* A, int64_t n) {
@@ -375,84 +551,83 @@ __global__ void imex_gather_kernel(const double* u, const int64_t* dofs, int64_t
   out[t] = u[r * ndof + dofs[i]];
 }
 
-// u[c] = u_k + dt v + (1/2 - beta) dt^2 a
-__global__ void imex_predict_kernel(double* u, const int64_t* dofs, const double* uold,
-                                    const double* v, const double* a, int64_t nc, int64_t ndof,
-                                    int nrhs, double dt) {
+// the predictor u_p = u_k + dt v + (1/2 - beta) dt^2 a on the implicit DOFs
+__global__ void imex_predict_kernel(const double* uold, const double* v, const double* a,
+                                    int64_t nv, double dt, double* upred) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * nrhs) return;
-  const int64_t r = t / nc, i = t % nc;
-  u[r * ndof + dofs[i]] = uold[t] + dt * v[t] + (0.5 - kBeta) * dt * dt * a[t];
+  if (t >= nv) return;
+  upred[t] = uold[t] + dt * v[t] + (0.5 - kBeta) * dt * dt * a[t];
 }
 
-// b = F(t) - r on the implicit DOFs (F from the point sources of the call)
-__global__ void imex_rhs_kernel(const double* rk, const int64_t* dofs, const SourceDev* src,
-                                int64_t nc, int64_t ndof, int64_t nnodes, int nrhs, int dim, int p,
-                                int np0, int np1, double t, double* b) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nc * nrhs) return;
-  const int64_t r = e / nc, i = e % nc;
-  const int64_t g = dofs[i];
-  double f = 0.0;
-  if (src) {
-    const SourceDev& s = src[r];
-    const int comp = (int)(g / nnodes);
-    const int64_t node = g % nnodes;
-    const int x = (int)(node % np0), y = (int)((node / np0) % np1), z = (int)(node / ((int64_t)np0 * np1));
-    const int sx = x - s.cell[0] * p, sy = y - s.cell[1] * p, sz = (dim == 3) ? z - s.cell[2] * p : 0;
-    const int np1p = p + 1;
-    const int ns = (dim == 3) ? np1p * np1p * np1p : np1p * np1p;
-    if (sx >= 0 && sx <= p && sy >= 0 && sy <= p && sz >= 0 && sz <= p)
-      f = ricker(t, s.f0) * s.b[comp * ns + sx + np1p * (sy + np1p * sz)];
+// F(t) of right-hand side r at DOF g (the point source of the call, 0 without one)
+__device__ inline double source_at(const SourceDev* src, int64_t r, int64_t g, int64_t nnodes,
+                                   int dim, int p, int np0, int np1, double t) {
+  if (!src) return 0.0;
+  const SourceDev& s = src[r];
+  const int comp = (int)(g / nnodes);
+  const int64_t node = g % nnodes;
+  const int x = (int)(node % np0), y = (int)((node / np0) % np1),
+            z = (int)(node / ((int64_t)np0 * np1));
+  const int sx = x - s.cell[0] * p, sy = y - s.cell[1] * p, sz = (dim == 3) ? z - s.cell[2] * p : 0;
+  const int np1p = p + 1;
+  const int ns = (dim == 3) ? np1p * np1p * np1p : np1p * np1p;
+  if (sx >= 0 && sx <= p && sy >= 0 && sy <= p && sz >= 0 && sz <= p)
+    return ricker(t, s.f0) * s.b[comp * ns + sx + np1p * (sy + np1p * sz)];
+  return 0.0;
+}
+
+// b[r][i] = F(t) - (K^c u)_i on the implicit DOFs, u from uimp [nrhs][nc] on the implicit
+// DOFs and from u [nrhs][ndof] elsewhere: one wave per implicit row of the padded sparse
+// rows (lanes over the slots, a fixed butterfly for the sum)
+__global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
+    const int32_t* col, const double* val, int W, const double* u, const double* uimp,
+    const int64_t* dofs, const SourceDev* src, int64_t nc, int64_t ndof, int64_t nnodes,
+    int nrhs, int dim, int p, int np0, int np1, double t, double* b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nc) return;
+  const int32_t* ci = col + i * W;
+  const double* vi = val + i * W;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* ur = u + (int64_t)r * ndof;
+    const double* ui = uimp + (int64_t)r * nc;
+    double s = 0.0;
+    for (int w = lane; w < W; w += 64) {
+      const int32_t cw = ci[w];
+      s += vi[w] * (cw >= 0 ? ur[cw] : ui[-cw - 1]);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0)
+      b[(int64_t)r * nc + i] = source_at(src, r, dofs[i], nnodes, dim, p, np0, np1, t) - s;
   }
-  b[e] = f - rk[r * ndof + g];
 }
 
-// v += dt ((1 - gamma) a_k + gamma a_{k+1}); u[c] += beta dt^2 a_{k+1}; d[c] = u[c] - u_k;
-// a = a_{k+1}
-__global__ void imex_correct_kernel(double* u, double* d, const int64_t* dofs, const double* uold,
-                                    double* v, double* a, const double* anew, int64_t nc,
-                                    int64_t ndof, int nrhs, double dt) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * nrhs) return;
-  const int64_t r = t / nc, i = t % nc;
-  const int64_t g = r * ndof + dofs[i];
-  const double an = anew[t];
-  v[t] = v[t] + dt * ((1.0 - kGamma) * a[t] + kGamma * an);
-  const double un = u[g] + kBeta * dt * dt * an;
-  u[g] = un;
-  d[g] = un - uold[t];
-  a[t] = an;
+// part = the tile products of x = A b (A the packed upper tiles of the inverse of S or M^cc)
+static void symp_tiles(Ctx& c, const double* A, int64_t n, const double* b, int nrhs,
+                       double* part) {
+  const int64_t T = (n + kTile - 1) / kTile;
+  symp_tile_kernel<<<(unsigned)((T * (T + 1) / 2 + 3) / 4), 256, 0, c.stream>>>(A, n, T, b, nrhs,
+                                                                               part);
 }
 
-// consistent-mass central differences on the implicit DOFs: d = d_k + w a, u = u_k + d
-__global__ void cons_fix_kernel(double* u, double* d, const int64_t* dofs, const double* uold,
-                                const double* dold, const double* a, int64_t nc, int64_t ndof,
-                                int nrhs, double w) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nc * nrhs) return;
-  const int64_t r = t / nc, i = t % nc;
-  const int64_t g = r * ndof + dofs[i];
-  const double dn = dold[t] + w * a[t];
-  d[g] = dn;
-  u[g] = uold[t] + dn;
-}
-
-// x = A b for nrhs right-hand sides (A the dense inverse of S or M^cc)
-static void solve_product(Ctx& c, const double* A, int64_t n, const double* b, double* x,
-                          int nrhs) {
-  if (nrhs == 1 && n % 2 == 0)
-    sym_gemv1_kernel<<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(A, n, b, x);
-  else
-    sym_gemv_kernel<<<(unsigned)((n + 3) / 4), 256, 0, c.stream>>>(A, n, b, x, nrhs);
+// the reduction of the tile products, fused with the update that consumes x
+template <int MODE>
+static void symp_finish(Ctx& c, const double* part, int nrhs, const ImexUpd& e) {
+  const int64_t n = c.imex_nc, T = (n + kTile - 1) / kTile;
+  symp_reduce_kernel<MODE><<<(unsigned)(((n + 15) / 16) * nrhs), 256, 0, c.stream>>>(
+      part, n, T, nrhs, e);
 }
 
 void imex_free(Ctx& c) {
   for (void* p : {(void*)c.d_imex_dofs, (void*)c.d_imex_s, (void*)c.d_imex_m,
-                  (void*)c.d_imex_work, (void*)c.d_imex_flag})
+                  (void*)c.d_imex_sp, (void*)c.d_imex_mp, (void*)c.d_imex_kcol,
+                  (void*)c.d_imex_kval, (void*)c.d_imex_work, (void*)c.d_imex_flag})
     if (p) (void)hipFree(p);
   c.d_imex_dofs = nullptr;
-  c.d_imex_s = c.d_imex_m = c.d_imex_work = nullptr;
+  c.d_imex_s = c.d_imex_m = c.d_imex_sp = c.d_imex_mp = c.d_imex_work = nullptr;
+  c.d_imex_kcol = nullptr;
+  c.d_imex_kval = nullptr;
+  c.imex_kw = 0;
   c.d_imex_flag = nullptr;
   c.imex_work_bytes = 0;
   c.imex_nc = -1;
@@ -509,6 +684,10 @@ fcw_status imex_prepare(Ctx& c, double dt) {
               FCW_IMEX_MAX_NC);
     return fail(FCW_E_UNSUPPORTED);
   }
+  if (c.ndof > INT32_MAX) {
+    set_error("IMEX: %lld DOFs exceed the 32-bit column indices", (long long)c.ndof);
+    return fail(FCW_E_UNSUPPORTED);
+  }
   c.imex_ncn = ncn;
   if (nc > 0) {
     const size_t mat = (size_t)nc * nc * sizeof(double);
@@ -558,10 +737,36 @@ fcw_status imex_prepare(Ctx& c, double dt) {
       if (e != hipSuccess) return fail(hip_fail(e, "IMEX identity"));
       if ((st = imex_solve(c, f, nc, (int)nc, inv, inv))) return fail(st);
     }
+    // both inverses as packed upper tiles, and the implicit rows of K
+    const int64_t T = (nc + kTile - 1) / kTile;
+    const int64_t packed = T * (T + 1) / 2 * kTile * kTile;
+    int W = c.ncomp;
+    for (int k = 0; k < c.dim; ++k) W *= 2 * c.p + 1;
+    if (hipMalloc(&c.d_imex_sp, packed * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c.d_imex_mp, packed * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c.d_imex_kcol, (size_t)nc * W * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_kval, (size_t)nc * W * sizeof(double)) != hipSuccess) {
+      set_error("IMEX: allocation of the packed inverses (%lld DOFs) failed", (long long)nc);
+      return fail(FCW_E_NOMEM);
+    }
+    c.imex_kw = W;
+    pack_inverse_tiles_kernel<<<blocks_for(packed), 256, 0, c.stream>>>(
+        c.d_imex_s + 2 * (size_t)nc * nc, nc, T, c.d_imex_sp);
+    pack_inverse_tiles_kernel<<<blocks_for(packed), 256, 0, c.stream>>>(
+        c.d_imex_m + 2 * (size_t)nc * nc, nc, T, c.d_imex_mp);
+    imex_kc_assemble_kernel<<<blocks_for(nc * W), 256, 0, c.stream>>>(
+        a, W, mark, pos, ncn, c.d_imex_kcol, c.d_imex_kval);
+    {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return fail(hip_fail(e, "IMEX packing"));
+    }
     {
       const hipError_t e = hipStreamSynchronize(c.stream);
       if (e != hipSuccess) return fail(hip_fail(e, "IMEX inverse"));
     }
+    // the dense S, its factor and S^{-1} are not used by the steps
+    (void)hipFree(c.d_imex_s);
+    c.d_imex_s = nullptr;
   }
   (void)hipFree(mark);
   (void)hipFree(pos);
@@ -575,11 +780,12 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
                     double t0, double dt, int nsteps, int start, bool consistent) {
   const int64_t nc = c.imex_nc, ndof = c.ndof;
   const int64_t nv = nc * nrhs;
-  // work: r (nrhs x ndof), then b, anew, uold, dold (nrhs x nc each), each part starting
-  // on a 256-byte boundary
+  // work: b, u_k, d_k and the predictor on the implicit DOFs (nrhs x nc each), then the
+  // tile products of the inverse ([T][nrhs][32 T]), each part on a 256-byte boundary
   auto up32 = [](size_t v) { return (v + 31) / 32 * 32; };
-  const size_t nr = up32((size_t)nrhs * ndof), nvp = up32((size_t)nv);
-  const size_t need = (nr + 4 * nvp) * sizeof(double);
+  const int64_t T = (nc + kTile - 1) / kTile;
+  const size_t nvp = up32((size_t)nv), npart = (size_t)T * nrhs * T * kTile;
+  const size_t need = (4 * nvp + npart) * sizeof(double);
   if (c.imex_work_bytes < need) {
     if (c.d_imex_work) FCW_HIP(hipFree(c.d_imex_work));
     c.d_imex_work = nullptr;
@@ -587,58 +793,73 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     FCW_HIP(hipMalloc(&c.d_imex_work, need));
     c.imex_work_bytes = need;
   }
-  double* rk = c.d_imex_work;
-  double* bv = rk + nr;
-  double* an = bv + nvp;
-  double* uold = an + nvp;
+  double* bv = c.d_imex_work;
+  double* uold = bv + nvp;
+  double* dold = uold + nvp;
+  double* upred = dold + nvp;
+  double* part = upred + nvp;
+  const unsigned gw = (unsigned)((nc + 3) / 4);  // one wave per implicit row
   const unsigned gb = blocks_for(nv);
+  ImexUpd e{};
+  e.u = u;
+  e.d = d;
+  e.dofs = c.d_imex_dofs;
+  e.uold = uold;
+  e.dold = dold;
+  e.v = v_c;
+  e.a = a_c;
+  e.upred = upred;
+  e.ndof = ndof;
+  e.dt = dt;
+  auto kc_rhs = [&](const double* uimp, double t) {
+    imex_kc_rhs_kernel<<<gw, 256, 0, c.stream>>>(
+        c.d_imex_kcol, c.d_imex_kval, c.imex_kw, u, uimp, c.d_imex_dofs, c.d_src, nc, ndof,
+        c.nnodes, nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, bv);
+  };
   fcw_status st;
+  if (nc > 0) {
+    // the implicit DOFs' state at the call's start; the fused updates keep it afterwards
+    imex_gather_kernel<<<gb, 256, 0, c.stream>>>(u, c.d_imex_dofs, nc, ndof, nrhs, uold);
+    if (consistent)
+      imex_gather_kernel<<<gb, 256, 0, c.stream>>>(d, c.d_imex_dofs, nc, ndof, nrhs, dold);
+  }
   if (consistent) {
-    // central differences with the consistent cut-DOF mass (a = (M^cc)^{-1} (F - K u) on
-    // the implicit DOFs, the diagonal elsewhere)
-    double* dold = uold + nvp;
+    // central differences with the consistent cut-DOF mass: a = (M^cc)^{-1} (F - K^c u)
+    // on the implicit DOFs (from u_k, before the explicit step overwrites it), the
+    // lumped diagonal elsewhere
     for (int k = 0; k < nsteps; ++k) {
       const double t = t0 + k * dt;
       const int first = start && k == 0;
       if (nc > 0) {
-        imex_gather_kernel<<<gb, 256, 0, c.stream>>>(u, c.d_imex_dofs, nc, ndof, nrhs, uold);
-        imex_gather_kernel<<<gb, 256, 0, c.stream>>>(d, c.d_imex_dofs, nc, ndof, nrhs, dold);
-        if ((st = launch_apply(c, nrhs, u, rk))) return st;
-        imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes,
-                                                  nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, bv);
-        solve_product(c, c.d_imex_m + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
+        kc_rhs(uold, t);
+        symp_tiles(c, c.d_imex_mp, nc, bv, nrhs, part);
       }
       if ((st = run_steps(c, c.tile_choice, nrhs, u, d, c.d_ubuf, t, dt, 1, first))) return st;
-      if (nc > 0)
-        cons_fix_kernel<<<gb, 256, 0, c.stream>>>(u, d, c.d_imex_dofs, uold, dold, an, nc, ndof,
-                                                  nrhs, (first ? 0.5 : 1.0) * dt * dt);
+      if (nc > 0) {
+        e.w = (first ? 0.5 : 1.0) * dt * dt;
+        symp_finish<kUpdCons>(c, part, nrhs, e);
+      }
       FCW_HIP(hipGetLastError());
     }
     return FCW_OK;
   }
   if (start && nc > 0) {
     // a_0 from M^cc a_0 = F_0 - (K u_0) on the implicit DOFs
-    if ((st = launch_apply(c, nrhs, u, rk))) return st;
-    imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes, nrhs,
-                                              c.dim, c.p, c.npts[0], c.npts[1], t0, bv);
+    kc_rhs(uold, t0);
     if ((st = imex_solve(c, c.d_imex_m, nc, nrhs, bv, a_c))) return st;
   }
+  // the first predictor; each corrector leaves the next one
+  if (nc > 0) imex_predict_kernel<<<gb, 256, 0, c.stream>>>(uold, v_c, a_c, nv, dt, upred);
   for (int k = 0; k < nsteps; ++k) {
     const double t = t0 + k * dt;
-    if (nc > 0)
-      imex_gather_kernel<<<gb, 256, 0, c.stream>>>(u, c.d_imex_dofs, nc, ndof, nrhs, uold);
     // explicit DOFs: one central-difference step of the explicit solver
     if ((st = run_steps(c, c.tile_choice, nrhs, u, d, c.d_ubuf, t, dt, 1, (start && k == 0))))
       return st;
     if (nc == 0) continue;
-    imex_predict_kernel<<<gb, 256, 0, c.stream>>>(u, c.d_imex_dofs, uold, v_c, a_c, nc, ndof,
-                                                  nrhs, dt);
-    if ((st = launch_apply(c, nrhs, u, rk))) return st;
-    imex_rhs_kernel<<<gb, 256, 0, c.stream>>>(rk, c.d_imex_dofs, c.d_src, nc, ndof, c.nnodes, nrhs,
-                                              c.dim, c.p, c.npts[0], c.npts[1], t + dt, bv);
-    solve_product(c, c.d_imex_s + 2 * (size_t)nc * nc, nc, bv, an, nrhs);
-    imex_correct_kernel<<<gb, 256, 0, c.stream>>>(u, d, c.d_imex_dofs, uold, v_c, a_c, an, nc,
-                                                  ndof, nrhs, dt);
+    // K^c u_p: the explicit DOFs' new values with the predictor on the implicit DOFs
+    kc_rhs(upred, t + dt);
+    symp_tiles(c, c.d_imex_sp, nc, bv, nrhs, part);
+    symp_finish<kUpdImex>(c, part, nrhs, e);
     FCW_HIP(hipGetLastError());
   }
   return FCW_OK;
