@@ -179,3 +179,36 @@ def test_displacement_form_equals_predictor_corrector(mode):
     u, v, a = _newmark_predictor_corrector(disc, (c, d), dt, 60, src)
     assert np.linalg.norm(got["u"] - u) <= 1e-9 * np.linalg.norm(u)
     assert np.linalg.norm(got["v_c"] - v) <= 1e-8 * np.linalg.norm(v)
+
+
+def test_implicit_set_of_the_3d_imex_workload_exceeds_the_dense_limit():
+    """Size of the implicit set (every component of the nodes of cut cells, Sec. 2.5) of the
+    3-D elastic IMEX workload (64^3 cells, p = 3, the spherical-pore field): counted from the
+    oracle's cell classes, it is far above the dense limit of the device's IMEX set-up, so
+    that workload needs a sparse factorisation of S."""
+    import re
+    from pathlib import Path
+
+    import workloads
+    from oracle import geometry
+    from oracle.problem import Problem
+    cfg = workloads.config("c4")
+    prob = Problem.from_config(cfg)
+    cls = geometry.classify_cells(prob)
+    n = prob.ncells
+    cut = np.flatnonzero(cls == geometry.CUT)
+    assert cut.size > 0
+    cx, cy, cz = cut % n[0], (cut // n[0]) % n[1], cut // (n[0] * n[1])
+    npts = [k * prob.p + 1 for k in n]
+    mark = np.zeros(npts[::-1], dtype=bool)  # [z][y][x]
+    for i in range(prob.p + 1):
+        for j in range(prob.p + 1):
+            for k in range(prob.p + 1):
+                mark[cz * prob.p + k, cy * prob.p + j, cx * prob.p + i] = True
+    n_c = 3 * int(mark.sum())
+    header = (Path(__file__).resolve().parents[1] / "include" / "fcw.h").read_text()
+    limit = int(re.search(r"#define FCW_IMEX_MAX_NC (\d+)", header).group(1))
+    # the all-void cut cells the device drops can only shrink the set by the nodes that no
+    # other cut cell shares; the count stays orders of magnitude above the limit
+    assert n_c > 100 * limit, n_c
+    print(f"cut cells {cut.size}, implicit DOFs {n_c}")
