@@ -32,7 +32,8 @@ the FP32 and FP64 device states after the same steps from rest at that dt are co
 the oracle's (`rel_l2_vs_oracle`).
 
 Further legs in the same JSON line: `c3` (3-D elastic 96^3 p=2: FP32, split BF16, FP64),
-`imex` (the semi-explicit scheme of Alg. imex, FP64, on the same void field at 64^2 p=3),
+`imex` (the semi-explicit scheme of Alg. imex, FP64, on the same void field at 64^2 p=3
+and at its full size),
 `iga` (IGA-FCM with B-splines and row-sum lumping on the 512^2 void field, p=4, FP32) and
 `serving` (p50/p99 latency of a seeded request stream).
 """
@@ -284,17 +285,13 @@ def bench_c3(steps, warmup, with_fp64):
     return out
 
 
-def bench_imex(steps, warmup):
-    """Semi-explicit (IMEX) scheme, FP64: the C2 void field at 64 x 64 cells, p = 3.
-    The implicit set (nodes of cut cells) has about 5.8 k DOFs; S and M^cc are dense and
-    factored once on the device."""
+def _imex_leg(cfg, steps, warmup):
+    """IMEX, explicit and consistent-mass steps of one FP64 problem, each timed over
+    ``steps`` steps after ``warmup``."""
     import torch
-    import workloads
     from paper_2501_19013_amd import fcw
     from paper_2501_19013_amd.solver import Solver
-    cc, rr = workloads.random_circles(seed=2)
-    cfg = workloads._base(2, (64, 64), 3, cc, rr, nsteps=steps)
-    src = cfg["sources"]
+    src = cfg["sources"][:1]
     s = Solver(cfg, precision="fp64", device="cuda:0")
     dt = 0.9 * s.critical_dt(max_iter=4000, rtol=1e-7)
     torch.cuda.synchronize()
@@ -302,6 +299,7 @@ def bench_imex(steps, warmup):
     nc = fcw.imex_prepare(s.ctx, dt)
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t0
+    lay = fcw.imex_layout(s.ctx)
     u, d = s.zeros(1), s.zeros(1)
     v = torch.zeros(1, max(nc, 1), dtype=torch.float64, device="cuda:0")
     a = torch.zeros_like(v)
@@ -335,15 +333,32 @@ def bench_imex(steps, warmup):
     torch.cuda.synchronize()
     ms_con = e0.elapsed_time(e1)
     s.close()
-    return dict(workload="2-D scalar, the c2 void field at 64x64 cells, p=3 GLL, FP64, IMEX "
-                         "(Alg. imex, beta=1/4, gamma=1/2), dense FP64 Cholesky of S and M^cc, "
-                         "S^-1 as packed upper tiles",
-                value=active * steps / (ms * 1e-3), unit="DOF-updates/s", ms_per_step=ms / steps,
-                steps=steps, n_implicit=nc, active_dof=active, prepare_s=t_prep, dt=dt,
+    return dict(value=active * steps / (ms * 1e-3), unit="DOF-updates/s", ms_per_step=ms / steps,
+                steps=steps, n_implicit=nc, n_blocks=lay["n_blocks"],
+                largest_block=lay["largest"], active_dof=active, prepare_s=t_prep, dt=dt,
                 explicit_ms_per_step=ms_exp / steps,
                 consistent_mass_cdm_ms_per_step=ms_con / steps,
-                # S^-1 as the packed 32 x 32 tiles of its upper triangle
-                solve_bytes_per_step=8 * 1024 * ((nc + 31) // 32) * ((nc + 31) // 32 + 1) // 2)
+                # the packed upper tiles of the blocks of S^-1, read once per step
+                solve_bytes_per_step=lay["solve_bytes"])
+
+
+def bench_imex(steps, warmup, full_steps):
+    """Semi-explicit (IMEX) scheme, FP64: the C2 void field at 64 x 64 cells, p = 3 (about
+    5.7 k implicit DOFs), and at its full size, 512 x 512 cells, p = 4 (about 80 k implicit
+    DOFs).  S and M^cc are block diagonal over the blocks of coupled implicit DOFs; each
+    block is dense, factored and inverted once on the device."""
+    import workloads
+    cc, rr = workloads.random_circles(seed=2)
+    cfg = workloads._base(2, (64, 64), 3, cc, rr, nsteps=steps)
+    res = _imex_leg(cfg, steps, warmup)
+    res["workload"] = ("2-D scalar, the c2 void field at 64x64 cells, p=3 GLL, FP64, IMEX "
+                       "(Alg. imex, beta=1/4, gamma=1/2), S and M^cc block diagonal: dense "
+                       "FP64 Cholesky per block, S^-1 as packed upper tiles")
+    if full_steps > 0:
+        full = _imex_leg(workloads.config("c2"), full_steps, warmup)
+        full["workload"] = "the same scheme on the c2 void field at full size, 512x512 cells, p=4"
+        res["c2_full"] = full
+    return res
 
 
 def bench_iga(steps, warmup):
@@ -454,6 +469,8 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D elastic workload")
     ap.add_argument("--imex-steps", type=int, default=200,
                     help="steps of the IMEX leg (0 skips it)")
+    ap.add_argument("--imex-full-steps", type=int, default=100,
+                    help="steps of the IMEX leg at the full c2 size (0 skips it)")
     ap.add_argument("--iga-steps", type=int, default=500, help="steps of the IGA-FCM leg (0: skip)")
     ap.add_argument("--c3-steps", type=int, default=1000)
     ap.add_argument("--c3-warmup", type=int, default=10)
@@ -515,9 +532,16 @@ def main():
     if not args.no_c3:
         res["c3"] = bench_c3(args.c3_steps, args.c3_warmup, not args.no_fp64)
     if args.imex_steps > 0:
-        res["imex"] = bench_imex(args.imex_steps, 5)
+        res["imex"] = bench_imex(args.imex_steps, 5, args.imex_full_steps)
         print(f"[bench] imex: {res['imex']['ms_per_step']:.3f} ms/step, "
-              f"{res['imex']['n_implicit']} implicit DOFs", file=sys.stderr, flush=True)
+              f"{res['imex']['n_implicit']} implicit DOFs in {res['imex']['n_blocks']} blocks",
+              file=sys.stderr, flush=True)
+        if "c2_full" in res["imex"]:
+            f = res["imex"]["c2_full"]
+            print(f"[bench] imex c2 full size: {f['ms_per_step']:.3f} ms/step, "
+                  f"{f['n_implicit']} implicit DOFs in {f['n_blocks']} blocks (largest "
+                  f"{f['largest_block']}), set-up {f['prepare_s']:.1f} s, explicit "
+                  f"{f['explicit_ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if args.iga_steps > 0:
         res["iga"] = bench_iga(args.iga_steps, 10)
         print(f"[bench] iga: {res['iga']['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,

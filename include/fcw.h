@@ -263,23 +263,34 @@ fcw_status fcw_set_stream(fcw_ctx* ctx, void* stream);
 fcw_status fcw_kernel_times(fcw_ctx* ctx, int32_t nrhs, int32_t nsteps, double* main_us,
                             double* cut_us);
 
-/* Largest implicit set of the IMEX step (its matrices are held dense). */
+/* Largest block of coupled implicit DOFs of the IMEX step (each block's matrices are
+ * held dense; the implicit set as a whole has no such limit). */
 #define FCW_IMEX_MAX_NC 16384
 
 /* Set up the semi-explicit (IMEX) scheme of Sec. 2.5 (Alg. imex) for step size dt:
  * the implicit DOFs are those of the nodes of the cut cells (every component), the
  * rest of the active DOFs are explicit.  Assembles M^cc (the consistent cut-cell masses
  * M^o_e without stabilisation plus the GLL diagonals of the uncut cells on implicit
- * DOFs) and S = M^cc + dt^2/4 K^cc, dense, and factors both by Cholesky on the device
- * (FP64); the steps use S^{-1} and (M^cc)^{-1} (kept as the packed 32 x 32 tiles of their
- * upper triangles) and the rows of K at the implicit DOFs (kept as padded sparse rows).
+ * DOFs) and S = M^cc + dt^2/4 K^cc.  Both are block diagonal over the blocks of implicit
+ * nodes linked through shared active cells; each block is assembled dense and factored
+ * by Cholesky on the device (FP64).  The steps use the blocks of S^{-1} and (M^cc)^{-1}
+ * (kept as the packed 32 x 32 tiles of their upper triangles) and the rows of K at the
+ * implicit DOFs (kept as padded sparse rows).
  * *n_c receives the number of implicit DOFs, whose global indices
  * FCW_ARR_IMEX_DOFS exports (ascending: component-major, then node).
- * FP64 contexts only (FCW_E_UNSUPPORTED otherwise, when n_c > FCW_IMEX_MAX_NC and when
- * ndof >= 2^31);
+ * FP64 contexts only (FCW_E_UNSUPPORTED otherwise, when a block holds more than
+ * FCW_IMEX_MAX_NC DOFs and when ndof >= 2^31);
  * FCW_E_NOCONV if a matrix is not positive definite.  Requires the stabilised state.
  * fcw_step_imex calls it itself when dt changes. */
 fcw_status fcw_imex_prepare(fcw_ctx* ctx, double dt, int64_t* n_c);
+
+/* Layout of the prepared implicit set (Sec. 2.5: S and M^cc are block diagonal over the
+ * blocks of implicit nodes linked through shared active cells): *n_blocks blocks, the
+ * largest with *largest DOFs, and *solve_bytes, the bytes of the packed upper tiles of
+ * the blocks of S^{-1} (the same for (M^cc)^{-1}): what one step's implicit solve reads
+ * per call.  Any output pointer may be NULL.  FCW_E_ARG before fcw_imex_prepare. */
+fcw_status fcw_imex_layout(fcw_ctx* ctx, int32_t* n_blocks, int64_t* largest,
+                           int64_t* solve_bytes);
 
 /* nsteps semi-explicit steps (Alg. imex, beta = 1/4, gamma = 1/2): central differences on
  * the explicit DOFs (the step of fcw_step_explicit, in increment form), the trapezoidal

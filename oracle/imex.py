@@ -24,6 +24,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from .problem import assembled_K, load_vector, ricker
 
@@ -70,11 +71,14 @@ def mass_matrices(disc, c, d):
     return full_diag[d], M[c][:, c]
 
 
-def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None, u0=None):
+def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None, u0=None,
+         sparse=False):
     """Run ``nsteps`` steps of the IMEX scheme of Sec. 2.5 from u0 (default 0) at rest.
     ``split`` overrides the partition (c, d) (a test reduces the scheme to one of its two
     parts with it).  Returns the final u (all DOFs), the implicit DOFs' velocity and
-    acceleration, and the split.
+    acceleration, and the split.  The solves with S and M^cc use a dense Cholesky factor,
+    or with ``sparse`` a sparse LU factor (SuperLU) of the same matrices, for implicit
+    sets too large for a dense one.
 
     The explicit DOFs take eq. cdm.  The implicit DOFs take the Newmark relations
         u_{k+1} = u_k + dt v_k + dt^2 ((1/2 - beta) a_k + beta a_{k+1}),
@@ -104,11 +108,21 @@ def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None,
     v_c = np.zeros(len(c))
     a_c = np.zeros(len(c))
     bdt2 = beta * dt * dt
-    if len(c):
+    if len(c) and sparse:
+        Mc = (0.5 * (Mcc + Mcc.T)).tocsc()
+        S = (Mc + bdt2 * Kcc).tocsc()
+        S_lu = spla.splu((0.5 * (S + S.T)).tocsc())
+        solve_S = S_lu.solve
+        # initial acceleration from the equation of motion at t_0
+        a_c = spla.splu(Mc).solve(force(0)[c] - K[c] @ u)
+    elif len(c):
         Mc = Mcc.toarray()
         Mc = 0.5 * (Mc + Mc.T)
         S = Mc + bdt2 * Kcc.toarray()
         S_f = sla.cho_factor(0.5 * (S + S.T), lower=True)
+
+        def solve_S(rhs):
+            return sla.cho_solve(S_f, rhs)
         # initial acceleration from the equation of motion at t_0
         a_c = sla.cho_solve(sla.cho_factor(Mc, lower=True), force(0)[c] - K[c] @ u)
     inv_dd = np.where(m_dd > 0, 1.0 / np.where(m_dd > 0, m_dd, 1.0), 0.0)
@@ -127,7 +141,7 @@ def imex(disc, dt, nsteps, sources=(), beta=0.25, gamma=0.5, t0=0.0, split=None,
         if len(c):
             w = u[c] + dt * v_c + (0.5 - beta) * dt * dt * a_c
             rhs = Mc @ w + bdt2 * (force(k + 1)[c] - Kcd @ ud_new)
-            uc_new = sla.cho_solve(S_f, rhs)
+            uc_new = solve_S(rhs)
             a_new = (uc_new - w) / bdt2
             v_c = v_c + dt * ((1.0 - gamma) * a_c + gamma * a_new)
             a_c = a_new

@@ -824,6 +824,21 @@ fcw_status fcw_imex_prepare(fcw_ctx* c, double dt, int64_t* n_c) {
   return FCW_OK;
 }
 
+fcw_status fcw_imex_layout(fcw_ctx* c, int32_t* n_blocks, int64_t* largest,
+                           int64_t* solve_bytes) {
+  g_err.clear();
+  fcw_status st = check_ctx(c, 2);
+  if (st) return st;
+  if (c->imex_nc < 0) {
+    set_error("fcw_imex_prepare has not run");
+    return FCW_E_ARG;
+  }
+  if (n_blocks) *n_blocks = c->imex_nblk;
+  if (largest) *largest = c->imex_largest;
+  if (solve_bytes) *solve_bytes = c->imex_ntiles * 32 * 32 * (int64_t)sizeof(double);
+  return FCW_OK;
+}
+
 fcw_status fcw_step_imex(fcw_ctx* c, int32_t nrhs, void* u, void* d, void* v_c, void* a_c,
                          const fcw_source* src, double t0, double dt, int32_t nsteps,
                          int32_t start) {

@@ -141,13 +141,24 @@ struct Ctx {
   int64_t imex_ncn = 0;            // implicit nodes
   double imex_dt = 0.0;
   int64_t* d_imex_dofs = nullptr;  // [imex_nc] global DOF of each implicit DOF
-  double* d_imex_s = nullptr;      // [3][imex_nc^2] L of S (row-major, lower), L^T, S^{-1}
-  double* d_imex_m = nullptr;      // [3][imex_nc^2] the same for M^cc
-  double* d_imex_sp = nullptr;     // S^{-1} as its upper 64 x 64 tiles, packed row by row
+  double* d_imex_s = nullptr;      // set-up only: [3][n_b^2] L of S (row-major, lower), L^T, S^{-1}
+  double* d_imex_m = nullptr;      // set-up only: the same for M^cc
+  double* d_imex_sp = nullptr;     // S^{-1} as its upper 32 x 32 tiles, block by block
   double* d_imex_mp = nullptr;     // (M^cc)^{-1}, the same
   int32_t* d_imex_kcol = nullptr;  // [imex_nc][imex_kw] the implicit rows of K: columns
   double* d_imex_kval = nullptr;   // [imex_nc][imex_kw] and values (0 in padding slots)
   int imex_kw = 0;
+  // the implicit set splits into blocks (connected through shared cells) that S and M^cc
+  // never couple; b and x of the tiled products run in block order
+  int32_t imex_nblk = 0;           // blocks
+  int64_t imex_largest = 0;        // DOFs of the largest block
+  int64_t imex_ntiles = 0;         // packed tiles over all blocks
+  int64_t imex_part = 0;           // tile-product partials per right-hand side
+  int32_t* d_imex_cpos = nullptr;     // [imex_nc] block-order position of each implicit DOF
+  int32_t* d_imex_members = nullptr;  // [imex_nc] implicit DOF at each block-order position
+  int32_t* d_imex_pblk = nullptr;     // [imex_nc] block of each block-order position
+  void* d_imex_blocks = nullptr;      // [imex_nblk] block descriptors
+  void* d_imex_tiles = nullptr;       // [imex_ntiles] (I, J, block) of each packed tile
   double* d_imex_work = nullptr;   // per-call work vectors
   size_t imex_work_bytes = 0;
   int32_t* d_imex_flag = nullptr;  // [1] non-positive pivot seen

@@ -24,10 +24,13 @@
 // consistent-mass spectral cell method, eq. cdm with M = diag(M^dd, M^cc)): per step
 // a = (M^cc)^{-1} (F_k - K^c u_k) on the implicit DOFs, the lumped step elsewhere.
 //
-// S and M^cc are assembled dense (entry by entry from the cells around the two nodes,
-// in a fixed order) and factored on the device by a blocked right-looking Cholesky.
-// The dense form bounds the implicit set (FCW_IMEX_MAX_NC); a sparse factorisation is
-// what large cut fractions would need.
+// The implicit set splits into blocks: implicit nodes linked through shared active
+// cells (in a void field, the cut cells around one void or one cluster of voids).  S and
+// M^cc have no entry between blocks, so each block is assembled dense (entry by entry
+// from the cells around the two nodes, in a fixed order), factored on the device by a
+// blocked right-looking Cholesky and inverted on its own.  The dense form bounds a block
+// (FCW_IMEX_MAX_NC), not the whole set; one block that large (a percolating pore space)
+// would need a sparse factorisation.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -379,9 +382,12 @@ __device__ inline void tile_at(int64_t q, int64_t T, int64_t& I, int64_t& J) {
   J = i + (q - tile_index(i, i, T));
 }
 
-// P[tile (I, J)][r][c] = (A_ij + A_ji) / 2 at i = 32 I + r, j = 32 J + c (0 beyond n):
-// the inverse from column-wise solves is symmetric up to rounding; both halves are kept
-__global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T, double* P) {
+// P[tile (I, J)][r][c] = (A_ij + A_ji) / 2 at i = 32 I + r, j = 32 J + c (0 beyond n),
+// for the T (T + 1) / 2 upper tiles of one block in packed order, and the tiles'
+// descriptors (I, J, block): the inverse from column-wise solves is symmetric up to
+// rounding; both halves are kept
+__global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T, double* P,
+                                          int4* tiles, int32_t blk) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T * (T + 1) / 2 * kTile * kTile) return;
   const int64_t q = t / (kTile * kTile);
@@ -390,33 +396,46 @@ __global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T,
   tile_at(q, T, I, J);
   const int64_t i = I * kTile + e / kTile, j = J * kTile + e % kTile;
   P[t] = (i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0;
+  if (tiles && e == 0) tiles[q] = make_int4((int)I, (int)J, blk, 0);
 }
 
-// Partial products of x = A b over the packed upper tiles, one wave per tile (I, J): the
-// tile's rows against b's block J go to part[J][r][block I] and, for I < J, its columns
-// against b's block I to part[I][r][block J].  part is [T][nrhs][32 T]; every entry is
-// written by exactly one tile, and x_i is the sum of part[0 .. T-1][r][i].
+// one block of the implicit set: its n DOFs sit at block-order positions moff .. moff+n-1,
+// its T = ceil(n / 32) tile rows' partial products at part + nrhs * poff
+struct ImexBlock {
+  int64_t moff, poff;
+  int32_t n, T;
+};
+
+// Partial products of x = A b over the packed upper tiles, one wave per tile (I, J) of a
+// block: the tile's rows against b's block J go to part[J][r][block I] and, for I < J, its
+// columns against b's block I to part[I][r][block J], where part is the block's
+// [T][nrhs][32 T] array; every entry is written by exactly one tile, and x_i is the sum of
+// part[0 .. T-1][r][i].  b and x are in block order ([nrhs][nc]).
 // Lane layout: columns 2 cp, 2 cp + 1 (cp = lane mod 16), rows rs + 4 k (k < 8,
 // rs = lane / 16): each load instruction reads four 256-byte tile rows.
-__global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, int64_t n, int64_t T,
-                                                        const double* b, int nrhs,
+__global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, const int4* tiles,
+                                                        int64_t ntiles, const ImexBlock* blocks,
+                                                        const double* b, int64_t nc, int nrhs,
                                                         double* part) {
   const int lane = threadIdx.x & 63;
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= T * (T + 1) / 2) return;
+  if (q >= ntiles) return;
   const int cp = lane & 15, rs = lane >> 4;
-  int64_t I, J;
-  tile_at(q, T, I, J);
+  const int4 td = tiles[q];
+  const int64_t I = td.x, J = td.y;
+  const ImexBlock bk = blocks[td.z];
+  const int64_t n = bk.n;
   const double2* tile = (const double2*)(P + q * kTile * kTile);
   double2 v[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = tile[(rs + 4 * k) * (kTile / 2) + cp];
-  const int64_t stride = T * kTile;
+  const int64_t stride = (int64_t)bk.T * kTile;
+  double* pb = part + nrhs * bk.poff;
   const bool off_diag = I < J;
   const int64_t iB = I * kTile + (lane & 31), jB = J * kTile + (lane & 31);
   const int b3 = (cp >> 3) & 1, b2 = (cp >> 2) & 1, b1 = (cp >> 1) & 1;
   for (int r = 0; r < nrhs; ++r) {
-    const double* br = b + (int64_t)r * n;
+    const double* br = b + (int64_t)r * nc + bk.moff;
     const double bI = iB < n ? br[iB] : 0.0, bJ = jB < n ? br[jB] : 0.0;
     const double bj0 = __shfl(bJ, 2 * cp), bj1 = __shfl(bJ, 2 * cp + 1);
     double s[8];
@@ -451,7 +470,7 @@ __global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, int64_t
     }
     w += __shfl_xor(w, 1);
     if ((cp & 1) == 0)
-      part[(J * nrhs + r) * stride + I * kTile + rs + 4 * (4 * b3 + 2 * b2 + b1)] = w;
+      pb[(J * nrhs + r) * stride + I * kTile + rs + 4 * (4 * b3 + 2 * b2 + b1)] = w;
     if (off_diag) {
       // column sums over the four row groups
       cs0 += __shfl_xor(cs0, 16);
@@ -459,7 +478,7 @@ __global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, int64_t
       cs0 += __shfl_xor(cs0, 32);
       cs1 += __shfl_xor(cs1, 32);
       if (lane < 16)
-        *(double2*)(part + (I * nrhs + r) * stride + J * kTile + 2 * cp) = make_double2(cs0, cs1);
+        *(double2*)(pb + (I * nrhs + r) * stride + J * kTile + 2 * cp) = make_double2(cs0, cs1);
     }
   }
 }
@@ -506,33 +525,43 @@ __device__ inline void cons_fix_at(const ImexUpd& e, int64_t t, int64_t r, int64
   e.uold[t] = un;
 }
 
-constexpr int kUpdImex = 1, kUpdCons = 2;
+constexpr int kUpdStore = 0, kUpdImex = 1, kUpdCons = 2;
 
-// x[r][i] = sum over Y of part[Y][r][i], i < n, handed to the update MODE: 16 i per
+// x at block-order position m: the sum over Y of its block's part[Y][r][m - moff], handed
+// to the update MODE at the implicit DOF members[m] (kUpdStore: a = x).  16 positions per
 // workgroup, sixteen groups of lanes each summing every sixteenth Y, then the groups in a
-// fixed order
+// fixed order.
 template <int MODE>
-__global__ __launch_bounds__(256) void symp_reduce_kernel(const double* part, int64_t n,
-                                                          int64_t T, int nrhs, ImexUpd e) {
+__global__ __launch_bounds__(256) void symp_reduce_kernel(const double* part,
+                                                          const int32_t* pblk,
+                                                          const int32_t* members,
+                                                          const ImexBlock* blocks, int64_t nc,
+                                                          int nrhs, ImexUpd e) {
   __shared__ double red[16][16];
   const int il = threadIdx.x & 15, g = threadIdx.x >> 4;
-  const int64_t nb = (n + 15) / 16;
+  const int64_t nb = (nc + 15) / 16;
   const int64_t r = blockIdx.x / nb;
-  const int64_t i = (blockIdx.x % nb) * 16 + il;
-  const int64_t stride = T * kTile;
+  const int64_t m = (blockIdx.x % nb) * 16 + il;
   double s = 0.0;
-  if (i < n)
-    for (int64_t y = g; y < T; y += 16) s += part[(y * nrhs + r) * stride + i];
+  if (m < nc) {
+    const ImexBlock bk = blocks[pblk[m]];
+    const int64_t stride = (int64_t)bk.T * kTile;
+    const double* p = part + nrhs * bk.poff + r * stride + (m - bk.moff);
+    for (int64_t y = g; y < bk.T; y += 16) s += p[y * nrhs * stride];
+  }
   red[g][il] = s;
   __syncthreads();
-  if (g == 0 && i < n) {
+  if (g == 0 && m < nc) {
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc += red[q][il];
-    if (MODE == kUpdImex)
-      imex_correct_at(e, r * n + i, r, i, acc);
+    const int64_t i = members[m], t = r * nc + i;
+    if (MODE == kUpdStore)
+      e.a[t] = acc;
+    else if (MODE == kUpdImex)
+      imex_correct_at(e, t, r, i, acc);
     else
-      cons_fix_at(e, r * n + i, r, i, acc);
+      cons_fix_at(e, t, r, i, acc);
   }
 }
 
@@ -576,13 +605,14 @@ __device__ inline double source_at(const SourceDev* src, int64_t r, int64_t g, i
   return 0.0;
 }
 
-// b[r][i] = F(t) - (K^c u)_i on the implicit DOFs, u from uimp [nrhs][nc] on the implicit
-// DOFs and from u [nrhs][ndof] elsewhere: one wave per implicit row of the padded sparse
-// rows (lanes over the slots, a fixed butterfly for the sum)
+// b = F(t) - K^c u on the implicit DOFs (written in block order: b[r][cpos[i]]), u from
+// uimp [nrhs][nc] on the implicit DOFs and from u [nrhs][ndof] elsewhere: one wave per
+// implicit row of the padded sparse rows (lanes over the slots, a fixed butterfly for the
+// sum)
 __global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
     const int32_t* col, const double* val, int W, const double* u, const double* uimp,
     const int64_t* dofs, const SourceDev* src, int64_t nc, int64_t ndof, int64_t nnodes,
-    int nrhs, int dim, int p, int np0, int np1, double t, double* b) {
+    int nrhs, int dim, int p, int np0, int np1, double t, const int32_t* cpos, double* b) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= nc) return;
@@ -598,36 +628,41 @@ __global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
     }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (lane == 0)
-      b[(int64_t)r * nc + i] = source_at(src, r, dofs[i], nnodes, dim, p, np0, np1, t) - s;
+      b[(int64_t)r * nc + cpos[i]] = source_at(src, r, dofs[i], nnodes, dim, p, np0, np1, t) - s;
   }
 }
 
-// part = the tile products of x = A b (A the packed upper tiles of the inverse of S or M^cc)
-static void symp_tiles(Ctx& c, const double* A, int64_t n, const double* b, int nrhs,
-                       double* part) {
-  const int64_t T = (n + kTile - 1) / kTile;
-  symp_tile_kernel<<<(unsigned)((T * (T + 1) / 2 + 3) / 4), 256, 0, c.stream>>>(A, n, T, b, nrhs,
-                                                                               part);
+// part = the tile products of x = A b (A the packed upper tiles of the blocks of the
+// inverse of S or M^cc; b in block order)
+static void symp_tiles(Ctx& c, const double* A, const double* b, int nrhs, double* part) {
+  symp_tile_kernel<<<(unsigned)((c.imex_ntiles + 3) / 4), 256, 0, c.stream>>>(
+      A, (const int4*)c.d_imex_tiles, c.imex_ntiles, (const ImexBlock*)c.d_imex_blocks, b,
+      c.imex_nc, nrhs, part);
 }
 
 // the reduction of the tile products, fused with the update that consumes x
 template <int MODE>
 static void symp_finish(Ctx& c, const double* part, int nrhs, const ImexUpd& e) {
-  const int64_t n = c.imex_nc, T = (n + kTile - 1) / kTile;
+  const int64_t n = c.imex_nc;
   symp_reduce_kernel<MODE><<<(unsigned)(((n + 15) / 16) * nrhs), 256, 0, c.stream>>>(
-      part, n, T, nrhs, e);
+      part, c.d_imex_pblk, c.d_imex_members, (const ImexBlock*)c.d_imex_blocks, n, nrhs, e);
 }
 
 void imex_free(Ctx& c) {
   for (void* p : {(void*)c.d_imex_dofs, (void*)c.d_imex_s, (void*)c.d_imex_m,
                   (void*)c.d_imex_sp, (void*)c.d_imex_mp, (void*)c.d_imex_kcol,
-                  (void*)c.d_imex_kval, (void*)c.d_imex_work, (void*)c.d_imex_flag})
+                  (void*)c.d_imex_kval, (void*)c.d_imex_work, (void*)c.d_imex_flag,
+                  (void*)c.d_imex_cpos, (void*)c.d_imex_members, (void*)c.d_imex_pblk,
+                  c.d_imex_blocks, c.d_imex_tiles})
     if (p) (void)hipFree(p);
   c.d_imex_dofs = nullptr;
   c.d_imex_s = c.d_imex_m = c.d_imex_sp = c.d_imex_mp = c.d_imex_work = nullptr;
-  c.d_imex_kcol = nullptr;
+  c.d_imex_kcol = c.d_imex_cpos = c.d_imex_members = c.d_imex_pblk = nullptr;
   c.d_imex_kval = nullptr;
+  c.d_imex_blocks = c.d_imex_tiles = nullptr;
   c.imex_kw = 0;
+  c.imex_nblk = 0;
+  c.imex_largest = c.imex_ntiles = c.imex_part = 0;
   c.d_imex_flag = nullptr;
   c.imex_work_bytes = 0;
   c.imex_nc = -1;
@@ -679,29 +714,145 @@ fcw_status imex_prepare(Ctx& c, double dt) {
   fcw_status st = exclusive_scan(c, mark, pos, c.nnodes, &ncn);
   if (st) return fail(st);
   const int64_t nc = (int64_t)ncn * c.ncomp;
-  if (nc > FCW_IMEX_MAX_NC) {
-    set_error("IMEX: %lld implicit DOFs exceed the dense limit %d", (long long)nc,
-              FCW_IMEX_MAX_NC);
-    return fail(FCW_E_UNSUPPORTED);
-  }
   if (c.ndof > INT32_MAX) {
     set_error("IMEX: %lld DOFs exceed the 32-bit column indices", (long long)c.ndof);
     return fail(FCW_E_UNSUPPORTED);
   }
   c.imex_ncn = ncn;
   if (nc > 0) {
-    const size_t mat = (size_t)nc * nc * sizeof(double);
-    if (hipMalloc(&c.d_imex_dofs, nc * sizeof(int64_t)) != hipSuccess ||
-        hipMalloc(&c.d_imex_s, 3 * mat) != hipSuccess ||
-        hipMalloc(&c.d_imex_m, 3 * mat) != hipSuccess) {
-      set_error("IMEX: allocation of the dense implicit matrices (%lld DOFs) failed",
-                (long long)nc);
-      return fail(FCW_E_NOMEM);
+    // Blocks of the implicit set: implicit nodes are linked when they share an active cell
+    // (S and M^cc have no entry between DOFs of different blocks).  Union-find on the host
+    // over the cells; blocks are numbered by their lowest node, their DOFs ordered
+    // component-major, then by node.
+    const int64_t ncells = (int64_t)c.ncells[0] * c.ncells[1] * (c.dim == 3 ? c.ncells[2] : 1);
+    std::vector<int32_t> h_mark(c.nnodes), h_pos(c.nnodes), h_info(ncells);
+    if (hipMemcpyAsync(h_mark.data(), mark, c.nnodes * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       c.stream) != hipSuccess ||
+        hipMemcpyAsync(h_pos.data(), pos, c.nnodes * sizeof(int32_t), hipMemcpyDeviceToHost,
+                       c.stream) != hipSuccess ||
+        hipMemcpyAsync(h_info.data(), c.d_info, ncells * sizeof(int32_t),
+                       hipMemcpyDeviceToHost, c.stream) != hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+      return fail(hip_fail(hipGetLastError(), "IMEX node marks to the host"));
+    std::vector<int64_t> node_of(ncn);
+    for (int64_t nd = 0; nd < c.nnodes; ++nd)
+      if (h_mark[nd]) node_of[h_pos[nd]] = nd;
+    std::vector<int32_t> par(ncn);
+    for (int32_t j = 0; j < ncn; ++j) par[j] = j;
+    auto find = [&](int32_t x) {
+      while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+      }
+      return x;
+    };
+    const int P1 = c.p + 1, nz = (c.dim == 3) ? P1 : 1;
+    for (int64_t cell = 0; cell < ncells; ++cell) {
+      if (h_info[cell] == kInfoOut) continue;
+      const int64_t cx = cell % c.ncells[0], cy = (cell / c.ncells[0]) % c.ncells[1],
+                    cz = cell / ((int64_t)c.ncells[0] * c.ncells[1]);
+      int32_t first = -1;
+      for (int k2 = 0; k2 < nz; ++k2)
+        for (int k1 = 0; k1 < P1; ++k1)
+          for (int k0 = 0; k0 < P1; ++k0) {
+            const int64_t nd = (cx * c.p + k0) +
+                               (int64_t)c.npts[0] * ((cy * c.p + k1) +
+                                                     (int64_t)c.npts[1] * (cz * c.p + k2));
+            if (!h_mark[nd]) continue;
+            const int32_t j = h_pos[nd];
+            if (first < 0) {
+              first = j;
+              continue;
+            }
+            const int32_t ra = find(first), rb = find(j);
+            if (ra != rb) par[std::max(ra, rb)] = std::min(ra, rb);
+          }
     }
+    std::vector<int32_t> lab(ncn), rank(ncn), root_lab(ncn, -1), cnt;
+    for (int32_t j = 0; j < ncn; ++j) {
+      const int32_t rt = find(j);
+      if (root_lab[rt] < 0) {
+        root_lab[rt] = (int32_t)cnt.size();
+        cnt.push_back(0);
+      }
+      lab[j] = root_lab[rt];
+      rank[j] = cnt[lab[j]]++;
+    }
+    const int32_t nblk = (int32_t)cnt.size();
+    std::vector<ImexBlock> blk(nblk);
+    std::vector<int64_t> toff(nblk);
+    int64_t moff = 0, poff = 0, ntiles = 0, nmax = 0;
+    for (int32_t q = 0; q < nblk; ++q) {
+      const int64_t n = (int64_t)cnt[q] * c.ncomp, T = (n + kTile - 1) / kTile;
+      if (n > FCW_IMEX_MAX_NC) {
+        set_error("IMEX: a block of %lld coupled implicit DOFs exceeds the dense limit %d",
+                  (long long)n, FCW_IMEX_MAX_NC);
+        return fail(FCW_E_UNSUPPORTED);
+      }
+      blk[q] = ImexBlock{moff, poff, (int32_t)n, (int32_t)T};
+      toff[q] = ntiles;
+      moff += n;
+      poff += T * T * kTile;
+      ntiles += T * (T + 1) / 2;
+      nmax = std::max(nmax, n);
+    }
+    std::vector<int32_t> h_cpos(nc), h_members(nc), h_pblk(nc);
+    std::vector<int64_t> h_cdofs(nc);
+    for (int k = 0; k < c.ncomp; ++k)
+      for (int32_t j = 0; j < ncn; ++j) {
+        const ImexBlock& bk = blk[lab[j]];
+        const int64_t i = (int64_t)k * ncn + j;
+        const int64_t m = bk.moff + (int64_t)k * cnt[lab[j]] + rank[j];
+        h_cpos[i] = (int32_t)m;
+        h_members[m] = (int32_t)i;
+        h_pblk[m] = lab[j];
+        h_cdofs[m] = (int64_t)k * c.nnodes + node_of[j];
+      }
+    c.imex_nblk = nblk;
+    c.imex_largest = nmax;
+    c.imex_ntiles = ntiles;
+    c.imex_part = poff;
+    int W = c.ncomp;
+    for (int k = 0; k < c.dim; ++k) W *= 2 * c.p + 1;
+    int64_t* d_cdofs = nullptr;
+    const size_t mat = (size_t)nmax * nmax * sizeof(double);
+    const size_t packed = (size_t)ntiles * kTile * kTile * sizeof(double);
+    auto fail2 = [&](fcw_status st2) {
+      if (d_cdofs) (void)hipFree(d_cdofs);
+      return fail(st2);
+    };
+    if (hipMalloc(&c.d_imex_dofs, nc * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&d_cdofs, nc * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_cpos, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_members, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_pblk, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_blocks, nblk * sizeof(ImexBlock)) != hipSuccess ||
+        hipMalloc(&c.d_imex_tiles, ntiles * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&c.d_imex_s, 3 * mat) != hipSuccess ||
+        hipMalloc(&c.d_imex_m, 3 * mat) != hipSuccess ||
+        hipMalloc(&c.d_imex_sp, packed) != hipSuccess ||
+        hipMalloc(&c.d_imex_mp, packed) != hipSuccess ||
+        hipMalloc(&c.d_imex_kcol, (size_t)nc * W * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_kval, (size_t)nc * W * sizeof(double)) != hipSuccess) {
+      set_error("IMEX: allocation of the implicit matrices (%lld DOFs, largest block %lld) "
+                "failed", (long long)nc, (long long)nmax);
+      return fail2(FCW_E_NOMEM);
+    }
+    c.imex_kw = W;
+    if (hipMemcpyAsync(d_cdofs, h_cdofs.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice,
+                       c.stream) != hipSuccess ||
+        hipMemcpyAsync(c.d_imex_cpos, h_cpos.data(), nc * sizeof(int32_t),
+                       hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+        hipMemcpyAsync(c.d_imex_members, h_members.data(), nc * sizeof(int32_t),
+                       hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+        hipMemcpyAsync(c.d_imex_pblk, h_pblk.data(), nc * sizeof(int32_t),
+                       hipMemcpyHostToDevice, c.stream) != hipSuccess ||
+        hipMemcpyAsync(c.d_imex_blocks, blk.data(), nblk * sizeof(ImexBlock),
+                       hipMemcpyHostToDevice, c.stream) != hipSuccess)
+      return fail2(hip_fail(hipGetLastError(), "IMEX block tables"));
     imex_dofs_kernel<<<blocks_for(c.nnodes), 256, 0, c.stream>>>(mark, pos, c.nnodes, ncn,
                                                                 c.ncomp, c.d_imex_dofs);
     ImexAsm a{};
-    a.dofs = c.d_imex_dofs;
     a.info = c.d_info;
     a.kref = c.d_kref;
     a.lref = c.d_lref;
@@ -709,7 +860,6 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     a.mcut = c.d_mcut;
     a.S = c.d_imex_s;
     a.M = c.d_imex_m;
-    a.nc = nc;
     a.nnodes = c.nnodes;
     a.dim = c.dim;
     a.p = c.p;
@@ -720,53 +870,58 @@ fcw_status imex_prepare(Ctx& c, double dt) {
       a.np[k] = c.npts[k];
     }
     a.bdt2 = kBeta * dt * dt;
-    const unsigned gy = (unsigned)std::min<int64_t>(nc, 65535);
-    const unsigned gz = (unsigned)((nc + gy - 1) / gy);
-    imex_assemble_kernel<<<dim3(blocks_for(nc), gy, gz), 256, 0, c.stream>>>(a);
-    {
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return fail(hip_fail(e, "IMEX assembly"));
+    // per block: dense S and M^cc, Cholesky, inverses, packed upper tiles
+    for (int32_t q = 0; q < nblk; ++q) {
+      const int64_t n = blk[q].n, T = blk[q].T;
+      a.dofs = d_cdofs + blk[q].moff;
+      a.nc = n;
+      const unsigned gy = (unsigned)std::min<int64_t>(n, 65535);
+      const unsigned gz = (unsigned)((n + gy - 1) / gy);
+      imex_assemble_kernel<<<dim3(blocks_for(n), gy, gz), 256, 0, c.stream>>>(a);
+      {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail2(hip_fail(e, "IMEX assembly"));
+      }
+      if ((st = cholesky(c, c.d_imex_s, c.d_imex_s + (size_t)n * n, n))) return fail2(st);
+      if ((st = cholesky(c, c.d_imex_m, c.d_imex_m + (size_t)n * n, n))) return fail2(st);
+      // S^{-1} and (M^cc)^{-1}, column by column
+      for (double* fm : {c.d_imex_s, c.d_imex_m}) {
+        double* inv = fm + 2 * (size_t)n * n;
+        identity_kernel<<<blocks_for(n * n), 256, 0, c.stream>>>(inv, n);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail2(hip_fail(e, "IMEX identity"));
+        if ((st = imex_solve(c, fm, n, (int)n, inv, inv))) return fail2(st);
+      }
+      const int64_t np = T * (T + 1) / 2 * kTile * kTile;
+      const size_t off = (size_t)toff[q] * kTile * kTile;
+      pack_inverse_tiles_kernel<<<blocks_for(np), 256, 0, c.stream>>>(
+          c.d_imex_s + 2 * (size_t)n * n, n, T, c.d_imex_sp + off,
+          (int4*)c.d_imex_tiles + toff[q], q);
+      pack_inverse_tiles_kernel<<<blocks_for(np), 256, 0, c.stream>>>(
+          c.d_imex_m + 2 * (size_t)n * n, n, T, c.d_imex_mp + off, nullptr, q);
+      {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail2(hip_fail(e, "IMEX packing"));
+      }
     }
-    if ((st = cholesky(c, c.d_imex_s, c.d_imex_s + (size_t)nc * nc, nc))) return fail(st);
-    if ((st = cholesky(c, c.d_imex_m, c.d_imex_m + (size_t)nc * nc, nc))) return fail(st);
-    // S^{-1} and (M^cc)^{-1}, column by column (symmetric: row r of the result is column r)
-    for (double* f : {c.d_imex_s, c.d_imex_m}) {
-      double* inv = f + 2 * (size_t)nc * nc;
-      identity_kernel<<<blocks_for(nc * nc), 256, 0, c.stream>>>(inv, nc);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return fail(hip_fail(e, "IMEX identity"));
-      if ((st = imex_solve(c, f, nc, (int)nc, inv, inv))) return fail(st);
-    }
-    // both inverses as packed upper tiles, and the implicit rows of K
-    const int64_t T = (nc + kTile - 1) / kTile;
-    const int64_t packed = T * (T + 1) / 2 * kTile * kTile;
-    int W = c.ncomp;
-    for (int k = 0; k < c.dim; ++k) W *= 2 * c.p + 1;
-    if (hipMalloc(&c.d_imex_sp, packed * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c.d_imex_mp, packed * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c.d_imex_kcol, (size_t)nc * W * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c.d_imex_kval, (size_t)nc * W * sizeof(double)) != hipSuccess) {
-      set_error("IMEX: allocation of the packed inverses (%lld DOFs) failed", (long long)nc);
-      return fail(FCW_E_NOMEM);
-    }
-    c.imex_kw = W;
-    pack_inverse_tiles_kernel<<<blocks_for(packed), 256, 0, c.stream>>>(
-        c.d_imex_s + 2 * (size_t)nc * nc, nc, T, c.d_imex_sp);
-    pack_inverse_tiles_kernel<<<blocks_for(packed), 256, 0, c.stream>>>(
-        c.d_imex_m + 2 * (size_t)nc * nc, nc, T, c.d_imex_mp);
+    // the implicit rows of K (rows in implicit order)
+    a.dofs = c.d_imex_dofs;
+    a.nc = nc;
     imex_kc_assemble_kernel<<<blocks_for(nc * W), 256, 0, c.stream>>>(
         a, W, mark, pos, ncn, c.d_imex_kcol, c.d_imex_kval);
     {
       const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return fail(hip_fail(e, "IMEX packing"));
+      if (e != hipSuccess) return fail2(hip_fail(e, "IMEX stiffness rows"));
     }
     {
       const hipError_t e = hipStreamSynchronize(c.stream);
-      if (e != hipSuccess) return fail(hip_fail(e, "IMEX inverse"));
+      if (e != hipSuccess) return fail2(hip_fail(e, "IMEX set-up"));
     }
-    // the dense S, its factor and S^{-1} are not used by the steps
+    // the dense blocks, their factors and inverses are not used by the steps
+    (void)hipFree(d_cdofs);
     (void)hipFree(c.d_imex_s);
-    c.d_imex_s = nullptr;
+    (void)hipFree(c.d_imex_m);
+    c.d_imex_s = c.d_imex_m = nullptr;
   }
   (void)hipFree(mark);
   (void)hipFree(pos);
@@ -781,10 +936,10 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
   const int64_t nc = c.imex_nc, ndof = c.ndof;
   const int64_t nv = nc * nrhs;
   // work: b, u_k, d_k and the predictor on the implicit DOFs (nrhs x nc each), then the
-  // tile products of the inverse ([T][nrhs][32 T]), each part on a 256-byte boundary
+  // tile products of the inverse (per block [T][nrhs][32 T]), each part on a 256-byte
+  // boundary
   auto up32 = [](size_t v) { return (v + 31) / 32 * 32; };
-  const int64_t T = (nc + kTile - 1) / kTile;
-  const size_t nvp = up32((size_t)nv), npart = (size_t)T * nrhs * T * kTile;
+  const size_t nvp = up32((size_t)nv), npart = (size_t)nrhs * c.imex_part;
   const size_t need = (4 * nvp + npart) * sizeof(double);
   if (c.imex_work_bytes < need) {
     if (c.d_imex_work) FCW_HIP(hipFree(c.d_imex_work));
@@ -814,7 +969,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
   auto kc_rhs = [&](const double* uimp, double t) {
     imex_kc_rhs_kernel<<<gw, 256, 0, c.stream>>>(
         c.d_imex_kcol, c.d_imex_kval, c.imex_kw, u, uimp, c.d_imex_dofs, c.d_src, nc, ndof,
-        c.nnodes, nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, bv);
+        c.nnodes, nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, c.d_imex_cpos, bv);
   };
   fcw_status st;
   if (nc > 0) {
@@ -832,7 +987,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
       const int first = start && k == 0;
       if (nc > 0) {
         kc_rhs(uold, t);
-        symp_tiles(c, c.d_imex_mp, nc, bv, nrhs, part);
+        symp_tiles(c, c.d_imex_mp, bv, nrhs, part);
       }
       if ((st = run_steps(c, c.tile_choice, nrhs, u, d, c.d_ubuf, t, dt, 1, first))) return st;
       if (nc > 0) {
@@ -844,9 +999,10 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     return FCW_OK;
   }
   if (start && nc > 0) {
-    // a_0 from M^cc a_0 = F_0 - (K u_0) on the implicit DOFs
+    // a_0 = (M^cc)^{-1} (F_0 - K^c u_0) on the implicit DOFs
     kc_rhs(uold, t0);
-    if ((st = imex_solve(c, c.d_imex_m, nc, nrhs, bv, a_c))) return st;
+    symp_tiles(c, c.d_imex_mp, bv, nrhs, part);
+    symp_finish<kUpdStore>(c, part, nrhs, e);
   }
   // the first predictor; each corrector leaves the next one
   if (nc > 0) imex_predict_kernel<<<gb, 256, 0, c.stream>>>(uold, v_c, a_c, nv, dt, upred);
@@ -858,7 +1014,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
     if (nc == 0) continue;
     // K^c u_p: the explicit DOFs' new values with the predictor on the implicit DOFs
     kc_rhs(upred, t + dt);
-    symp_tiles(c, c.d_imex_sp, nc, bv, nrhs, part);
+    symp_tiles(c, c.d_imex_sp, bv, nrhs, part);
     symp_finish<kUpdImex>(c, part, nrhs, e);
     FCW_HIP(hipGetLastError());
   }

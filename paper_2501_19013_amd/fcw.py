@@ -24,7 +24,7 @@ _ARR_DTYPE = {ARR_CELL_CLASS: np.int8, ARR_CUT_CELLS: np.int32, ARR_IMEX_DOFS: n
 
 # every entry point declared in include/fcw.h
 EXPORTS = ("fcw_assemble_cells", "fcw_stabilize_cut_cells", "fcw_critical_dt",
-           "fcw_step_explicit", "fcw_step_explicit_noalloc", "fcw_imex_prepare", "fcw_step_imex", "fcw_step_consistent",
+           "fcw_step_explicit", "fcw_step_explicit_noalloc", "fcw_imex_prepare", "fcw_imex_layout", "fcw_step_imex", "fcw_step_consistent",
            "fcw_apply_stiffness",
            "fcw_query",
            "fcw_autotune", "fcw_tile_config", "fcw_tile_name", "fcw_select_tile", "fcw_set_stream", "fcw_kernel_times", "fcw_run",
@@ -121,6 +121,8 @@ def load(path=LIB_PATH):
     lib.fcw_step_explicit_noalloc.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32,
                                               i32]
     lib.fcw_imex_prepare.argtypes = [vp, f64, C.POINTER(C.c_int64)]
+    lib.fcw_imex_layout.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]
     lib.fcw_step_imex.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_step_consistent.argtypes = [vp, i32, vp, vp, C.POINTER(Source), f64, f64, i32, i32]
     lib.fcw_apply_stiffness.argtypes = [vp, i32, vp, vp]
@@ -253,6 +255,13 @@ def imex_prepare(ctx, dt):
     n = C.c_int64()
     _check(load().fcw_imex_prepare(ctx, float(dt), C.byref(n)))
     return n.value
+
+
+def imex_layout(ctx):
+    """Blocks of the prepared implicit set: dict(n_blocks, largest, solve_bytes)."""
+    nb, lg, sb = C.c_int32(), C.c_int64(), C.c_int64()
+    _check(load().fcw_imex_layout(ctx, C.byref(nb), C.byref(lg), C.byref(sb)))
+    return dict(n_blocks=nb.value, largest=lg.value, solve_bytes=sb.value)
 
 
 def step_consistent(ctx, nrhs, u, d, sources, t0, dt, nsteps, start):

@@ -40,13 +40,14 @@ def _run(cfg, dt, chunks, sources):
         k += n
     torch.cuda.synchronize()
     out = dict(u=u.double().cpu().numpy(), v=v.cpu().numpy()[:, :nc], a=a.cpu().numpy()[:, :nc],
-               dofs=dofs, nc=nc)
+               dofs=dofs, nc=nc, layout=fcw.imex_layout(s.ctx))
     s.close()
     return out
 
 
-def _check(cfg, steps, chunks, sources, dt=None, tol=TOL):
-    disc = problem.build(problem.Problem.from_config(cfg))
+def _check(cfg, steps, chunks, sources, dt=None, tol=TOL, disc=None, sparse=False):
+    if disc is None:
+        disc = problem.build(problem.Problem.from_config(cfg))
     if dt is None:
         dt = 0.9 * timestep.critical_dt(disc)
     got = _run(cfg, dt, chunks, sources)
@@ -54,7 +55,8 @@ def _check(cfg, steps, chunks, sources, dt=None, tol=TOL):
     assert got["nc"] == len(c)
     assert np.array_equal(got["dofs"], c)
     for r, src in enumerate(sources):
-        ref = ox.imex(disc, dt, steps, sources=[src])
+        ref = ox.imex(disc, dt, steps, sources=[src], sparse=sparse)
+        assert np.linalg.norm(ref["u"]) > 0
         e = np.linalg.norm(got["u"][r] - ref["u"]) / np.linalg.norm(ref["u"])
         ev = np.linalg.norm(got["v"][r] - ref["v_c"]) / max(np.linalg.norm(ref["v_c"]), 1e-300)
         assert e <= tol and ev <= tol, (r, e, ev)
@@ -85,7 +87,7 @@ def test_imex_two_sources_batched():
 
 
 def test_imex_ten_sources():
-    # ten right-hand sides: the S^-1 product runs them in passes of eight
+    # ten right-hand sides (each tile of S^-1 is read once for all of them)
     cfg = _c1(1e-4)
     xs = [(0.1, 0.1), (0.9, 0.1), (0.1, 0.9), (0.9, 0.9), (0.5, 0.08), (0.08, 0.5),
           (0.92, 0.5), (0.5, 0.92), (0.25, 0.75), (0.75, 0.25)]
@@ -105,6 +107,34 @@ def test_imex_3d_elastic_parity():
                           alpha=1e-4)
     cfg["sources"] = [dict(x=(0.1, 0.1, 0.1), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
     _check(cfg, 40, [40], cfg["sources"])
+
+
+def test_imex_implicit_set_above_the_dense_block_limit():
+    """A 2-D p = 4 field of 50 voids on 96 x 96 cells: 19 815 implicit DOFs, more than one
+    dense block may hold (FCW_IMEX_MAX_NC).  The device splits them into blocks of coupled
+    DOFs (the cut cells around one void or cluster of voids, linked through shared cells);
+    the oracle solves with a sparse LU factor of the whole S.  Two right-hand sides, two
+    calls."""
+    import re
+    from pathlib import Path
+    cc, rr = workloads.random_circles(seed=5, count=50, rmin=0.02, rmax=0.04)
+    cfg = workloads._base(2, (96, 96), 4, cc, rr, alpha=1e-4)
+    disc = problem.build(problem.Problem.from_config(cfg))
+    c, d = ox.partition(disc)
+    header = (Path(__file__).resolve().parents[1] / "include" / "fcw.h").read_text()
+    limit = int(re.search(r"#define FCW_IMEX_MAX_NC (\d+)", header).group(1))
+    assert len(c) > limit
+    # a step below the explicit block's limit (Gershgorin bound of (M^dd)^-1 K^dd)
+    K = problem.assembled_K(disc).tocsr()
+    im = disc.inv_mass_dof()
+    g = np.asarray(abs(K[d][:, d]).sum(axis=1)).ravel() * im[d]
+    dt = 0.8 * 2.0 / np.sqrt(g.max())
+    srcs = [dict(x=(0.1, 0.1), f0=45.0, amp=1.0), dict(x=(0.85, 0.6), f0=60.0, amp=0.7)]
+    got = _check(cfg, 80, [30, 50], srcs, dt=dt, disc=disc, sparse=True)
+    lay = got["layout"]
+    assert 1 < lay["n_blocks"] and lay["largest"] <= limit
+    # each block's packed upper tiles: far less than one dense inverse of the whole set
+    assert lay["solve_bytes"] < 0.25 * 8 * len(c) ** 2
 
 
 def test_imex_without_cut_cells_is_the_explicit_step():

@@ -182,12 +182,18 @@ def test_displacement_form_equals_predictor_corrector(mode):
 
 
 def test_implicit_set_of_the_3d_imex_workload_exceeds_the_dense_limit():
-    """Size of the implicit set (every component of the nodes of cut cells, Sec. 2.5) of the
-    3-D elastic IMEX workload (64^3 cells, p = 3, the spherical-pore field): counted from the
-    oracle's cell classes, it is far above the dense limit of the device's IMEX set-up, so
-    that workload needs a sparse factorisation of S."""
+    """Size and blocks of the implicit set (every component of the nodes of cut cells,
+    Sec. 2.5) of the 3-D elastic IMEX workload (64^3 cells, p = 3, the spherical-pore
+    field), from the oracle's cell classes.  S couples two implicit nodes when an active
+    cell holds both; at porosity 0.2 nearly all implicit nodes fall into one such block,
+    far above the dense block limit of the device's IMEX set-up, so this workload needs a
+    sparse factorisation of S."""
+    import itertools
     import re
     from pathlib import Path
+
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
 
     import workloads
     from oracle import geometry
@@ -195,20 +201,49 @@ def test_implicit_set_of_the_3d_imex_workload_exceeds_the_dense_limit():
     cfg = workloads.config("c4")
     prob = Problem.from_config(cfg)
     cls = geometry.classify_cells(prob)
-    n = prob.ncells
-    cut = np.flatnonzero(cls == geometry.CUT)
-    assert cut.size > 0
-    cx, cy, cz = cut % n[0], (cut // n[0]) % n[1], cut // (n[0] * n[1])
-    npts = [k * prob.p + 1 for k in n]
-    mark = np.zeros(npts[::-1], dtype=bool)  # [z][y][x]
-    for i in range(prob.p + 1):
-        for j in range(prob.p + 1):
-            for k in range(prob.p + 1):
-                mark[cz * prob.p + k, cy * prob.p + j, cx * prob.p + i] = True
-    n_c = 3 * int(mark.sum())
+    n, p = prob.ncells, prob.p
+    npts = [k * p + 1 for k in n]
+
+    def cell_nodes(cells):
+        ix = [cells % n[0], (cells // n[0]) % n[1], cells // (n[0] * n[1])]
+        return np.stack([(ix[0] * p + a) + npts[0] * ((ix[1] * p + b) + npts[1] * (ix[2] * p + c))
+                         for c, b, a in itertools.product(range(p + 1), repeat=3)], 1)
+
+    cut_nodes = cell_nodes(np.flatnonzero(cls == geometry.CUT))
+    imp = np.unique(cut_nodes)
+    n_c = 3 * imp.size
     header = (Path(__file__).resolve().parents[1] / "include" / "fcw.h").read_text()
     limit = int(re.search(r"#define FCW_IMEX_MAX_NC (\d+)", header).group(1))
-    # the all-void cut cells the device drops can only shrink the set by the nodes that no
-    # other cut cell shares; the count stays orders of magnitude above the limit
-    assert n_c > 100 * limit, n_c
-    print(f"cut cells {cut.size}, implicit DOFs {n_c}")
+    # blocks: implicit nodes linked through every active (cut or uncut) cell
+    rows, cols = [], []
+    for cells in (np.flatnonzero(cls == geometry.CUT), np.flatnonzero(cls == geometry.UNCUT)):
+        nodes = cell_nodes(cells)
+        pos = np.minimum(np.searchsorted(imp, nodes), imp.size - 1)
+        hit = imp[pos] == nodes
+        first = np.where(hit.any(1), pos[np.arange(len(pos)), hit.argmax(1)], -1)
+        keep = hit & (first[:, None] >= 0)
+        rows.append(np.broadcast_to(first[:, None], pos.shape)[keep])
+        cols.append(pos[keep])
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    g = coo_matrix((np.ones(r.size), (r, c)), shape=(imp.size, imp.size))
+    nblk, lab = connected_components(g, directed=False)
+    largest = 3 * int(np.bincount(lab).max())
+    assert n_c > 100 * limit and largest > 100 * limit, (n_c, largest)
+    assert largest > 0.9 * n_c
+    print(f"cut cells {int((cls == geometry.CUT).sum())}, implicit DOFs {n_c}, "
+          f"blocks {nblk}, largest {largest}")
+
+
+def test_sparse_and_dense_solves_agree():
+    """The sparse-LU variant of the oracle's IMEX solves (for large implicit sets) gives the
+    dense-Cholesky result: the same equations, another factorisation (alpha = 1e-4, where
+    S is well conditioned)."""
+    cfg = workloads.config("c1")
+    cfg["alpha"] = 1e-4
+    disc = problem.build(problem.Problem.from_config(cfg))
+    dt = 0.9 * timestep.critical_dt(disc)
+    a = ox.imex(disc, dt, 30, sources=cfg["sources"])
+    b = ox.imex(disc, dt, 30, sources=cfg["sources"], sparse=True)
+    assert len(a["c"]) > 0
+    for key in ("u", "v_c", "a_c"):
+        assert np.linalg.norm(a[key] - b[key]) <= 1e-9 * np.linalg.norm(a[key]), key
