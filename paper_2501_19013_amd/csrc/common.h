@@ -145,9 +145,9 @@ struct Ctx {
   double* d_imex_m = nullptr;      // set-up only: the same for M^cc
   double* d_imex_sp = nullptr;     // S^{-1} as its upper 32 x 32 tiles, block by block
   double* d_imex_mp = nullptr;     // (M^cc)^{-1}, the same
-  int32_t* d_imex_kcol = nullptr;  // [imex_nc][imex_kw] the implicit rows of K: columns
-  double* d_imex_kval = nullptr;   // [imex_nc][imex_kw] and values (0 in padding slots)
-  int imex_kw = 0;
+  int32_t* d_imex_kptr = nullptr;  // [imex_nc+1] the implicit rows of K, compressed: offsets,
+  int32_t* d_imex_kcol = nullptr;  // columns (-(implicit index + 1) for implicit DOFs)
+  double* d_imex_kval = nullptr;   // and values
   // the implicit set splits into blocks (connected through shared cells) that S and M^cc
   // never couple; b and x of the tiled products run in block order
   int32_t imex_nblk = 0;           // blocks
@@ -158,7 +158,7 @@ struct Ctx {
   int32_t* d_imex_members = nullptr;  // [imex_nc] implicit DOF at each block-order position
   int32_t* d_imex_pblk = nullptr;     // [imex_nc] block of each block-order position
   void* d_imex_blocks = nullptr;      // [imex_nblk] block descriptors
-  void* d_imex_tiles = nullptr;       // [imex_ntiles] (I, J, block) of each packed tile
+  void* d_imex_tiles = nullptr;       // [imex_ntiles] descriptor of each packed tile
   double* d_imex_work = nullptr;   // per-call work vectors
   size_t imex_work_bytes = 0;
   int32_t* d_imex_flag = nullptr;  // [1] non-positive pivot seen

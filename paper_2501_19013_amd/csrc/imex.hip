@@ -12,7 +12,7 @@
 //      DOFs (left in a vector over the implicit DOFs by the previous step's corrector),
 //      the explicit DOFs' new values serving as theirs;
 //   3. b = F_{k+1} - K^c u_p on the implicit DOFs: the implicit rows of K (every column
-//      they touch) assembled once as padded sparse rows, one wave per row;
+//      they touch) assembled once as compressed sparse rows, 16 lanes per row;
 //   4. S a_{k+1} = b, S = M^cc + beta dt^2 K^cc: a product with S^{-1}, formed once from
 //      the Cholesky factor of S (forward and backward sweeps against the unit vectors,
 //      one workgroup per column) and held as the 32 x 32 tiles of its upper triangle
@@ -384,10 +384,17 @@ __device__ inline void tile_at(int64_t q, int64_t T, int64_t& I, int64_t& J) {
 
 // P[tile (I, J)][r][c] = (A_ij + A_ji) / 2 at i = 32 I + r, j = 32 J + c (0 beyond n),
 // for the T (T + 1) / 2 upper tiles of one block in packed order, and the tiles'
-// descriptors (I, J, block): the inverse from column-wise solves is symmetric up to
-// rounding; both halves are kept
+// descriptors: the inverse from column-wise solves is symmetric up to rounding; both
+// halves are kept
+// one packed tile: (I, J) in its block of n DOFs and T tile rows, the block's first
+// block-order position and the offset of its partial products (per right-hand side)
+struct TileDesc {
+  int32_t I, J, n, T;
+  int64_t moff, poff;
+};
+
 __global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T, double* P,
-                                          int4* tiles, int32_t blk) {
+                                          TileDesc* tiles, int64_t moff, int64_t poff) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T * (T + 1) / 2 * kTile * kTile) return;
   const int64_t q = t / (kTile * kTile);
@@ -396,7 +403,7 @@ __global__ void pack_inverse_tiles_kernel(const double* A, int64_t n, int64_t T,
   tile_at(q, T, I, J);
   const int64_t i = I * kTile + e / kTile, j = J * kTile + e % kTile;
   P[t] = (i < n && j < n) ? 0.5 * (A[i * n + j] + A[j * n + i]) : 0.0;
-  if (tiles && e == 0) tiles[q] = make_int4((int)I, (int)J, blk, 0);
+  if (tiles && e == 0) tiles[q] = TileDesc{(int32_t)I, (int32_t)J, (int32_t)n, (int32_t)T, moff, poff};
 }
 
 // one block of the implicit set: its n DOFs sit at block-order positions moff .. moff+n-1,
@@ -406,46 +413,61 @@ struct ImexBlock {
   int32_t n, T;
 };
 
-// Partial products of x = A b over the packed upper tiles, one wave per tile (I, J) of a
-// block: the tile's rows against b's block J go to part[J][r][block I] and, for I < J, its
+// Partial products of x = A b over the packed upper tiles of the blocks: the rows of tile
+// (I, J) of a block against b's block J go to part[J][r][block I] and, for I < J, its
 // columns against b's block I to part[I][r][block J], where part is the block's
 // [T][nrhs][32 T] array; every entry is written by exactly one tile, and x_i is the sum of
 // part[0 .. T-1][r][i].  b and x are in block order ([nrhs][nc]).
-// Lane layout: columns 2 cp, 2 cp + 1 (cp = lane mod 16), rows rs + 4 k (k < 8,
+// One wave takes TPW consecutive tiles and issues all their loads before the first
+// product.  Lane layout: columns 2 cp, 2 cp + 1 (cp = lane mod 16), rows rs + 4 k (k < 8,
 // rs = lane / 16): each load instruction reads four 256-byte tile rows.
-__global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, const int4* tiles,
-                                                        int64_t ntiles, const ImexBlock* blocks,
-                                                        const double* b, int64_t nc, int nrhs,
-                                                        double* part) {
-  const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= ntiles) return;
-  const int cp = lane & 15, rs = lane >> 4;
-  const int4 td = tiles[q];
-  const int64_t I = td.x, J = td.y;
-  const ImexBlock bk = blocks[td.z];
-  const int64_t n = bk.n;
-  const double2* tile = (const double2*)(P + q * kTile * kTile);
+struct TileIn {
   double2 v[8];
+  double bI, bJ;  // b at rows 32 I + (lane mod 32) and 32 J + (lane mod 32), first rhs
+};
+
+__device__ inline void tile_load(const double* P, const TileDesc& td, int64_t q,
+                                 const double* b, int lane, TileIn& in) {
+  const int cp = lane & 15, rs = lane >> 4;
+  const int64_t iB = (int64_t)td.I * kTile + (lane & 31), jB = (int64_t)td.J * kTile + (lane & 31);
+  in.bI = iB < td.n ? b[td.moff + iB] : 0.0;
+  in.bJ = jB < td.n ? b[td.moff + jB] : 0.0;
+  // the tiles are read once per product: nontemporal loads keep them from displacing the
+  // vectors and partial products in the caches
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v* tile = (const d2v*)(P + q * kTile * kTile);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = tile[(rs + 4 * k) * (kTile / 2) + cp];
-  const int64_t stride = (int64_t)bk.T * kTile;
-  double* pb = part + nrhs * bk.poff;
+  for (int k = 0; k < 8; ++k) {
+    const d2v x = __builtin_nontemporal_load(tile + (rs + 4 * k) * (kTile / 2) + cp);
+    in.v[k] = make_double2(x.x, x.y);
+  }
+}
+
+__device__ inline void tile_products(const TileDesc& td, const TileIn& in, const double* b,
+                                     int64_t nc, int nrhs, double* part, int lane) {
+  const int cp = lane & 15, rs = lane >> 4;
+  const int64_t I = td.I, J = td.J, n = td.n;
+  const int64_t stride = (int64_t)td.T * kTile;
+  double* pb = part + nrhs * td.poff;
   const bool off_diag = I < J;
   const int64_t iB = I * kTile + (lane & 31), jB = J * kTile + (lane & 31);
   const int b3 = (cp >> 3) & 1, b2 = (cp >> 2) & 1, b1 = (cp >> 1) & 1;
   for (int r = 0; r < nrhs; ++r) {
-    const double* br = b + (int64_t)r * nc + bk.moff;
-    const double bI = iB < n ? br[iB] : 0.0, bJ = jB < n ? br[jB] : 0.0;
+    double bI = in.bI, bJ = in.bJ;
+    if (r > 0) {
+      const double* br = b + (int64_t)r * nc + td.moff;
+      bI = iB < n ? br[iB] : 0.0;
+      bJ = jB < n ? br[jB] : 0.0;
+    }
     const double bj0 = __shfl(bJ, 2 * cp), bj1 = __shfl(bJ, 2 * cp + 1);
     double s[8];
     double cs0 = 0.0, cs1 = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      s[k] = v[k].x * bj0 + v[k].y * bj1;
+      s[k] = in.v[k].x * bj0 + in.v[k].y * bj1;
       const double bi = __shfl(bI, rs + 4 * k);
-      cs0 += v[k].x * bi;
-      cs1 += v[k].y * bi;
+      cs0 += in.v[k].x * bi;
+      cs1 += in.v[k].y * bi;
     }
     // row sums over the 16 lanes of a row group: three halving exchanges leave each lane
     // one row (k = 4 b3 + 2 b2 + b1), then one butterfly step
@@ -482,6 +504,30 @@ __global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, const i
     }
   }
 }
+
+template <int TPW>
+__global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, const TileDesc* tiles,
+                                                        int64_t ntiles, const double* b,
+                                                        int64_t nc, int nrhs, double* part) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform tile index: the descriptors come through the scalar unit
+  const int64_t q0 =
+      TPW * ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));
+  if (q0 >= ntiles) return;
+  TileDesc td[TPW];
+  TileIn in[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    td[j] = tiles[min(q0 + j, ntiles - 1)];
+    if (q0 + j < ntiles) tile_load(P, td[j], q0 + j, b, lane, in[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < TPW; ++j)
+    if (q0 + j < ntiles) tile_products(td[j], in[j], b, nc, nrhs, part, lane);
+}
+
+// tiles per wave of symp_tile_kernel
+constexpr int kTilesPerWave = 1;
 
 // the updates that consume x = A b on the implicit DOFs ([nrhs][nc] vectors)
 struct ImexUpd {
@@ -547,7 +593,18 @@ __global__ __launch_bounds__(256) void symp_reduce_kernel(const double* part,
     const ImexBlock bk = blocks[pblk[m]];
     const int64_t stride = (int64_t)bk.T * kTile;
     const double* p = part + nrhs * bk.poff + r * stride + (m - bk.moff);
-    for (int64_t y = g; y < bk.T; y += 16) s += p[y * nrhs * stride];
+    const int64_t ys = nrhs * stride;
+    int64_t y = g;
+    // four loads in flight, summed in the order of y
+    for (; y + 48 < bk.T; y += 64) {
+      const double a0 = p[y * ys], a1 = p[(y + 16) * ys], a2 = p[(y + 32) * ys],
+                   a3 = p[(y + 48) * ys];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; y < bk.T; y += 16) s += p[y * ys];
   }
   red[g][il] = s;
   __syncthreads();
@@ -605,29 +662,54 @@ __device__ inline double source_at(const SourceDev* src, int64_t r, int64_t g, i
   return 0.0;
 }
 
+// nonzero slots of each padded row
+__global__ void imex_kc_count_kernel(const double* val, int W, int64_t nc, int32_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int32_t k = 0;
+  for (int w = 0; w < W; ++w) k += val[i * W + w] != 0.0;
+  cnt[i] = k;
+}
+
+// the padded rows' nonzero slots, in slot order, at ptr[i] .. ptr[i+1]-1
+__global__ void imex_kc_compact_kernel(const int32_t* ecol, const double* eval, int W,
+                                       int64_t nc, const int32_t* ptr, int32_t* col,
+                                       double* val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc) return;
+  int64_t o = ptr[i];
+  for (int w = 0; w < W; ++w) {
+    const double v = eval[i * W + w];
+    if (v != 0.0) {
+      col[o] = ecol[i * W + w];
+      val[o] = v;
+      ++o;
+    }
+  }
+}
+
 // b = F(t) - K^c u on the implicit DOFs (written in block order: b[r][cpos[i]]), u from
 // uimp [nrhs][nc] on the implicit DOFs and from u [nrhs][ndof] elsewhere: one wave per
-// implicit row of the padded sparse rows (lanes over the slots, a fixed butterfly for the
-// sum)
+// 16 lanes per implicit row of the compressed sparse rows, four rows per wave (lanes over
+// the row's entries, a fixed butterfly for the sum)
 __global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
-    const int32_t* col, const double* val, int W, const double* u, const double* uimp,
+    const int32_t* ptr, const int32_t* col, const double* val, const double* u, const double* uimp,
     const int64_t* dofs, const SourceDev* src, int64_t nc, int64_t ndof, int64_t nnodes,
     int nrhs, int dim, int p, int np0, int np1, double t, const int32_t* cpos, double* b) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= nc) return;
-  const int32_t* ci = col + i * W;
-  const double* vi = val + i * W;
+  const int lane = threadIdx.x & 15;
+  const int64_t i = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  // rows past the end still take part in the shuffles (empty entry range)
+  const int32_t k0 = i < nc ? ptr[i] : 0, k1 = i < nc ? ptr[i + 1] : 0;
   for (int r = 0; r < nrhs; ++r) {
     const double* ur = u + (int64_t)r * ndof;
     const double* ui = uimp + (int64_t)r * nc;
     double s = 0.0;
-    for (int w = lane; w < W; w += 64) {
-      const int32_t cw = ci[w];
-      s += vi[w] * (cw >= 0 ? ur[cw] : ui[-cw - 1]);
+    for (int32_t k = k0 + lane; k < k1; k += 16) {
+      const int32_t cw = col[k];
+      s += val[k] * (cw >= 0 ? ur[cw] : ui[-cw - 1]);
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (lane == 0)
+    for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0 && i < nc)
       b[(int64_t)r * nc + cpos[i]] = source_at(src, r, dofs[i], nnodes, dim, p, np0, np1, t) - s;
   }
 }
@@ -635,9 +717,10 @@ __global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
 // part = the tile products of x = A b (A the packed upper tiles of the blocks of the
 // inverse of S or M^cc; b in block order)
 static void symp_tiles(Ctx& c, const double* A, const double* b, int nrhs, double* part) {
-  symp_tile_kernel<<<(unsigned)((c.imex_ntiles + 3) / 4), 256, 0, c.stream>>>(
-      A, (const int4*)c.d_imex_tiles, c.imex_ntiles, (const ImexBlock*)c.d_imex_blocks, b,
-      c.imex_nc, nrhs, part);
+  constexpr int per_block = 4 * kTilesPerWave;
+  symp_tile_kernel<kTilesPerWave>
+      <<<(unsigned)((c.imex_ntiles + per_block - 1) / per_block), 256, 0, c.stream>>>(
+          A, (const TileDesc*)c.d_imex_tiles, c.imex_ntiles, b, c.imex_nc, nrhs, part);
 }
 
 // the reduction of the tile products, fused with the update that consumes x
@@ -653,14 +736,13 @@ void imex_free(Ctx& c) {
                   (void*)c.d_imex_sp, (void*)c.d_imex_mp, (void*)c.d_imex_kcol,
                   (void*)c.d_imex_kval, (void*)c.d_imex_work, (void*)c.d_imex_flag,
                   (void*)c.d_imex_cpos, (void*)c.d_imex_members, (void*)c.d_imex_pblk,
-                  c.d_imex_blocks, c.d_imex_tiles})
+                  (void*)c.d_imex_kptr, c.d_imex_blocks, c.d_imex_tiles})
     if (p) (void)hipFree(p);
   c.d_imex_dofs = nullptr;
   c.d_imex_s = c.d_imex_m = c.d_imex_sp = c.d_imex_mp = c.d_imex_work = nullptr;
-  c.d_imex_kcol = c.d_imex_cpos = c.d_imex_members = c.d_imex_pblk = nullptr;
+  c.d_imex_kcol = c.d_imex_kptr = c.d_imex_cpos = c.d_imex_members = c.d_imex_pblk = nullptr;
   c.d_imex_kval = nullptr;
   c.d_imex_blocks = c.d_imex_tiles = nullptr;
-  c.imex_kw = 0;
   c.imex_nblk = 0;
   c.imex_largest = c.imex_ntiles = c.imex_part = 0;
   c.d_imex_flag = nullptr;
@@ -814,11 +896,19 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     c.imex_part = poff;
     int W = c.ncomp;
     for (int k = 0; k < c.dim; ++k) W *= 2 * c.p + 1;
+    if (nc * W > INT32_MAX) {
+      set_error("IMEX: %lld implicit DOFs x %d stencil slots exceed 32-bit row offsets",
+                (long long)nc, W);
+      return fail(FCW_E_UNSUPPORTED);
+    }
     int64_t* d_cdofs = nullptr;
+    int32_t *ecol = nullptr, *kcnt = nullptr;
+    double* eval = nullptr;
     const size_t mat = (size_t)nmax * nmax * sizeof(double);
     const size_t packed = (size_t)ntiles * kTile * kTile * sizeof(double);
     auto fail2 = [&](fcw_status st2) {
-      if (d_cdofs) (void)hipFree(d_cdofs);
+      for (void* p : {(void*)d_cdofs, (void*)ecol, (void*)eval, (void*)kcnt})
+        if (p) (void)hipFree(p);
       return fail(st2);
     };
     if (hipMalloc(&c.d_imex_dofs, nc * sizeof(int64_t)) != hipSuccess ||
@@ -827,18 +917,19 @@ fcw_status imex_prepare(Ctx& c, double dt) {
         hipMalloc(&c.d_imex_members, nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c.d_imex_pblk, nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc(&c.d_imex_blocks, nblk * sizeof(ImexBlock)) != hipSuccess ||
-        hipMalloc(&c.d_imex_tiles, ntiles * sizeof(int4)) != hipSuccess ||
+        hipMalloc(&c.d_imex_tiles, ntiles * sizeof(TileDesc)) != hipSuccess ||
         hipMalloc(&c.d_imex_s, 3 * mat) != hipSuccess ||
         hipMalloc(&c.d_imex_m, 3 * mat) != hipSuccess ||
         hipMalloc(&c.d_imex_sp, packed) != hipSuccess ||
         hipMalloc(&c.d_imex_mp, packed) != hipSuccess ||
-        hipMalloc(&c.d_imex_kcol, (size_t)nc * W * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc(&c.d_imex_kval, (size_t)nc * W * sizeof(double)) != hipSuccess) {
+        hipMalloc(&c.d_imex_kptr, (nc + 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&kcnt, nc * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&ecol, (size_t)nc * W * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&eval, (size_t)nc * W * sizeof(double)) != hipSuccess) {
       set_error("IMEX: allocation of the implicit matrices (%lld DOFs, largest block %lld) "
                 "failed", (long long)nc, (long long)nmax);
       return fail2(FCW_E_NOMEM);
     }
-    c.imex_kw = W;
     if (hipMemcpyAsync(d_cdofs, h_cdofs.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice,
                        c.stream) != hipSuccess ||
         hipMemcpyAsync(c.d_imex_cpos, h_cpos.data(), nc * sizeof(int32_t),
@@ -896,19 +987,36 @@ fcw_status imex_prepare(Ctx& c, double dt) {
       const size_t off = (size_t)toff[q] * kTile * kTile;
       pack_inverse_tiles_kernel<<<blocks_for(np), 256, 0, c.stream>>>(
           c.d_imex_s + 2 * (size_t)n * n, n, T, c.d_imex_sp + off,
-          (int4*)c.d_imex_tiles + toff[q], q);
+          (TileDesc*)c.d_imex_tiles + toff[q], blk[q].moff, blk[q].poff);
       pack_inverse_tiles_kernel<<<blocks_for(np), 256, 0, c.stream>>>(
-          c.d_imex_m + 2 * (size_t)n * n, n, T, c.d_imex_mp + off, nullptr, q);
+          c.d_imex_m + 2 * (size_t)n * n, n, T, c.d_imex_mp + off, nullptr, 0, 0);
       {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail2(hip_fail(e, "IMEX packing"));
       }
     }
-    // the implicit rows of K (rows in implicit order)
+    // the implicit rows of K (rows in implicit order): padded, then compressed to their
+    // nonzero entries
     a.dofs = c.d_imex_dofs;
     a.nc = nc;
-    imex_kc_assemble_kernel<<<blocks_for(nc * W), 256, 0, c.stream>>>(
-        a, W, mark, pos, ncn, c.d_imex_kcol, c.d_imex_kval);
+    imex_kc_assemble_kernel<<<blocks_for(nc * W), 256, 0, c.stream>>>(a, W, mark, pos, ncn,
+                                                                      ecol, eval);
+    imex_kc_count_kernel<<<blocks_for(nc), 256, 0, c.stream>>>(eval, W, nc, kcnt);
+    {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return fail2(hip_fail(e, "IMEX stiffness rows"));
+    }
+    int32_t nnz = 0;
+    if ((st = exclusive_scan(c, kcnt, c.d_imex_kptr, nc, &nnz))) return fail2(st);
+    if (hipMemcpyAsync(c.d_imex_kptr + nc, &nnz, sizeof(int32_t), hipMemcpyHostToDevice,
+                       c.stream) != hipSuccess ||
+        hipMalloc(&c.d_imex_kcol, std::max<int64_t>(nnz, 1) * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c.d_imex_kval, std::max<int64_t>(nnz, 1) * sizeof(double)) != hipSuccess) {
+      set_error("IMEX: allocation of the implicit rows of K (%d entries) failed", nnz);
+      return fail2(FCW_E_NOMEM);
+    }
+    imex_kc_compact_kernel<<<blocks_for(nc), 256, 0, c.stream>>>(
+        ecol, eval, W, nc, c.d_imex_kptr, c.d_imex_kcol, c.d_imex_kval);
     {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return fail2(hip_fail(e, "IMEX stiffness rows"));
@@ -919,6 +1027,9 @@ fcw_status imex_prepare(Ctx& c, double dt) {
     }
     // the dense blocks, their factors and inverses are not used by the steps
     (void)hipFree(d_cdofs);
+    (void)hipFree(ecol);
+    (void)hipFree(eval);
+    (void)hipFree(kcnt);
     (void)hipFree(c.d_imex_s);
     (void)hipFree(c.d_imex_m);
     c.d_imex_s = c.d_imex_m = nullptr;
@@ -953,7 +1064,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
   double* dold = uold + nvp;
   double* upred = dold + nvp;
   double* part = upred + nvp;
-  const unsigned gw = (unsigned)((nc + 3) / 4);  // one wave per implicit row
+  const unsigned gw = (unsigned)((nc + 15) / 16);  // 16 lanes per implicit row
   const unsigned gb = blocks_for(nv);
   ImexUpd e{};
   e.u = u;
@@ -968,7 +1079,7 @@ fcw_status imex_run(Ctx& c, int nrhs, double* u, double* d, double* v_c, double*
   e.dt = dt;
   auto kc_rhs = [&](const double* uimp, double t) {
     imex_kc_rhs_kernel<<<gw, 256, 0, c.stream>>>(
-        c.d_imex_kcol, c.d_imex_kval, c.imex_kw, u, uimp, c.d_imex_dofs, c.d_src, nc, ndof,
+        c.d_imex_kptr, c.d_imex_kcol, c.d_imex_kval, u, uimp, c.d_imex_dofs, c.d_src, nc, ndof,
         c.nnodes, nrhs, c.dim, c.p, c.npts[0], c.npts[1], t, c.d_imex_cpos, bv);
   };
   fcw_status st;
