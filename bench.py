@@ -285,9 +285,10 @@ def bench_c3(steps, warmup, with_fp64):
     return out
 
 
-def _imex_leg(cfg, steps, warmup):
+def _imex_leg(cfg, steps, warmup, batch_rhs=0):
     """IMEX, explicit and consistent-mass steps of one FP64 problem, each timed over
-    ``steps`` steps after ``warmup``."""
+    ``steps`` steps after ``warmup``; with ``batch_rhs`` also IMEX steps with that many
+    right-hand sides."""
     import torch
     from paper_2501_19013_amd import fcw
     from paper_2501_19013_amd.solver import Solver
@@ -332,6 +333,33 @@ def _imex_leg(cfg, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_con = e0.elapsed_time(e1)
+    batch = {}
+    if batch_rhs > 0:
+        # batch_rhs source positions as right-hand sides of one run (the first points of a
+        # 9 x 9 grid over the interior that lie in the material): each tile of S^-1 is read
+        # once per step for all of them
+        cen = np.asarray(cfg["void_center"], dtype=float).reshape(-1, 2)
+        rad = np.asarray(cfg["void_radius"], dtype=float)
+        srcs = []
+        for iy in range(9):
+            for ix in range(9):
+                x = np.array([0.1 + 0.1 * ix, 0.1 + 0.1 * iy])
+                if len(rad) == 0 or np.all(np.linalg.norm(cen - x, axis=1) > rad + 0.01):
+                    srcs.append(dict(x=(float(x[0]), float(x[1])), f0=10.0, amp=1.0))
+        srcs = srcs[:batch_rhs]
+        batch_rhs = len(srcs)
+        ub, db = s.zeros(batch_rhs), s.zeros(batch_rhs)
+        vb = torch.zeros(batch_rhs, max(nc, 1), dtype=torch.float64, device="cuda:0")
+        ab = torch.zeros_like(vb)
+        fcw.step_imex(s.ctx, batch_rhs, ub, db, vb, ab, srcs, 0.0, dt, warmup, 1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fcw.step_imex(s.ctx, batch_rhs, ub, db, vb, ab, srcs, warmup * dt, dt, steps, 0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        msb = e0.elapsed_time(e1)
+        batch = dict(batch_rhs=batch_rhs, batch_ms_per_step=msb / steps,
+                     batch_value=batch_rhs * active * steps / (msb * 1e-3))
     s.close()
     return dict(value=active * steps / (ms * 1e-3), unit="DOF-updates/s", ms_per_step=ms / steps,
                 steps=steps, n_implicit=nc, n_blocks=lay["n_blocks"],
@@ -339,7 +367,7 @@ def _imex_leg(cfg, steps, warmup):
                 explicit_ms_per_step=ms_exp / steps,
                 consistent_mass_cdm_ms_per_step=ms_con / steps,
                 # the packed upper tiles of the blocks of S^-1, read once per step
-                solve_bytes_per_step=lay["solve_bytes"])
+                solve_bytes_per_step=lay["solve_bytes"], **batch)
 
 
 def bench_imex(steps, warmup, full_steps):
@@ -355,7 +383,7 @@ def bench_imex(steps, warmup, full_steps):
                        "(Alg. imex, beta=1/4, gamma=1/2), S and M^cc block diagonal: dense "
                        "FP64 Cholesky per block, S^-1 as packed upper tiles")
     if full_steps > 0:
-        full = _imex_leg(workloads.config("c2"), full_steps, warmup)
+        full = _imex_leg(workloads.config("c2"), full_steps, warmup, batch_rhs=16)
         full["workload"] = "the same scheme on the c2 void field at full size, 512x512 cells, p=4"
         res["c2_full"] = full
     return res
@@ -541,7 +569,8 @@ def main():
             print(f"[bench] imex c2 full size: {f['ms_per_step']:.3f} ms/step, "
                   f"{f['n_implicit']} implicit DOFs in {f['n_blocks']} blocks (largest "
                   f"{f['largest_block']}), set-up {f['prepare_s']:.1f} s, explicit "
-                  f"{f['explicit_ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+                  f"{f['explicit_ms_per_step']:.3f} ms/step, {f['batch_rhs']} right-hand sides "
+                  f"{f['batch_ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if args.iga_steps > 0:
         res["iga"] = bench_iga(args.iga_steps, 10)
         print(f"[bench] iga: {res['iga']['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,
