@@ -529,6 +529,102 @@ __global__ __launch_bounds__(256) void symp_tile_kernel(const double* P, const T
 // tiles per wave of symp_tile_kernel
 constexpr int kTilesPerWave = 1;
 
+typedef double symp_f64x4 __attribute__((ext_vector_type(4)));
+
+// The same tile products for several right-hand sides on the FP64 matrix cores, 16
+// right-hand sides per pass: the wave's tile goes to LDS (rows padded to 33 doubles), then
+// Y = A B_J (32 x 16, B_J the right-hand sides' block J) and, for I < J, Z = A^T B_I, each
+// as two 16-row halves of eight k-steps of v_mfma_f64_16x16x4f64.  Operands: lane
+// l16 + 16 k4 holds A[l16][k4] and B[k4][l16]; the result lane holds rows 4 v + k4
+// (v < 4) of column l16.
+__global__ __launch_bounds__(256) void symp_tile_mfma_kernel(const double* P,
+                                                             const TileDesc* tiles,
+                                                             int64_t ntiles, const double* b,
+                                                             int64_t nc, int nrhs,
+                                                             double* part) {
+  constexpr int LD = kTile + 1;
+  __shared__ double lds[4][kTile * LD];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+  if (q >= ntiles) return;
+  const TileDesc td = tiles[q];
+  double* A = lds[wave];
+  {
+    const int cp = lane & 15, rs = lane >> 4;
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v* tile = (const d2v*)(P + q * kTile * kTile);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const d2v x = __builtin_nontemporal_load(tile + (rs + 4 * k) * (kTile / 2) + cp);
+      A[(rs + 4 * k) * LD + 2 * cp] = x.x;
+      A[(rs + 4 * k) * LD + 2 * cp + 1] = x.y;
+    }
+  }
+  // LDS accesses of one wave complete in order; the barrier keeps the compiler's order
+  __builtin_amdgcn_wave_barrier();
+  const int l16 = lane & 15, k4 = lane >> 4;
+  const int64_t I = td.I, J = td.J, n = td.n;
+  const int64_t stride = (int64_t)td.T * kTile;
+  double* pb = part + nrhs * td.poff;
+  const bool off_diag = I < J;
+  for (int r0 = 0; r0 < nrhs; r0 += 16) {
+    const int rr = r0 + l16;
+    const bool rv = rr < nrhs;
+    const double* br = b + (int64_t)(rv ? rr : 0) * nc + td.moff;
+    symp_f64x4 y0 = {0.0, 0.0, 0.0, 0.0}, y1 = y0, z0 = y0, z1 = y0;
+#pragma unroll
+    for (int ks = 0; ks < kTile / 4; ++ks) {
+      const int k = 4 * ks + k4;
+      const int64_t jk = J * kTile + k, ik = I * kTile + k;
+      const double bJ = (rv && jk < n) ? br[jk] : 0.0;
+      y0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[l16 * LD + k], bJ, y0, 0, 0, 0);
+      y1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(16 + l16) * LD + k], bJ, y1, 0, 0, 0);
+      if (off_diag) {
+        const double bI = (rv && ik < n) ? br[ik] : 0.0;
+        z0 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k * LD + l16], bI, z0, 0, 0, 0);
+        z1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k * LD + 16 + l16], bI, z1, 0, 0, 0);
+      }
+    }
+    if (r0 + 16 >= nrhs) {
+      // last pass: the tile is no longer needed, so its LDS takes the results (Y in rows
+      // 0..15, Z in rows 16..31, one row of 32 positions per right-hand side), written out
+      // as whole 256-byte rows
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + k4;
+        A[l16 * LD + i] = y0[v];
+        A[l16 * LD + 16 + i] = y1[v];
+        A[(16 + l16) * LD + i] = z0[v];
+        A[(16 + l16) * LD + 16 + i] = z1[v];
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int rl = t * 2 + (lane >> 5), pos = lane & 31;
+        if (r0 + rl < nrhs) {
+          pb[(J * nrhs + r0 + rl) * stride + I * kTile + pos] = A[rl * LD + pos];
+          if (off_diag) pb[(I * nrhs + r0 + rl) * stride + J * kTile + pos] = A[(16 + rl) * LD + pos];
+        }
+      }
+    } else {
+      double* py = pb + (J * nrhs + rr) * stride + I * kTile;
+      double* pz = pb + (I * nrhs + rr) * stride + J * kTile;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + k4;
+        py[i] = y0[v];
+        py[16 + i] = y1[v];
+        if (off_diag) {
+          pz[i] = z0[v];
+          pz[16 + i] = z1[v];
+        }
+      }
+    }
+  }
+}
+
 // the updates that consume x = A b on the implicit DOFs ([nrhs][nc] vectors)
 struct ImexUpd {
   double* u;             // [nrhs][ndof]
@@ -717,6 +813,11 @@ __global__ __launch_bounds__(256) void imex_kc_rhs_kernel(
 // part = the tile products of x = A b (A the packed upper tiles of the blocks of the
 // inverse of S or M^cc; b in block order)
 static void symp_tiles(Ctx& c, const double* A, const double* b, int nrhs, double* part) {
+  if (nrhs >= 2) {  // several right-hand sides: the matrix cores
+    symp_tile_mfma_kernel<<<(unsigned)((c.imex_ntiles + 3) / 4), 256, 0, c.stream>>>(
+        A, (const TileDesc*)c.d_imex_tiles, c.imex_ntiles, b, c.imex_nc, nrhs, part);
+    return;
+  }
   constexpr int per_block = 4 * kTilesPerWave;
   symp_tile_kernel<kTilesPerWave>
       <<<(unsigned)((c.imex_ntiles + per_block - 1) / per_block), 256, 0, c.stream>>>(
