@@ -23,11 +23,13 @@ TOL = 1e-10       # alpha = 1e-4
 TOL_ILL = 1e-5    # alpha = 1e-12
 
 
-def _run(cfg, dt, chunks, sources):
+def _run(cfg, dt, chunks, sources, autotune=False):
     import torch
     from paper_2501_19013_amd import fcw
     from paper_2501_19013_amd.solver import Solver
     s = Solver(cfg, precision="fp64")
+    if autotune:
+        s.autotune(nrhs=len(sources), nsteps=10)
     nc = fcw.imex_prepare(s.ctx, dt)
     dofs = fcw.export(s.ctx, fcw.ARR_IMEX_DOFS)
     nrhs = len(sources)
@@ -45,12 +47,13 @@ def _run(cfg, dt, chunks, sources):
     return out
 
 
-def _check(cfg, steps, chunks, sources, dt=None, tol=TOL, disc=None, sparse=False):
+def _check(cfg, steps, chunks, sources, dt=None, tol=TOL, disc=None, sparse=False,
+           autotune=False):
     if disc is None:
         disc = problem.build(problem.Problem.from_config(cfg))
     if dt is None:
         dt = 0.9 * timestep.critical_dt(disc)
-    got = _run(cfg, dt, chunks, sources)
+    got = _run(cfg, dt, chunks, sources, autotune=autotune)
     c, _ = ox.partition(disc)
     assert got["nc"] == len(c)
     assert np.array_equal(got["dofs"], c)
@@ -135,6 +138,23 @@ def test_imex_implicit_set_above_the_dense_block_limit():
     assert 1 < lay["n_blocks"] and lay["largest"] <= limit
     # each block's packed upper tiles: far less than one dense inverse of the whole set
     assert lay["solve_bytes"] < 0.25 * 8 * len(c) ** 2
+
+
+def test_imex_with_the_autotuned_explicit_kernel():
+    """The explicit part runs whichever step kernel the context has selected (here the one
+    the autotuner picks on the void field at 64 x 64 cells, p = 3); one and two right-hand
+    sides."""
+    cc, rr = workloads.random_circles(seed=2)
+    cfg = workloads._base(2, (64, 64), 3, cc, rr, alpha=1e-4)
+    disc = problem.build(problem.Problem.from_config(cfg))
+    c, d = ox.partition(disc)
+    K = problem.assembled_K(disc).tocsr()
+    im = disc.inv_mass_dof()
+    g = np.asarray(abs(K[d][:, d]).sum(axis=1)).ravel() * im[d]
+    dt = 0.8 * 2.0 / np.sqrt(g.max())
+    srcs = [dict(x=(0.1, 0.1), f0=20.0, amp=1.0), dict(x=(0.7, 0.45), f0=25.0, amp=0.5)]
+    for batch in (srcs[:1], srcs):
+        _check(cfg, 60, [20, 40], batch, dt=dt, disc=disc, sparse=True, autotune=True)
 
 
 def test_imex_without_cut_cells_is_the_explicit_step():
