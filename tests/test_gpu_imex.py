@@ -112,6 +112,18 @@ def test_imex_3d_elastic_parity():
     _check(cfg, 40, [40], cfg["sources"])
 
 
+def test_imex_3d_elastic_two_blocks():
+    """Two pores far enough apart that no active cell holds implicit nodes of both: two
+    blocks of coupled DOFs, each with the three components of its nodes (the block order
+    permutes the component-major implicit DOFs)."""
+    cfg = workloads._base(3, (8, 4, 4), 2, [(0.4, 0.5, 0.5), (1.6, 0.5, 0.5)], [0.2, 0.2],
+                          ncomp=3, nsteps=40, hi=(2.0, 1.0, 1.0), alpha=1e-4)
+    cfg["sources"] = [dict(x=(1.0, 0.3, 0.3), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0),
+                      dict(x=(1.1, 0.6, 0.7), dir=(0.0, 0.0, 1.0), f0=12.0, amp=0.5)]
+    got = _check(cfg, 40, [15, 25], cfg["sources"])
+    assert got["layout"]["n_blocks"] == 2
+
+
 def test_imex_implicit_set_above_the_dense_block_limit():
     """A 2-D p = 4 field of 50 voids on 96 x 96 cells: 19 815 implicit DOFs, more than one
     dense block may hold (FCW_IMEX_MAX_NC).  The device splits them into blocks of coupled
