@@ -285,6 +285,54 @@ def bench_c3(steps, warmup, with_fp64):
     return out
 
 
+def bench_c4(steps, warmup):
+    """The 3-D elastic workload at 64^3 cells, p = 3 (n_loc = 192), with its 16 source
+    positions as right-hand sides of one explicit FP32 run (the explicit part of the IMEX
+    configuration; its implicit set is one block of millions of DOFs, beyond the dense
+    block limit)."""
+    import torch
+    import workloads
+    from paper_2501_19013_amd import fcw
+    from paper_2501_19013_amd.solver import Solver
+    cfg = workloads.config("c4")
+    # a source position inside a pore moves up in z until it is in the material
+    cen = np.asarray(cfg["void_center"], dtype=float).reshape(-1, 3)
+    rad = np.asarray(cfg["void_radius"], dtype=float)
+    src = []
+    for sd in cfg["sources"]:
+        x = np.array(sd["x"], dtype=float)
+        while np.any(np.linalg.norm(cen - x, axis=1) <= rad + 0.01):
+            x[2] += 0.01
+        src.append(dict(sd, x=tuple(float(v) for v in x)))
+    t0 = time.perf_counter()
+    s = Solver(cfg, precision="fp32", device="cuda:0")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = s.info
+    print(f"[bench] c4 set-up {t_setup:.1f} s, {info['n_cut']} cut cells", file=sys.stderr,
+          flush=True)
+    s.autotune(nrhs=len(src), nsteps=3)
+    dt = 0.9 * s.critical_dt(max_iter=4000, rtol=1e-7)
+    u, d = s.zeros(len(src)), s.zeros(len(src))
+    s.step(u, d, src, dt, warmup, t0=0.0, start=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(u, d, src, dt, steps, t0=warmup * dt, start=False)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    active = int((s.export(fcw.ARR_MASS) > 0).sum())
+    ok = bool(torch.isfinite(u).all())
+    s.close()
+    return dict(workload="c4: 3-D elastic, the c3 pore field at 64^3 cells, p=3 GLL (192 DOFs "
+                         "per cell), 16 source positions as right-hand sides, FP32 explicit "
+                         "step, FP64 setup", value=len(src) * active * steps / (ms * 1e-3),
+                unit="DOF-updates/s", ms_per_step=ms / steps, nrhs=len(src), steps=steps,
+                ndof=info["ndof"], active_dof=active, n_cut=info["n_cut"], setup_s=t_setup,
+                dt=dt, finite=ok)
+
+
 def _imex_leg(cfg, steps, warmup, batch_rhs=0):
     """IMEX, explicit and consistent-mass steps of one FP64 problem, each timed over
     ``steps`` steps after ``warmup``; with ``batch_rhs`` also IMEX steps with that many
@@ -502,6 +550,8 @@ def main():
                     help="steps of the IMEX leg at the full c2 size (0 skips it)")
     ap.add_argument("--iga-steps", type=int, default=500, help="steps of the IGA-FCM leg (0: skip)")
     ap.add_argument("--c3-steps", type=int, default=1000)
+    ap.add_argument("--c4-steps", type=int, default=0,
+                    help="steps of the 3-D elastic p=3 leg with 16 right-hand sides (0: skip)")
     ap.add_argument("--c3-warmup", type=int, default=10)
     ap.add_argument("--serve-count", type=int, default=64, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-scale", type=float, default=0.5, help="cell counts per side x this")
@@ -560,6 +610,10 @@ def main():
               f"fp64 {par['fp64']:.2e}", file=sys.stderr, flush=True)
     if not args.no_c3:
         res["c3"] = bench_c3(args.c3_steps, args.c3_warmup, not args.no_fp64)
+    if args.c4_steps > 0:
+        res["c4"] = bench_c4(args.c4_steps, 2)
+        print(f"[bench] c4: {res['c4']['ms_per_step']:.2f} ms/step for 16 right-hand sides",
+              file=sys.stderr, flush=True)
     if args.imex_steps > 0:
         res["imex"] = bench_imex(args.imex_steps, 5, args.imex_full_steps)
         print(f"[bench] imex: {res['imex']['ms_per_step']:.3f} ms/step, "

@@ -316,7 +316,7 @@ static CutLaunch cut_kind(const Ctx& c, int* cpb) {
   FCW_CUT(2, 1, 1) FCW_CUT(2, 2, 1) FCW_CUT(2, 3, 1) FCW_CUT(2, 4, 1) FCW_CUT(2, 5, 1)
   FCW_CUT(2, 6, 1)
   FCW_CUT(3, 1, 1) FCW_CUT(3, 2, 1) FCW_CUT(3, 3, 1) FCW_CUT(3, 4, 1)
-  FCW_CUT(3, 1, 3) FCW_CUT(3, 2, 3)
+  FCW_CUT(3, 1, 3) FCW_CUT(3, 2, 3) FCW_CUT(3, 3, 3)
 #undef FCW_CUT
   return nullptr;
 }

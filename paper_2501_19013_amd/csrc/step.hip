@@ -798,6 +798,7 @@ static int candidates(const Ctx& c, Cand* out) {
     FCW_C0(3, 4, 1, 4, 4, 2) FCW_C(3, 4, 1, 4, 2, 2)
     FCW_C0(3, 1, 3, 8, 4, 4)
     FCW_C0(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
+    FCW_C0(3, 3, 3, 4, 2, 2)
   } else {
     FCW_C0(2, 1, 1, 32, 32, 1) FCW_C(2, 1, 1, 32, 16, 1)
     FCW_C0(2, 2, 1, 16, 16, 1) FCW_C(2, 2, 1, 16, 8, 1) FCW_C(2, 2, 1, 32, 16, 1)
@@ -813,6 +814,7 @@ static int candidates(const Ctx& c, Cand* out) {
     FCW_C0(3, 1, 3, 8, 4, 4)
     FCW_C0(3, 2, 3, 4, 4, 4) FCW_C(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
     FCW_CW(3, 2, 3, 4, 4, 4, 8) FCW_CW(3, 2, 3, 8, 4, 4, 8)
+    FCW_C0(3, 3, 3, 4, 2, 2) FCW_C(3, 3, 3, 4, 4, 2)
     FCW_CZ(2, 3, 8, 8, 16, 6) FCW_CZ(2, 3, 8, 8, 32, 6)
     FCW_CZ(2, 3, 8, 4, 16, 6) FCW_CZ(2, 3, 8, 4, 32, 6)
   }

@@ -360,6 +360,40 @@ def test_elastic_3d_every_tile_configuration(precision, tol):
     s.close()
 
 
+def _elastic_p3():
+    # 3-D elastic p = 3 (n_loc = 192) on a ragged 5x4x3 grid with one ball: two tiles per
+    # axis of the 4x2x2 and 4x4x2 tile shapes, cut cells
+    cfg = workloads._base(3, (5, 4, 3), 3, [(0.3, 0.22, 0.16)], [0.12], ncomp=3, nsteps=40,
+                          hi=(0.5, 0.4, 0.3), tree_depth=2)
+    cfg["sources"] = [dict(x=(0.05, 0.05, 0.05), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0)]
+    return cfg
+
+
+def test_elastic_3d_p3_setup_parity():
+    cfg = _elastic_p3()
+    disc = _oracle(cfg)
+    assert disc.prob.n_loc == 192 and len(disc.cut_cells) > 0
+    s = _solver(cfg, "fp64")
+    _setup_parity(cfg, disc, s)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_elastic_3d_p3_every_tile_configuration(precision, tol):
+    cfg = _elastic_p3()
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    ref = timestep.cdm(disc, dt, 40, sources=cfg["sources"])["u"]
+    s = _solver(cfg, precision)
+    confs = s.tile_configs()
+    assert len(confs) >= 1
+    for i, conf in enumerate(confs):
+        s.select_tile(i)
+        got = _run_gpu(s, cfg, dt, 40, [15, 25])
+        assert rel_l2(got[40], ref) <= tol, (i, conf)
+    s.close()
+
+
 @pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_scalar_3d_every_tile_configuration(p, precision, tol):
