@@ -53,8 +53,13 @@ struct CutShape {
   static constexpr int CPW = PIPE ? 8 : 1;                        // cells per wave
   static constexpr int WPB_ = 64 * 1024 / (STRIDE * 4);
   static constexpr int WPB = PIPE ? 1 : (WPB_ < 1 ? 1 : (WPB_ > 4 ? 4 : WPB_));  // waves per block
-  static constexpr int CPB = WPB * CPW;  // cells per block
-  static constexpr int LDS = WPB * STRIDE * 4;
+  // Cooperative form, for matrices of three or more row groups of which only one fits per
+  // wave's LDS share: the four waves of a block share one cell's matrix, wave g forming
+  // the rows of group g.
+  static constexpr bool COOP = !PIPE && (NL + 63) / 64 >= 3 && WPB_ < 2;
+  static constexpr int CPB = COOP ? 1 : WPB * CPW;  // cells per block
+  static constexpr int THREADS = COOP ? 256 : 64 * WPB;
+  static constexpr int LDS = (COOP ? 1 : WPB) * STRIDE * 4;
 };
 
 __device__ static inline void lds_dword(const void* gsrc, void* lds_wave_base) {
@@ -145,11 +150,11 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
   }
   const CutProb<T>& pr = SINGLE ? one : probs[k];
   if (j >= pr.nsteps) return;
-  const int64_t q0 = ((blk - pr.blk0) * S::WPB + wave) * S::CPW;
+  const int64_t q0 = S::COOP ? blk - pr.blk0 : ((blk - pr.blk0) * S::WPB + wave) * S::CPW;
   if (q0 < 0 || q0 >= pr.ncand) return;
   const int ncell = (int)min((int64_t)S::CPW, pr.ncand - q0);
 
-  unsigned int* kw = lds_u32 + wave * S::STRIDE;
+  unsigned int* kw = lds_u32 + (S::COOP ? 0 : wave) * S::STRIDE;
   const T* K = (const T*)kw;
   T* ue = (T*)(kw + S::KDP);
   const T* uin = ((pr.nsteps - 1 - j) & 1) ? pr.ua : pr.ub;
@@ -239,6 +244,39 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
       for (int rr = 0; rr < NR; ++rr)
         if (lane + 64 * rr < NL) yo[lane + 64 * rr] = (T)yprev[rr];
     }
+  } else if constexpr (S::COOP) {
+    // one cell per block: the four waves bring its packed triangle global -> LDS by DMA,
+    // wave 0 stages each right-hand side's node values, wave g < NR forms rows
+    // lane + 64 g (columns in order, FP64 accumulation, as cell_rows)
+    const int64_t q = q0;
+    if (!__shfl(my_on, 0)) return;  // uniform over the block: one cell
+    const int cell = __shfl(my_cell, 0);
+    for (int w = wave; w < S::KDP / 64; w += 4)
+      lds_dword(kall + min(q * S::KD + w * 64 + lane, total - 1), kw + w * 64);
+    int64_t nodes[NR];
+    cell_dofs<DIM, P, NCOMP, NR>(pr, cell, lane, nodes);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const int row = lane + 64 * wave;
+    const int tr = row * (row + 1) / 2;
+    for (int r = 0; r < pr.nrhs; ++r) {
+      const T* u = uin + (int64_t)r * pr.ndof;
+      if (wave == 0) {
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+          if (lane + 64 * rr < NL) ue[lane + 64 * rr] = u[nodes[rr]];
+      }
+      __syncthreads();
+      if (wave < NR && row < NL) {
+        double y = 0.0;
+#pragma unroll 8
+        for (int jj = 0; jj < NL; ++jj)
+          y += (double)K[(row <= jj) ? jj * (jj + 1) / 2 + row : tr + jj] * (double)ue[jj];
+        pr.y[((int64_t)r * pr.ncand + q) * NL + row] = (T)y;
+      }
+      // every wave has read ue before the next right-hand side overwrites it
+      __syncthreads();
+    }
   } else {
     // one cell per wave: packed triangle global -> LDS by DMA (64 coalesced dwords per
     // instruction, no registers), node values of rhs 0 in flight alongside
@@ -288,13 +326,13 @@ struct CutKind {
       static const hipError_t attr = hipFuncSetAttribute(
           (const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
       FCW_HIP(attr);
-      kern<<<(unsigned)(8 * chunk), 64 * S::WPB, S::LDS, s>>>(nullptr, 1, rec, chunk, j);
+      kern<<<(unsigned)(8 * chunk), S::THREADS, S::LDS, s>>>(nullptr, 1, rec, chunk, j);
     } else {
       auto kern = cut_apply_kernel<T, DIM, P, NCOMP, false>;
       static const hipError_t attr = hipFuncSetAttribute(
           (const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, S::LDS);
       FCW_HIP(attr);
-      kern<<<(unsigned)(8 * chunk), 64 * S::WPB, S::LDS, s>>>((const CutProb<T>*)probs, nprob,
+      kern<<<(unsigned)(8 * chunk), S::THREADS, S::LDS, s>>>((const CutProb<T>*)probs, nprob,
                                                               CutProb<T>{}, chunk, j);
     }
     FCW_HIP(hipGetLastError());
