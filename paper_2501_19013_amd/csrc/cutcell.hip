@@ -257,6 +257,54 @@ __global__ __launch_bounds__(256) void cut_apply_kernel(const CutProb<T>* __rest
     cell_dofs<DIM, P, NCOMP, NR>(pr, cell, lane, nodes);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
+    if (pr.nrhs >= 2 && NL % 16 == 0) {
+      // several right-hand sides: Y = K U on the matrix cores, 16 right-hand sides per
+      // pass, wave w taking the row blocks w, w + 4, ... of 16 rows; A from the packed
+      // triangle in LDS, B gathered from the node values of the pass's right-hand sides
+      // (lane l16 + 16 k4 holds A[l16][k4] and B[k4][l16]; Mma<T>::row gives the result rows)
+      constexpr int NMB = NL / 16, MPW = (NMB + 3) / 4;
+      const int l16 = lane & 15, k4 = lane >> 4;
+      const int cx = cell % pr.n[0], cy = (cell / pr.n[0]) % pr.n[1],
+                cz = (DIM == 3) ? cell / (pr.n[0] * pr.n[1]) : 0;
+      for (int r0 = 0; r0 < pr.nrhs; r0 += 16) {
+        const int rr = r0 + l16;
+        const bool rv = rr < pr.nrhs;
+        const T* u = uin + (int64_t)(rv ? rr : 0) * pr.ndof;
+        typename Mma<T>::acc acc[MPW];
+#pragma unroll
+        for (int m = 0; m < MPW; ++m)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[m][v] = 0;
+        for (int ks = 0; ks < NL / 4; ++ks) {
+          const int k = 4 * ks + k4;
+          const int comp = k / NS, loc = k % NS;
+          const int i0 = loc % NP1, i1 = (loc / NP1) % NP1, i2 = loc / (NP1 * NP1);
+          const int64_t dof = (int64_t)comp * pr.nnodes + (cx * P + i0) +
+                              (int64_t)pr.np[0] * ((cy * P + i1) + (int64_t)pr.np[1] * (cz * P + i2));
+          const T bk = rv ? u[dof] : (T)0;
+          const int tk = k * (k + 1) / 2;
+#pragma unroll
+          for (int m = 0; m < MPW; ++m) {
+            const int mb = wave + 4 * m;
+            if (mb < NMB) {
+              const int i = mb * 16 + l16;
+              acc[m] = Mma<T>::mma(K[(i <= k) ? tk + i : i * (i + 1) / 2 + k], bk, acc[m]);
+            }
+          }
+        }
+        if (rv) {
+          T* yo = pr.y + ((int64_t)rr * pr.ncand + q) * NL;
+#pragma unroll
+          for (int m = 0; m < MPW; ++m) {
+            const int mb = wave + 4 * m;
+            if (mb < NMB)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) yo[mb * 16 + Mma<T>::row(k4, v)] = (T)acc[m][v];
+          }
+        }
+      }
+      return;
+    }
     const int row = lane + 64 * wave;
     const int tr = row * (row + 1) / 2;
     for (int r = 0; r < pr.nrhs; ++r) {

@@ -394,6 +394,31 @@ def test_elastic_3d_p3_every_tile_configuration(precision, tol):
     s.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_elastic_3d_p3_multi_rhs(precision, tol):
+    # three right-hand sides in one call (the cut products of 192-row cells on the matrix
+    # cores), each against its own oracle run, every tile configuration
+    import torch
+    cfg = _elastic_p3()
+    srcs = [cfg["sources"][0],
+            dict(x=(0.45, 0.05, 0.25), dir=(0.0, 0.6, 0.8), f0=14.0, amp=-0.7),
+            dict(x=(0.1, 0.35, 0.2), dir=(0.0, 0.0, 1.0), f0=8.0, amp=0.4)]
+    disc = _oracle(cfg)
+    dt = 0.9 * timestep.critical_dt(disc)
+    refs = [timestep.cdm(disc, dt, 40, sources=[q])["u"] for q in srcs]
+    s = _solver(cfg, precision)
+    for i, conf in enumerate(s.tile_configs()):
+        s.select_tile(i)
+        u, d = s.zeros(len(srcs)), s.zeros(len(srcs))
+        s.step(u, d, srcs, dt, 15, start=True)
+        s.step(u, d, srcs, dt, 25, t0=15 * dt)
+        torch.cuda.synchronize()
+        got = u.double().cpu().numpy()
+        for q in range(len(srcs)):
+            assert rel_l2(got[q], refs[q]) <= tol, (i, conf, q)
+    s.close()
+
+
 @pytest.mark.parametrize("p", [2, 3])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-4)])
 def test_scalar_3d_every_tile_configuration(p, precision, tol):
