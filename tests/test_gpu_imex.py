@@ -112,6 +112,15 @@ def test_imex_3d_elastic_parity():
     _check(cfg, 40, [40], cfg["sources"])
 
 
+def test_imex_3d_elastic_p3_parity():
+    # 3-D elastic p = 3 (192 DOFs per cell, 1 029 stencil slots per implicit row of K)
+    cfg = workloads._base(3, (5, 4, 3), 3, [(0.3, 0.22, 0.16)], [0.12], ncomp=3, nsteps=30,
+                          hi=(0.5, 0.4, 0.3), tree_depth=2, alpha=1e-4)
+    cfg["sources"] = [dict(x=(0.05, 0.05, 0.05), dir=(1.0, 0.0, 0.0), f0=10.0, amp=1.0),
+                      dict(x=(0.45, 0.05, 0.25), dir=(0.0, 0.6, 0.8), f0=14.0, amp=-0.7)]
+    _check(cfg, 30, [12, 18], cfg["sources"])
+
+
 def test_imex_3d_elastic_two_blocks():
     """Two pores far enough apart that no active cell holds implicit nodes of both: two
     blocks of coupled DOFs, each with the three components of its nodes (the block order
