@@ -815,7 +815,8 @@ static int candidates(const Ctx& c, Cand* out) {
     FCW_C0(3, 2, 3, 4, 4, 4) FCW_C(3, 2, 3, 4, 4, 2) FCW_C(3, 2, 3, 4, 2, 2)
     FCW_CW(3, 2, 3, 4, 4, 4, 8) FCW_CW(3, 2, 3, 8, 4, 4, 8)
     FCW_C0(3, 3, 3, 4, 2, 2) FCW_C(3, 3, 3, 4, 4, 2)
-    FCW_CW(3, 3, 3, 4, 2, 2, 8) FCW_CW(3, 3, 3, 4, 4, 2, 8)
+    FCW_CW(3, 3, 3, 4, 2, 2, 8) FCW_CW(3, 3, 3, 4, 4, 2, 8) FCW_CW(3, 3, 3, 4, 4, 4, 8)
+    FCW_CW(3, 3, 3, 8, 4, 2, 8)
     FCW_CZ(2, 3, 8, 8, 16, 6) FCW_CZ(2, 3, 8, 8, 32, 6)
     FCW_CZ(2, 3, 8, 4, 16, 6) FCW_CZ(2, 3, 8, 4, 32, 6)
   }
